@@ -1,0 +1,310 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test is chosen so that a plausible slip in the oracle (a dropped term,
+a wrong sign or index, a transposed operand, a missing 1/N, an off-by-one
+window) fails at least one of them.  Nothing here uses the HIP library.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+# Textbook cold-plasma dispersion constant, written independently of the
+# oracle: arrival delay of frequency f (MHz) is K_DM*DM/f^2 microseconds.
+K_DM_US = 4.148808e9
+
+
+def arrival_law(dm, f_ref):
+    """Physical arrival time (us) of frequency f relative to f_ref."""
+    return lambda f: K_DM_US * dm * (1.0 / (f * f) - 1.0 / (f_ref * f_ref))
+
+
+def direct_idft(X):
+    """x[n] = (1/N) sum_j X[j] exp(+2 pi i j n / N), by explicit loops."""
+    n = len(X)
+    out = np.zeros(n, dtype=np.complex128)
+    for t in range(n):
+        acc = 0j
+        for j in range(n):
+            ang = 2.0 * math.pi * ((j * t) % n) / n
+            acc += X[j] * complex(math.cos(ang), math.sin(ang))
+        out[t] = acc / n
+    return out
+
+
+# --------------------------------------------------------------------------
+# Overlap-save machinery: brute-force time-domain evaluation
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("N,L,nfront,T", [(64, 16, 7, 203), (32, 8, 0, 70),
+                                          (64, 20, 20, 64), (16, 4, 3, 1)])
+def test_overlap_save_equals_brute_force_block_convolution(N, L, nfront, T):
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(T) + 1j * rng.standard_normal(T)
+    H = O.transfer(N, 301.0, 0.5, 3.0)
+    h = direct_idft(H)                       # circular impulse response
+    M = N - L
+    want = np.zeros(T, dtype=np.complex128)
+    for k in range(-(-T // M)):
+        for m in range(M):
+            t = k * M + m
+            if t >= T:
+                break
+            acc = 0j
+            for mp in range(N):
+                src = k * M - nfront + mp
+                if 0 <= src < T:
+                    acc += x[src] * h[(nfront + m - mp) % N]
+            want[t] = acc
+    got = O.overlap_save(x, H, L, nfront)
+    assert np.max(np.abs(got - want)) < 1e-12 * max(1.0, np.max(np.abs(want)))
+
+
+def test_direct_dft_matches_numpy_convention():
+    """The oracle's O(N^2) DFT and numpy agree on sign and scale."""
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(24) + 1j * rng.standard_normal(24)
+    assert np.allclose(O.dft_direct(x), np.fft.fft(x), atol=1e-11)
+    assert np.allclose(direct_idft(np.fft.fft(x)), x, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# |H| = 1 (all-pass), DM = 0, round trip
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("fc,df,dm,n", [(325.0, 0.0625, 67.9, 8192),
+                                        (610.0, 16.0, 10.0, 1 << 14),
+                                        (300.02, 0.048828125, -120.0, 4096)])
+def test_parseval_per_block(fc, df, dm, n):
+    rng = np.random.default_rng(3)
+    s = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    z = np.fft.ifft(np.fft.fft(s) * O.transfer(n, fc, df, dm))
+    e0, e1 = np.sum(np.abs(s) ** 2), np.sum(np.abs(z) ** 2)
+    assert abs(e1 - e0) / e0 < 1e-13
+    # and it is not the identity
+    assert np.max(np.abs(z - s)) > 0.1
+
+
+def test_dm_zero_is_identity_and_plain_incoherent_sum():
+    rng = np.random.default_rng(4)
+    T, C = 1000, 5
+    v = rng.integers(-127, 128, size=(T, C, 2)).astype(np.int8)
+    out = O.dedisperse(v, 325.0, 1.0, 0.0, n_int=3, fft_len=256, overlap=24,
+                       nfront=11, want_voltages=True)
+    x = v[..., 0].astype(float) + 1j * v[..., 1].astype(float)
+    assert np.max(np.abs(out["y"] - x.T)) < 1e-12
+    p = np.abs(x) ** 2
+    P = np.array([[p[3 * u:3 * u + 3, c].sum() for u in range(T // 3)] for c in range(C)])
+    assert np.allclose(out["P"], P, rtol=0, atol=1e-9)
+    assert np.all(out["d"] == 0)
+    assert np.allclose(out["I"], P.sum(0)) and np.all(out["cov"] == C)
+
+
+def test_round_trip_block_level():
+    rng = np.random.default_rng(5)
+    n = 4096
+    s = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    disp = np.fft.ifft(np.fft.fft(s) * O.transfer(n, 330.0, 0.25, 40.0, sign=+1))
+    back = np.fft.ifft(np.fft.fft(disp) * O.transfer(n, 330.0, 0.25, 40.0, sign=-1))
+    assert np.max(np.abs(back - s)) < 1e-12
+    # dedispersing at -DM is dispersing at +DM
+    a = O.transfer(n, 330.0, 0.25, -40.0, sign=-1)
+    b = O.transfer(n, 330.0, 0.25, 40.0, sign=+1)
+    assert np.max(np.abs(a - b)) < 1e-9
+
+
+# --------------------------------------------------------------------------
+# Physics: a dispersed pulse collapses to its emission time
+# --------------------------------------------------------------------------
+def _smooth(p, w):
+    k = np.ones(w) / w
+    return np.convolve(p, k, mode="same")
+
+
+def test_single_channel_pulse_collapses_to_emission_time():
+    """Pulse synthesised from wave packets at their physical arrival times
+    (centre-referenced) is brought back to t0 by the dedispersing filter,
+    and smeared to twice the sweep by the opposite sign."""
+    rate, fcen, dm = 4.0, 300.0, 5.0
+    nsamp = 1 << 17
+    t0_us = 12000.0
+    rng = np.random.default_rng(6)
+    x = synth.single_pulse_cf32(rng, nsamp, rate, fcen, t0_us,
+                                arrival_law(dm, fcen), fwhm_us=40.0, amp=40.0,
+                                nsub=128, noise_sigma=0.0)
+    # the dispersed signal is spread over the sweep
+    sweep = K_DM_US * dm * ((fcen - rate / 2) ** -2 - (fcen + rate / 2) ** -2) * rate
+    assert sweep > 20000
+    N, L, nfront = O.overlap_plan(fcen, rate, 1, [dm], n_int=1)
+    y = O.overlap_save(x, O.transfer(N, fcen, rate, dm), L, nfront)
+    p = _smooth(np.abs(y) ** 2, 64)
+    t_peak = int(np.argmax(p))
+    assert abs(t_peak - t0_us * rate) < 40
+    # at least 60% of the pulse energy within +-300 samples of t0
+    c = int(t0_us * rate)
+    assert np.sum(np.abs(y[c - 300:c + 300]) ** 2) > 0.6 * np.sum(np.abs(y) ** 2)
+    # wrong sign: no collapse
+    yw = O.overlap_save(x, O.transfer(N, fcen, rate, dm, sign=+1), L, nfront)
+    pw = _smooth(np.abs(yw) ** 2, 64)
+    assert pw.max() < 0.1 * p.max()
+
+
+def test_channelised_pulse_arrives_at_delay_and_aligns():
+    """Per channel the dedispersed pulse sits at t0 + D DM (f_c^-2 - f_ref^-2);
+    after the delay-aligned sum it sits at t0 for every channel."""
+    b = synth.Beam(325.0, 2.0, 32, 40000, 60.0, n_int=4, sigma=0.0,
+                   period_s=0.0, amp_sigma=1.0, fwhm_s=0.4e-3)
+    b.sigma = 1.0
+    rng = np.random.default_rng(7)
+    fc, df = O.channel_centres(b.f_centre, b.bw, b.nchan)
+    t0_us = 120000.0
+    data = np.zeros((b.nsamp, b.nchan), dtype=np.complex128)
+    for c in range(b.nchan):
+        data[:, c] = synth.pulse_channel(rng, b.nsamp, df, fc[c] - df / 2, [t0_us],
+                                         arrival_law(b.dm, fc[-1]), 400.0, 30.0, 8)
+    out = O.dedisperse(data, b.f_centre, b.bw, b.dm, b.n_int)
+    for c in range(0, b.nchan, 5):
+        expect = (t0_us + K_DM_US * b.dm * (fc[c] ** -2 - fc[-1] ** -2)) * df / b.n_int
+        got = np.argmax(_smooth(out["P"][c], 5))
+        assert abs(got - expect) <= 3, (c, got, expect)
+    u0 = t0_us * df / b.n_int
+    assert abs(np.argmax(_smooth(out["I"], 5)) - u0) <= 2
+    # the aligned peak is about nchan times one channel's
+    assert out["I"].max() > 0.5 * b.nchan * np.mean([out["P"][c].max() for c in range(b.nchan)])
+
+
+# --------------------------------------------------------------------------
+# Chirp form: full-band chirp = per-channel chirp + delay + constant
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("f0,fc,dm", [(309.0, 311.53125, 67.9), (600.0, 615.5, 10.0)])
+def test_fullband_chirp_restricted_to_channel_is_channel_chirp_plus_delay(f0, fc, dm):
+    f = np.linspace(-0.03, 0.03, 41)
+    full = O.chirp_turns((fc - f0) + f, f0, dm)
+    chan = O.chirp_turns(f, fc, dm)
+    diff = full - chan
+    # affine in f: second differences vanish (relative to the phase size)
+    d2 = diff[2:] - 2 * diff[1:-1] + diff[:-2]
+    assert np.max(np.abs(d2)) < 1e-9 * max(1.0, np.max(np.abs(full)))
+    slope = np.polyfit(f, diff, 1)[0]              # turns per MHz = us
+    want = K_DM_US * dm * (1.0 / f0 ** 2 - 1.0 / fc ** 2)
+    assert abs(slope - want) < 1e-6 * abs(want)
+
+
+def test_chirp_group_delay_is_cold_plasma_law():
+    fc, dm = 327.0, 30.0
+    f = np.array([-0.5, -0.1, 0.2, 0.7])
+    h = 1e-6
+    dq = (O.chirp_turns(f + h, fc, dm) - O.chirp_turns(f - h, fc, dm)) / (2 * h)
+    want = K_DM_US * dm * (1.0 / fc ** 2 - 1.0 / (fc + f) ** 2)
+    assert np.allclose(dq, want, rtol=1e-6)
+    assert np.allclose(O.group_delay_us(f, fc, dm), want, rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Impulse response extent and the overlap / length rules
+# --------------------------------------------------------------------------
+def test_impulse_response_confined_to_predicted_extent():
+    fc, df, dm, n = 309.03125, 0.0625, 67.9, 4096
+    front, back = O.wrap_extent(fc, df, dm)
+    assert 30 < front < 45 and 30 < back < 45
+    h = np.fft.ifft(O.transfer(n, fc, df, dm))
+    lag = np.where(np.arange(n) < n // 2, np.arange(n), np.arange(n) - n)
+    inside = (lag >= -math.ceil(back) - 3) & (lag <= math.ceil(front) + 3)
+    e = np.abs(h) ** 2
+    assert e[inside].sum() > 0.97 * e.sum()
+    # both ends are reached: high frequencies delayed (positive lag) by ~front
+    assert e[(lag > front - 8) & (lag <= front + 3)].sum() > 0.01 * e.sum()
+    assert e[(lag < -back + 8) & (lag >= -back - 3)].sum() > 0.01 * e.sum()
+
+
+def test_length_rule_reproduces_max_dm_cases():
+    """Sec. 4.5's memory-bound DM limits each correspond to the same
+    real-sampled transform length under the Sec. 2.3 rule (2^27 points),
+    and twice the DM needs the next length."""
+    g = json.load(open(os.path.join(GOLDEN, "max_dm_sec4_5.json")))
+    for case in g["cases"]:
+        f, bw, dm = case["f_mhz"], case["bw_mhz"], case["dm"]
+        real_rate = 2.0 * bw
+        disp = O.dispersion_samples(f - bw / 2, f + bw / 2, real_rate, dm)
+        assert O.fft_len_rule(disp) == 1 << 27, case
+        disp2 = O.dispersion_samples(f - bw / 2, f + bw / 2, real_rate, 2.2 * dm)
+        assert O.fft_len_rule(disp2) == 1 << 28, case
+
+
+def test_plan_rule_reproduces_config1_lengths():
+    """The workload states FFT length 2^18 and overlap 2^17 for the 16 MHz
+    band at 610 MHz and DM 10: the length and overlap rules give both."""
+    N, L, nfront = O.overlap_plan(610.0, 16.0, 1, [10.0], n_int=16)
+    assert N == 1 << 18 and L == 1 << 17
+    front, back = O.wrap_extent(610.0, 16.0, 10.0)
+    assert math.ceil(front) <= nfront <= L - math.ceil(back)
+
+
+@pytest.mark.parametrize("fcen,bw,nchan,dms,n_int,fft", [
+    (325.0, 32.0, 512, [67.9], 4, 8192), (400.0, 200.0, 4096, [120.0], 4, 8192),
+    (325.0, 32.0, 512, [60.0, 76.0], 4, None), (610.0, 16.0, 512, [-10.0], 3, None),
+    (610.0, 16.0, 1, [10.0], 16, None)])
+def test_plan_window_lies_inside_uncorrupted_span(fcen, bw, nchan, dms, n_int, fft):
+    N, L, nfront = O.overlap_plan(fcen, bw, nchan, dms, n_int, fft)
+    fc, df = O.channel_centres(fcen, bw, nchan)
+    assert (N - L) % n_int == 0 and N & (N - 1) == 0
+    for dm in dms:
+        fr, bk = O.wrap_extent(fc, df, dm)
+        assert nfront >= math.ceil(fr) and nfront + (N - L) <= N - math.ceil(bk)
+
+
+# --------------------------------------------------------------------------
+# Detection, integration, delays and the aligned sum: brute force
+# --------------------------------------------------------------------------
+def test_detect_integrate_and_delay_sum_brute_force():
+    rng = np.random.default_rng(8)
+    C, T, n_int = 4, 23, 3
+    y = rng.standard_normal((C, T)) + 1j * rng.standard_normal((C, T))
+    P = O.detect_integrate(y, n_int)
+    t_int = T // n_int
+    assert P.shape == (C, t_int)
+    for c in range(C):
+        for u in range(t_int):
+            s = 0.0
+            for r in range(n_int):
+                z = y[c, u * n_int + r]
+                s += z.real * z.real + z.imag * z.imag
+            assert abs(P[c, u] - s) < 1e-12
+    d = np.array([5, 0, 2, 9])
+    I, cov = O.delay_sum(P, d)
+    for u in range(t_int):
+        s, n = 0.0, 0
+        for c in range(C):
+            if u + d[c] < t_int:
+                s += P[c, u + d[c]]
+                n += 1
+        assert abs(I[u] - s) < 1e-12 and cov[u] == n
+
+
+def test_channel_delays_sign_and_reference():
+    d = O.channel_delays(325.0, 32.0, 512, 67.9, 4)
+    assert d[-1] == 0 and d[0] > 0 and np.all(np.diff(d) <= 0)
+    fc, df = O.channel_centres(325.0, 32.0, 512)
+    want0 = K_DM_US * 67.9 * (fc[0] ** -2 - fc[-1] ** -2) * df / 4
+    assert abs(d[0] - want0) <= 0.5
+    dn = O.channel_delays(325.0, 32.0, 512, -67.9, 4)
+    assert dn[0] == 0 and dn[-1] > 0 and np.all(dn >= 0)
+
+
+def test_channel_centres_tile_the_band():
+    fc, df = O.channel_centres(325.0, 32.0, 512)
+    assert df == 0.0625 and fc[0] == 309.03125 and fc[-1] == 340.96875
+    assert np.allclose(np.diff(fc), df)
+
+
+def test_nyquist_bin_is_lower_band_edge():
+    """Channels are half-open, [f_c - df/2, f_c + df/2); the N/2 bin of a
+    channel's transform therefore sits at the lower edge, -df/2."""
+    off = O.bin_offsets(16, 2.0)
+    assert off[8] == -1.0 and off[7] == 7 * 2.0 / 16 and off.min() == -1.0
+    assert off.max() < 1.0
