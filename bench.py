@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of the coherent-dedispersion hot path on one MI355X.
+
+Workload (default): the 32 MHz GMRT-like filterbank beam -- 512 channels of
+62.5 kHz centred at 325 MHz, 4 s of int8 complex voltages (Gaussian sigma 20,
+clipped to +-127) with a dispersed 89 ms pulse train at DM 67.9; per-channel
+FFT length 8192, integration x4, delay-aligned sum to FP32 intensity.  Inputs
+are seeded, synthetic and resident in device memory before timing starts.
+
+One step = one call of the whole path (layout change, delays, fused
+FFT/chirp/IFFT/detect/integrate kernel, delay-aligned sum).  Prints one JSON
+line with Msamples/s (complex samples summed over channels per second), the
+real-time factor, the dominant kernel's roofline figures (from HIP events
+recorded on the launch stream during the timed steps) and the FP64 oracle
+timed on the host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published)
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E (published)
+K_DM_US = 4.148808e9       # cold-plasma constant, only to synthesise the pulses
+
+WORKLOADS = {
+    2: "filterbank_32MHz_512ch_4s_int8_N8192_nint4_dm67.9",
+    3: "filterbank_200MHz_4096ch_2s_int8_N8192_nint4_dm120",
+}
+
+
+def block_flops(N: int, M: int) -> float:
+    """Algorithmic flops of one overlap-save block: two complex FFTs at
+    5 N log2 N each (the paper's Eq. 5 convention), the chirp multiply
+    (6 flops per bin) and detection + integration (4 flops per kept sample)."""
+    return 10.0 * N * math.log2(N) + 6.0 * N + 4.0 * M
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("cdd_block.hip",):
+        with open(os.path.join(ROOT, "paper_1509_00186_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None if it is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        data = json.load(open(path))
+        rec = data[kernel][workload]
+    except Exception:
+        return None
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def make_input(cfg: int):
+    import synth
+    b = synth.config(cfg)
+    df = b.bw / b.nchan
+    fref = b.f_centre + b.bw / 2.0 - df / 2.0
+    law = lambda f: K_DM_US * b.dm * (1.0 / (f * f) - 1.0 / (fref * fref))  # noqa: E731
+    return b, synth.make_beam(b, synth.rng_for(cfg), law)
+
+
+def cpu_baseline(v, b, seconds: float):
+    """The FP64 oracle on whole channels of the same beam, one core, until
+    about ``seconds`` of work is done."""
+    import oracle as O
+    chans, t0 = [], time.perf_counter()
+    c = 0
+    while time.perf_counter() - t0 < seconds and c < b.nchan:
+        O.dedisperse(v, b.f_centre, b.bw, b.dm, b.n_int, fft_len=b.fft_len, overlap=128,
+                     nfront=64, channels=[c])
+        chans.append(c)
+        c += 1
+    dt = time.perf_counter() - t0
+    return {"value": len(chans) * b.nsamp / dt / 1e6, "unit": "Msamples/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d of %d channels, full %d-sample duration, FP64 numpy, %.1f s"
+                      % (len(chans), b.nchan, b.nsamp, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (the path shards by channel; see the design "
+              "notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1509_00186_amd as cdd
+
+    b, v = make_input(args.config)
+    dev = torch.device("cuda:0")
+    vd = torch.from_numpy(v).to(dev)
+    out = cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int)   # allocate
+    info = out["info"]
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, out=out)
+    torch.cuda.synchronize()
+    cdd.profile_read()
+    cdd.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cdd.profile_enable(False)
+    stages = cdd.profile_read()
+
+    ms = dt / args.steps * 1e3
+    samples = b.nchan * b.nsamp
+    value = samples / (ms * 1e-3) / 1e6
+    duration_s = b.nsamp / (b.bw / b.nchan * 1e6)
+    blk_ms, blk_n = stages["block"]
+    blk_avg = blk_ms / max(blk_n, 1)
+    flops = b.nchan * info["nblocks"] * block_flops(info["fft_len"], info["step"])
+    achieved = flops / (blk_avg * 1e-3) / 1e12
+    traffic = measured_traffic("block_kernel", WORKLOADS[args.config])
+    alg_bytes = b.nchan * b.nsamp * 2 + b.nchan * info["t_int"] * 4
+    res = {
+        "metric": "Msamples/s dedispersed",
+        "value": round(value, 1),
+        "unit": "Msamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.config], "nchan": b.nchan, "nsamp": b.nsamp,
+                   "fft_len": info["fft_len"], "overlap": info["overlap"],
+                   "nfront": info["nfront"], "n_int": b.n_int, "dm": b.dm,
+                   "input": "int8 time-major, resident in HBM"},
+        "x_realtime": round(duration_s / (ms * 1e-3), 1),
+        "stages_ms_per_step": {k: round(t / args.steps, 4) for k, (t, n) in stages.items()},
+        "roofline": {"kernel": "block_kernel (FFT+chirp+IFFT+detect+integrate)",
+                     "bound": "alu", "achieved": round(achieved, 2),
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": traffic,
+                     "avg_ms": round(blk_avg, 4),
+                     "alg_flops_per_launch": flops,
+                     "alg_hbm_bytes_per_launch": alg_bytes,
+                     "alg_hbm_frac": round(alg_bytes / (blk_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+        "gflops_paper_eq5": round(flops / (blk_avg * 1e-3) / 1e9, 1),
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(v, b, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * cdd.h -- C ABI of the MI355X coherent-dedispersion library (libcdd.so).
+ *
+ * The library implements overlap-save coherent dedispersion of channelised
+ * complex voltage beams as described by De & Gupta, "A Real-time Coherent
+ * Dedispersion Pipeline for the Giant Metrewave Radio Telescope":
+ *
+ *   per channel: forward FFT of N-sample blocks at stride M = N - L
+ *                (Sec. 2.2, Sec. 2.3), multiply by the all-pass chirp of
+ *                Eq. 3 (Sec. 2.1), inverse FFT keeping M samples per block
+ *                (overlap-save, Sec. 2.2 and Sec. 4.3), detect |y|^2 and
+ *                integrate n_int samples (Sec. 3.1, write-to-disk routine);
+ *   then:        delay-align the channels and sum them (Sec. 1.2, the
+ *                linear term of Eq. 2; sub-band alignment of Sec. 1.3).
+ *
+ * Conventions shared by every call:
+ *   - Channel c of a beam centred at f_centre with bandwidth bw (MHz, > 0)
+ *     covers [f_c - df/2, f_c + df/2), df = bw / nchan,
+ *     f_c = (f_centre - bw/2) + (c + 0.5) * df; channels ascend in frequency.
+ *   - The forward transform uses exp(-2 pi i j n / N), the inverse carries
+ *     1/N.  Bin j < N/2 sits at +j*df/N from f_c, bin j >= N/2 at (j-N)*df/N.
+ *   - The dedispersing filter is exp(-2 pi i q_j), q_j = D*DM*f_j^2 /
+ *     (f_c^2 (f_c + f_j)) turns (Eq. 3 with its sign read as the inverse of
+ *     the dispersive term of Eq. 2); D defaults to 4.148808e9.
+ *   - Block k of a channel transforms input samples [k*M - nfront,
+ *     k*M - nfront + N) (zeros outside the data) and yields output samples
+ *     [k*M, k*M + M) from its inverse-transform samples [nfront, nfront + M).
+ *   - Intensities are |y|^2 summed over samples [u*n_int, (u+1)*n_int),
+ *     u < T_int = nsamp / n_int, in (input units)^2.
+ *   - Channel delay d_c = floor(D*DM*(1/f_c^2 - 1/f_ref^2)*df/n_int + 0.5)
+ *     integrated samples, computed in FP64; f_ref is the top channel centre
+ *     for DM >= 0 and the bottom one for DM < 0.
+ *     I[u] = sum over c (ascending) with u + d_c < T_int of P_c[u + d_c];
+ *     coverage[u] is the number of channels in that sum.
+ *
+ * Memory: every data pointer is a DEVICE pointer owned by the caller, unless
+ * named host_*.  Calls that take a stream enqueue work on it and return
+ * without waiting (the stream is a hipStream_t passed as void*, NULL = the
+ * null stream).  The library owns only plan and server objects and a cache
+ * of FP64-derived twiddle tables per device.
+ *
+ * Errors: every call returns a cdd_status; no C++ exception, abort or exit
+ * crosses the ABI.  cdd_last_error() gives a message for the last failing
+ * call on the calling thread.
+ */
+#ifndef CDD_H
+#define CDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CDD_ABI_VERSION 1
+
+typedef enum {
+  CDD_OK = 0,
+  CDD_EINVAL = -1,    /* invalid argument; see cdd_last_error()            */
+  CDD_ENOMEM = -2,    /* host or device allocation failed                  */
+  CDD_EDEVICE = -3,   /* a HIP call failed; the message holds HIP's string  */
+  CDD_EBUSY = -4,     /* object in use (e.g. a stream with work in flight)  */
+  CDD_EAGAIN = -5,    /* admission refused now (over budget); retry later   */
+  CDD_EINTERNAL = -6, /* invariant broken inside the library               */
+  CDD_ENOTSUP = -7    /* valid request this build does not support          */
+} cdd_status;
+
+/* Input sample formats (time-major, as a voltage-beam recorder writes
+ * them; Sec. 1.1 and Sec. 2.3 describe 8-bit real/imag FFT outputs). */
+typedef enum {
+  CDD_CI8 = 0,  /* [nsamp][nchan][2] int8: re, im                        */
+  CDD_CF32 = 1  /* [nsamp][nchan] complex float (re, im interleaved)       */
+} cdd_dtype;
+
+/* How the chirp phase is evaluated on the GPU. */
+typedef enum {
+  CDD_PHASE_FP64_REDUCED = 0, /* q in FP64, r = q - rint(q), FP32 sin/cos   */
+  CDD_PHASE_FP32 = 1          /* q and sin/cos in FP32 (precision study)     */
+} cdd_phase_mode;
+
+/* Options.  Zero-initialise; zero fields take the rule-based defaults. */
+typedef struct {
+  int32_t explicit_plan;   /* 1: use fft_len/overlap/nfront as given        */
+  int32_t fft_len;         /* N (power of two); 0 = length rule (Sec. 2.3)  */
+  int32_t overlap;         /* L (explicit_plan only)                        */
+  int32_t nfront;          /* front discard (explicit_plan only)            */
+  double dm_const;         /* D of Eq. 3; 0 = 4.148808e9                    */
+  int32_t phase_mode;      /* cdd_phase_mode                                */
+  int32_t reserved[7];
+} cdd_opts;
+
+/* Plan figures for one beam (filled by cdd_query / cdd_plan_info). */
+typedef struct {
+  int32_t fft_len;     /* N                                                 */
+  int32_t overlap;     /* L                                                 */
+  int32_t nfront;      /* front discard                                     */
+  int32_t step;        /* M = N - L                                         */
+  int64_t nblocks;     /* blocks per channel, ceil(nsamp / M)               */
+  int64_t t_int;       /* nsamp / n_int                                     */
+  int32_t front;       /* ceil of the impulse response's forward reach      */
+  int32_t back;        /* ceil of its backward reach                        */
+  int64_t d_max;       /* largest channel delay (integrated samples)        */
+  size_t ws_bytes;     /* workspace the call needs                          */
+} cdd_plan_info;
+
+/*
+ * cdd_query -- plan figures and workspace size for cdd_dedisperse.  Host
+ * only; touches no device.  Arguments as cdd_dedisperse.  Rules (Sec. 2.2,
+ * 2.3): front/back = ceil of the largest forward/backward reach of the
+ * chirp's impulse response over the channels, from its group delay at the
+ * channel edges; L = next power of two >= front + back (>= 1), raised until
+ * n_int divides N - L; nfront = front + (L - front - back) / 2; N (if 0) =
+ * max(smallest power of two > 2 x the widest channel's dispersion samples,
+ * 2L, 256).  EINVAL if N is not a power of two in [256, 2^22], if
+ * L >= N ("DM too large for fft_len"), or on any invalid argument below.
+ */
+cdd_status cdd_query(int32_t dtype, int64_t nsamp, int32_t nchan,
+                     double f_centre_mhz, double bw_mhz, double dm,
+                     int32_t fft_len, int32_t n_int, int32_t want_voltages,
+                     const cdd_opts* opts, cdd_plan_info* info);
+
+/*
+ * cdd_dedisperse -- the whole path for one beam and one DM.
+ *   voltages     [nsamp][nchan][2] int8 or [nsamp][nchan] complex float
+ *   intensity    out, float [t_int]: the delay-aligned sum I
+ *   coverage     out, int32 [t_int] or NULL
+ *   chan_intensity out, float [nchan][t_int] (P_c) or NULL
+ *   volt_out     out, complex float [nchan][nsamp] dedispersed voltages,
+ *                channel-major, or NULL
+ *   workspace    device scratch of at least info.ws_bytes (cdd_query with
+ *                want_voltages = (volt_out != NULL)); 256-byte aligned
+ * Errors: EINVAL for nsamp < 1, nchan < 1, n_int < 1, n_int > nsamp,
+ * bw <= 0, f_centre - bw/2 <= 0, non-finite DM or frequency, bad dtype or
+ * phase mode, a plan rejected by cdd_query, a short or misaligned
+ * workspace, NULL voltages or intensity; EDEVICE if a launch fails.
+ * Negative DM is allowed (it disperses).
+ */
+cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp,
+                          int32_t nchan, double f_centre_mhz, double bw_mhz,
+                          double dm, int32_t fft_len, int32_t n_int,
+                          float* intensity, int32_t* coverage,
+                          float* chan_intensity, void* volt_out,
+                          const cdd_opts* opts, void* workspace,
+                          size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Batched form: many DM trials on several beams in one launch.  The
+ * forward transform of each (beam, channel, block) is computed once and
+ * every DM trial reuses it; the chirp is generated on the fly per trial.
+ * All trials of a beam share one (N, L, nfront), planned for the largest
+ * |DM| of the beam (overlap rules as cdd_query over all its DMs).
+ * ------------------------------------------------------------------- */
+typedef struct {
+  const void* voltages;   /* device, layout as cdd_dedisperse               */
+  int32_t dtype;
+  int32_t nchan;
+  int64_t nsamp;
+  double f_centre_mhz;
+  double bw_mhz;
+  const double* host_dms; /* host array of ndm DMs, copied at create        */
+  int32_t ndm;
+  int32_t n_int;
+  int32_t fft_len;        /* 0 = rule / autotuner                           */
+  int32_t reserved;
+  float* intensity;       /* device out, float [ndm][t_int]                 */
+  int32_t* coverage;      /* device out, int32 [ndm][t_int] or NULL         */
+} cdd_beam;
+
+typedef struct cdd_plan cdd_plan;
+
+/* Create a plan (host work only; twiddle tables are uploaded on first
+ * execute).  EINVAL as cdd_query for each beam; ENOMEM. */
+cdd_status cdd_plan_create(const cdd_beam* beams, int32_t nbeam,
+                           const cdd_opts* opts, cdd_plan** out);
+/* Plan figures of one beam (ws_bytes is the whole plan's workspace). */
+cdd_status cdd_plan_info_get(const cdd_plan* plan, int32_t beam,
+                             cdd_plan_info* info);
+/* Enqueue the whole batch on stream.  workspace as for cdd_dedisperse,
+ * sized by cdd_plan_info_get().ws_bytes.  The plan may be executed again
+ * (same buffers); it must not be executed concurrently with itself. */
+cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes,
+                            void* stream);
+void cdd_plan_destroy(cdd_plan* plan);
+
+/* ---------------------------------------------------------------------
+ * Stage timing.  When enabled, every call records a pair of HIP events on
+ * its stream around each kernel it launches; cdd_profile_read waits for the
+ * recorded events, returns the accumulated time per stage and starts over.
+ * Stages: 0 layout change (time-major -> channel-major), 1 channel delays,
+ * 2 fused FFT/chirp/IFFT/detect/integrate block kernel, 3 delay-aligned sum.
+ * ------------------------------------------------------------------- */
+#define CDD_NSTAGES 4
+typedef struct {
+  double ms[CDD_NSTAGES];     /* summed elapsed milliseconds per stage      */
+  int64_t count[CDD_NSTAGES]; /* number of launches timed per stage         */
+} cdd_profile;
+cdd_status cdd_profile_enable(int32_t on);  /* process-wide switch          */
+cdd_status cdd_profile_read(cdd_profile* out);
+
+/* ---------------------------------------------------------------------
+ * Host-side helpers (no device needed)
+ * ------------------------------------------------------------------- */
+const char* cdd_last_error(void);         /* thread-local, never NULL      */
+const char* cdd_status_str(cdd_status s); /* static string                 */
+int32_t cdd_abi_version(void);            /* CDD_ABI_VERSION               */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CDD_H */

@@ -1,0 +1,255 @@
+"""ctypes binding of libcdd.so: argument marshalling only.
+
+Every step of the computation runs in the HIP library; PyTorch supplies
+device memory (outputs and workspace) and the stream.  If the library has not
+been built, importing this module raises ImportError: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libcdd.so")
+
+CDD_CI8, CDD_CF32 = 0, 1
+PHASE_FP64_REDUCED, PHASE_FP32 = 0, 1
+
+STATUS = {0: "CDD_OK", -1: "CDD_EINVAL", -2: "CDD_ENOMEM", -3: "CDD_EDEVICE",
+          -4: "CDD_EBUSY", -5: "CDD_EAGAIN", -6: "CDD_EINTERNAL", -7: "CDD_ENOTSUP"}
+
+
+class CddError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("explicit_plan", ctypes.c_int32), ("fft_len", ctypes.c_int32),
+                ("overlap", ctypes.c_int32), ("nfront", ctypes.c_int32),
+                ("dm_const", ctypes.c_double), ("phase_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("fft_len", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("nfront", ctypes.c_int32), ("step", ctypes.c_int32),
+                ("nblocks", ctypes.c_int64), ("t_int", ctypes.c_int64),
+                ("front", ctypes.c_int32), ("back", ctypes.c_int32),
+                ("d_max", ctypes.c_int64), ("ws_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BeamDesc(ctypes.Structure):
+    _fields_ = [("voltages", ctypes.c_void_p), ("dtype", ctypes.c_int32),
+                ("nchan", ctypes.c_int32), ("nsamp", ctypes.c_int64),
+                ("f_centre_mhz", ctypes.c_double), ("bw_mhz", ctypes.c_double),
+                ("host_dms", ctypes.POINTER(ctypes.c_double)), ("ndm", ctypes.c_int32),
+                ("n_int", ctypes.c_int32), ("fft_len", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("intensity", ctypes.c_void_p),
+                ("coverage", ctypes.c_void_p)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 4), ("count", ctypes.c_int64 * 4)]
+
+
+STAGES = ("transpose", "delays", "block", "dsum")
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libcdd.so is not built (%s); run __graft_entry__.build()" % _LIB_PATH)
+    lib = ctypes.CDLL(_LIB_PATH)
+    i32, i64, f64, vp, sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                             ctypes.c_void_p, ctypes.c_size_t)
+    lib.cdd_query.argtypes = [i32, i64, i32, f64, f64, f64, i32, i32, i32,
+                              ctypes.POINTER(Opts), ctypes.POINTER(PlanInfo)]
+    lib.cdd_dedisperse.argtypes = [vp, i32, i64, i32, f64, f64, f64, i32, i32, vp, vp, vp,
+                                   vp, ctypes.POINTER(Opts), vp, sz, vp]
+    lib.cdd_plan_create.argtypes = [ctypes.POINTER(BeamDesc), i32, ctypes.POINTER(Opts),
+                                    ctypes.POINTER(vp)]
+    lib.cdd_plan_info_get.argtypes = [vp, i32, ctypes.POINTER(PlanInfo)]
+    lib.cdd_plan_execute.argtypes = [vp, vp, sz, vp]
+    lib.cdd_plan_destroy.argtypes = [vp]
+    lib.cdd_plan_destroy.restype = None
+    for f in ("cdd_query", "cdd_dedisperse", "cdd_plan_create", "cdd_plan_info_get",
+              "cdd_plan_execute"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.cdd_profile_enable.argtypes = [i32]
+    lib.cdd_profile_enable.restype = ctypes.c_int
+    lib.cdd_profile_read.argtypes = [ctypes.POINTER(Profile)]
+    lib.cdd_profile_read.restype = ctypes.c_int
+    lib.cdd_last_error.restype = ctypes.c_char_p
+    lib.cdd_last_error.argtypes = []
+    lib.cdd_status_str.restype = ctypes.c_char_p
+    lib.cdd_status_str.argtypes = [ctypes.c_int]
+    lib.cdd_abi_version.restype = ctypes.c_int32
+    return lib
+
+
+lib = _load()
+LIB_PATH = _LIB_PATH
+
+
+def _check(status: int):
+    if status != 0:
+        raise CddError(status, lib.cdd_last_error().decode())
+
+
+def profile_enable(on: bool = True):
+    _check(lib.cdd_profile_enable(int(bool(on))))
+
+
+def profile_read():
+    """{stage: (total_ms, count)} accumulated since the last read."""
+    p = Profile()
+    _check(lib.cdd_profile_read(ctypes.byref(p)))
+    return {name: (p.ms[i], p.count[i]) for i, name in enumerate(STAGES)}
+
+
+def make_opts(fft_len=0, overlap=None, nfront=None, dm_const=0.0, phase_mode=0):
+    o = Opts()
+    if overlap is not None or nfront is not None:
+        o.explicit_plan = 1
+        o.fft_len = int(fft_len)
+        o.overlap = int(overlap)
+        o.nfront = int(nfront)
+    o.dm_const = float(dm_const)
+    o.phase_mode = int(phase_mode)
+    return o
+
+
+def query(dtype, nsamp, nchan, f_centre, bw, dm, fft_len=0, n_int=1, want_voltages=False,
+          **opt):
+    """Plan figures of cdd_query as a dict (host only)."""
+    info = PlanInfo()
+    o = make_opts(fft_len, **opt)
+    _check(lib.cdd_query(int(dtype), int(nsamp), int(nchan), float(f_centre), float(bw),
+                         float(dm), int(fft_len), int(n_int), int(bool(want_voltages)),
+                         ctypes.byref(o), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def _layout(v):
+    """(dtype code, nsamp, nchan) of a time-major voltage tensor."""
+    import torch
+    if v.dtype == torch.int8:
+        if v.dim() != 3 or v.shape[2] != 2:
+            raise ValueError("int8 voltages must be [nsamp][nchan][2]")
+        return CDD_CI8, v.shape[0], v.shape[1]
+    if v.dtype == torch.complex64:
+        if v.dim() == 1:
+            return CDD_CF32, v.shape[0], 1
+        if v.dim() == 2:
+            return CDD_CF32, v.shape[0], v.shape[1]
+    raise ValueError("voltages must be int8 [T][C][2] or complex64 [T][C]")
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def dedisperse(voltages, f_centre, bw, dm, fft_len=0, n_int=1, *, want_chan=False,
+               want_voltages=False, overlap=None, nfront=None, dm_const=0.0, phase_mode=0,
+               stream=None, out=None):
+    """Run cdd_dedisperse on a resident device tensor.
+
+    Returns a dict: I [t_int] float32, cov [t_int] int32, P [nchan][t_int]
+    (if want_chan), y [nchan][nsamp] complex64 (if want_voltages), info.
+    ``out`` may pass preallocated tensors (keys I, cov, P, y, ws).
+    """
+    import torch
+    if not voltages.is_cuda or not voltages.is_contiguous():
+        raise ValueError("voltages must be a contiguous device tensor")
+    dt, nsamp, nchan = _layout(voltages)
+    o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode)
+    info = PlanInfo()
+    _check(lib.cdd_query(dt, nsamp, nchan, float(f_centre), float(bw), float(dm), int(fft_len),
+                         int(n_int), int(want_voltages), ctypes.byref(o), ctypes.byref(info)))
+    dev = voltages.device
+    out = dict(out or {})
+    t_int = info.t_int
+    if "I" not in out:
+        out["I"] = torch.empty(t_int, dtype=torch.float32, device=dev)
+    if "cov" not in out:
+        out["cov"] = torch.empty(t_int, dtype=torch.int32, device=dev)
+    if want_chan and "P" not in out:
+        out["P"] = torch.empty((nchan, t_int), dtype=torch.float32, device=dev)
+    if want_voltages and "y" not in out:
+        out["y"] = torch.empty((nchan, nsamp), dtype=torch.complex64, device=dev)
+    if "ws" not in out or out["ws"].numel() < info.ws_bytes:
+        out["ws"] = torch.empty(max(info.ws_bytes, 256), dtype=torch.uint8, device=dev)
+    ptr = lambda k: ctypes.c_void_p(out[k].data_ptr()) if k in out else None  # noqa: E731
+    _check(lib.cdd_dedisperse(ctypes.c_void_p(voltages.data_ptr()), dt, nsamp, nchan,
+                              float(f_centre), float(bw), float(dm), int(fft_len), int(n_int),
+                              ptr("I"), ptr("cov"), ptr("P") if want_chan else None,
+                              ptr("y") if want_voltages else None, ctypes.byref(o),
+                              ptr("ws"), out["ws"].numel(), _stream_handle(stream)))
+    out["info"] = info.as_dict()
+    return out
+
+
+class Plan:
+    """Batched DM trials over one or more beams (cdd_plan_*).
+
+    beams: list of dicts with keys voltages (device tensor), f_centre, bw,
+    dms (list of float), n_int, and optionally fft_len.  Output tensors are
+    allocated here: ``self.I[b]`` [ndm][t_int], ``self.cov[b]``.
+    """
+
+    def __init__(self, beams, dm_const=0.0, phase_mode=0, fft_len=0, overlap=None,
+                 nfront=None):
+        import torch
+        self._descs = (BeamDesc * len(beams))()
+        self._keep = []
+        self.I, self.cov = [], []
+        for i, b in enumerate(beams):
+            v = b["voltages"]
+            dt, nsamp, nchan = _layout(v)
+            dms = (ctypes.c_double * len(b["dms"]))(*[float(x) for x in b["dms"]])
+            n_int = int(b.get("n_int", 1))
+            t_int = nsamp // n_int
+            I = torch.empty((len(b["dms"]), t_int), dtype=torch.float32, device=v.device)
+            cov = torch.empty((len(b["dms"]), t_int), dtype=torch.int32, device=v.device)
+            self.I.append(I)
+            self.cov.append(cov)
+            self._keep += [v, dms]
+            d = self._descs[i]
+            d.voltages, d.dtype, d.nchan, d.nsamp = v.data_ptr(), dt, nchan, nsamp
+            d.f_centre_mhz, d.bw_mhz = float(b["f_centre"]), float(b["bw"])
+            d.host_dms, d.ndm, d.n_int = dms, len(b["dms"]), n_int
+            d.fft_len = int(b.get("fft_len", fft_len))
+            d.intensity, d.coverage = I.data_ptr(), cov.data_ptr()
+        o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode)
+        h = ctypes.c_void_p()
+        _check(lib.cdd_plan_create(self._descs, len(beams), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        info = self.info(0)
+        self.ws = torch.empty(max(info["ws_bytes"], 256), dtype=torch.uint8,
+                              device=beams[0]["voltages"].device)
+
+    def info(self, beam):
+        inf = PlanInfo()
+        _check(lib.cdd_plan_info_get(self._h, int(beam), ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def execute(self, stream=None):
+        _check(lib.cdd_plan_execute(self._h, ctypes.c_void_p(self.ws.data_ptr()),
+                                    self.ws.numel(), _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.cdd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

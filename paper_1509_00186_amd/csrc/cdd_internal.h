@@ -1,0 +1,81 @@
+// Internal declarations shared by the host API, the planner and the kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cdd.h"
+
+namespace cdd {
+
+constexpr double kDefaultD = 4.148808e9;  // Eq. 3's D (us MHz^2 cm^3 / pc)
+constexpr int kMinFFT = 256;
+constexpr int kMaxFFT = 1 << 22;
+constexpr int kMaxDmTile = 64;            // DM trials per batched launch
+
+// Thread-local error message and status (set by every failing call).
+cdd_status fail(cdd_status s, const char* fmt, ...);
+void clear_error();
+
+// Channel geometry and the overlap-save plan of one beam (all DMs share it).
+struct BeamPlan {
+  int32_t dtype = CDD_CI8;
+  int64_t nsamp = 0;
+  int32_t nchan = 0;
+  double f_centre = 0, bw = 0, df = 0, f_lo = 0, dconst = kDefaultD;
+  int32_t n_int = 1;
+  int32_t phase_mode = CDD_PHASE_FP64_REDUCED;
+  std::vector<double> dms;
+  int32_t N = 0, L = 0, nfront = 0, M = 0;
+  int32_t front = 0, back = 0;
+  int64_t nblocks = 0, t_int = 0, d_max = 0;
+};
+
+// Fill a BeamPlan from the call arguments, applying the length, overlap
+// and front-discard rules (Sec. 2.2, 2.3) unless opts->explicit_plan.
+cdd_status make_plan(int32_t dtype, int64_t nsamp, int32_t nchan,
+                     double f_centre, double bw, const double* dms, int32_t ndm,
+                     int32_t fft_len, int32_t n_int, const cdd_opts* opts,
+                     BeamPlan* out);
+
+// FP64 channel centre, same operation order as the device code.
+double channel_centre(const BeamPlan& p, int c);
+// FP64 delay of channel c in integrated samples (Sec. 1.2, Eq. 2).
+int64_t channel_delay(const BeamPlan& p, double dm, int c);
+
+// Workspace layout for one beam (one DM tile).
+struct WsLayout {
+  size_t xt_off = 0, xt_bytes = 0;   // channel-major copy of the input
+  size_t p_off = 0, p_bytes = 0;     // per-channel intensities [ndm][C][T_int]
+  size_t d_off = 0, d_bytes = 0;     // delays [ndm][C] int32
+  size_t total = 0;
+};
+WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p);
+
+// ---------------------------------------------------------------------
+// Launchers (defined in the .hip files).  Return hipError_t as int.
+// ---------------------------------------------------------------------
+struct DmTile {
+  int32_t ndm = 0;
+  double dm[kMaxDmTile];
+};
+
+int launch_transpose(const void* in, void* out, int32_t dtype, int64_t nsamp,
+                     int32_t nchan, void* stream);
+int launch_block(const BeamPlan& p, const void* xt, const DmTile& dms,
+                 float* P, void* vout, void* stream);
+int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream);
+int launch_dsum(const BeamPlan& p, int ndm, const float* P, const int32_t* d,
+                float* I, int32_t* cov, int64_t out_stride, void* stream);
+bool block_supported(int N);
+
+// Stage timing (cdd_profile.hip): no-ops unless profiling is enabled.
+bool profiling();
+int stage_begin(void* stream, void** token);
+int stage_end(int stage, void* stream, void* token);
+enum { kStageTranspose = 0, kStageDelays = 1, kStageBlock = 2, kStageDsum = 3 };
+const char* hip_error_string(int err);
+
+}  // namespace cdd

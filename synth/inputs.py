@@ -127,26 +127,27 @@ def pulse_channel(rng, nsamp: int, rate_mhz: float, f_lo: float, t_pulses_us,
     y = np.zeros(nsamp, dtype=np.complex128)
     sig = fwhm_us / (2.0 * np.sqrt(2.0 * np.log(2.0))) * rate_mhz   # samples
     half = int(np.ceil(5.0 * sig)) + nsub
+    width = 2 * half + 2
+    tp = np.asarray(list(t_pulses_us), dtype=np.float64)
+    if tp.size == 0:
+        return y
+    ar = np.arange(width)
     for s in range(nsub):
         nu = (s + 0.5) / nsub * rate_mhz                 # MHz above f_lo
         f_s = f_lo + nu
         nu_c = nu - rate_mhz / 2.0                       # relative to centre
-        for tp in t_pulses_us:
-            centre = (tp + arrival_us(f_s)) * rate_mhz   # samples
-            a = int(np.floor(centre)) - half
-            b = int(np.ceil(centre)) + half + 1
-            lo, hi = max(0, a), min(nsamp, b)
-            if hi <= lo:
-                continue
-            n = hi - lo + nsub - 1
-            w = rng.standard_normal((n, 2))
-            wn = (w[:, 0] + 1j * w[:, 1]) / np.sqrt(2.0)
-            if nsub > 1:
-                c = np.cumsum(np.concatenate([[0], wn]))
-                wn = (c[nsub:] - c[:-nsub]) / np.sqrt(nsub)
-            t = np.arange(lo, hi, dtype=np.float64)
-            env = np.exp(-0.5 * ((t - centre) / sig) ** 2)
-            y[lo:hi] += (amp / np.sqrt(nsub)) * env * wn[:hi - lo] * np.exp(2j * np.pi * nu_c * t / rate_mhz)
+        centre = (tp + arrival_us(f_s)) * rate_mhz       # samples, per pulse
+        t = (np.floor(centre).astype(np.int64) - half)[:, None] + ar[None, :]
+        w = rng.standard_normal((tp.size, width + nsub - 1, 2))
+        wn = (w[..., 0] + 1j * w[..., 1]) / np.sqrt(2.0)
+        if nsub > 1:
+            c = np.concatenate([np.zeros((tp.size, 1)), np.cumsum(wn, axis=1)], axis=1)
+            wn = (c[:, nsub:] - c[:, :-nsub]) / np.sqrt(nsub)
+        env = np.exp(-0.5 * ((t - centre[:, None]) / sig) ** 2)
+        val = (amp / np.sqrt(nsub)) * env * wn[:, :width] \
+            * np.exp(2j * np.pi * nu_c * t / rate_mhz)
+        ok = (t >= 0) & (t < nsamp)
+        np.add.at(y, t[ok], val[ok])
     return y
 
 
@@ -163,30 +164,42 @@ def make_beam(beam: Beam, rng, arrival_us=None, nsub: int = 8,
               pulse_chans=None) -> np.ndarray:
     """Noise plus (if arrival_us is given) a dispersed pulse train.
 
-    int8 beams: [nsamp][nchan][2] int8, noise sigma per component, pulses of
-    amp_sigma * sigma.  Complex beams: [nsamp][nchan] complex64.
+    int8 beams: [nsamp][nchan][2] int8, Gaussian noise of sigma per
+    component plus pulses of amp_sigma * sigma, rounded half to even once and
+    clipped to +-127.  Complex beams: [nsamp][nchan] complex64.
     ``pulse_chans`` limits the pulse synthesis to some channels (speed).
     """
     fc_lo = beam.f_centre - beam.bw / 2.0
+    T, C = beam.nsamp, beam.nchan
     if beam.int8:
-        data = noise_int8(rng, beam.nsamp, beam.nchan, beam.sigma)
+        g = np.empty((T, C, 2), dtype=np.float32)
+        chunk = max(1, (1 << 22) // (2 * C))
+        for t0 in range(0, T, chunk):
+            t1 = min(T, t0 + chunk)
+            g[t0:t1] = rng.standard_normal((t1 - t0, C, 2), dtype=np.float32)
+            g[t0:t1] *= np.float32(beam.sigma)
     else:
-        data = np.stack([noise_cf32(rng, beam.nsamp, beam.sigma)
-                         for _ in range(beam.nchan)], axis=1)
-    if arrival_us is None or beam.amp_sigma == 0:
+        data = np.stack([noise_cf32(rng, T, beam.sigma) for _ in range(C)], axis=1)
+    if arrival_us is not None and beam.amp_sigma != 0:
+        tps = pulse_times_us(beam)
+        chans = range(C) if pulse_chans is None else pulse_chans
+        for c in chans:
+            p = pulse_channel(rng, T, beam.df, fc_lo + c * beam.df, tps, arrival_us,
+                              beam.fwhm_s * 1e6, beam.amp_sigma * beam.sigma, nsub)
+            nz = np.flatnonzero(p)
+            if beam.int8:
+                g[nz, c, 0] += p.real[nz].astype(np.float32)
+                g[nz, c, 1] += p.imag[nz].astype(np.float32)
+            else:
+                data[nz, c] += p[nz].astype(np.complex64)
+    if not beam.int8:
         return data
-    tps = pulse_times_us(beam)
-    chans = range(beam.nchan) if pulse_chans is None else pulse_chans
-    for c in chans:
-        p = pulse_channel(rng, beam.nsamp, beam.df, fc_lo + c * beam.df, tps,
-                          arrival_us, beam.fwhm_s * 1e6,
-                          beam.amp_sigma * beam.sigma, nsub)
-        if beam.int8:
-            v = data[:, c, :].astype(np.float64)
-            data[:, c, :] = quantise_int8(v[:, 0] + p.real, v[:, 1] + p.imag)
-        else:
-            data[:, c] = (data[:, c] + p).astype(np.complex64)
-    return data
+    out = np.empty((T, C, 2), dtype=np.int8)
+    chunk = max(1, (1 << 24) // (2 * C))
+    for t0 in range(0, T, chunk):
+        t1 = min(T, t0 + chunk)
+        out[t0:t1] = np.clip(np.rint(g[t0:t1]), -127, 127).astype(np.int8)
+    return out
 
 
 def single_pulse_cf32(rng, nsamp: int, rate_mhz: float, f_centre: float,

@@ -1,0 +1,219 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (stated as relative L2 against the oracle): dedispersed voltages
+<= 1e-5, intensities (per channel and the aligned sum) <= 1e-4; coverage
+counts and delays exact.  Every input is seeded and synthetic.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from tests.util import arrival_law, flush, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_V, TOL_I = 1e-5, 1e-4
+
+
+def _cdd():
+    import paper_1509_00186_amd as cdd
+    return cdd
+
+
+def _run_both(v, fcen, bw, dm, n_int, fft_len=0, phase_mode=0, want_v=True, **plan):
+    import torch
+    cdd = _cdd()
+    flush("case: shape=%s dtype=%s fcen=%g bw=%g dm=%g n_int=%d N=%d phase=%d" %
+          (tuple(v.shape), v.dtype, fcen, bw, dm, n_int, fft_len, phase_mode))
+    g = cdd.dedisperse(to_dev(v), fcen, bw, dm, fft_len, n_int, want_chan=True,
+                       want_voltages=want_v, phase_mode=phase_mode, **plan)
+    torch.cuda.synchronize()
+    info = g["info"]
+    o = O.dedisperse(v, fcen, bw, dm, n_int, fft_len=info["fft_len"],
+                     overlap=info["overlap"], nfront=info["nfront"], want_voltages=want_v)
+    got = {k: g[k].cpu().numpy() for k in ("I", "cov", "P") + (("y",) if want_v else ())}
+    return got, o, info
+
+
+def _check(got, o, tol_v=TOL_V, tol_i=TOL_I):
+    if "y" in got:
+        assert rel_l2(got["y"], o["y"]) <= tol_v, rel_l2(got["y"], o["y"])
+    assert rel_l2(got["P"], o["P"]) <= tol_i, rel_l2(got["P"], o["P"])
+    assert rel_l2(got["I"], o["I"]) <= tol_i, rel_l2(got["I"], o["I"])
+    assert np.array_equal(got["cov"], o["cov"])
+
+
+def _beam_int8(seed, nsamp, nchan, fcen, bw, dm, pulse=True):
+    b = synth.Beam(fcen, bw, nchan, nsamp, dm, period_s=0.02, fwhm_s=0.3e-3)
+    rng = np.random.default_rng(seed)
+    fc, _ = O.channel_centres(fcen, bw, nchan)
+    return synth.make_beam(b, rng, arrival_law(dm, fc[-1]) if pulse else None)
+
+
+@pytest.mark.parametrize("N", [256, 512, 1024, 2048, 4096, 8192, 16384])
+def test_every_block_length_int8(N):
+    # channel width chosen so the impulse response fits N/8 at this DM
+    nchan, fcen, dm = 6, 330.0, 25.0
+    df = {256: 0.02, 512: 0.03, 1024: 0.04, 2048: 0.05, 4096: 0.0625, 8192: 0.08,
+          16384: 0.1}[N]
+    M_guess = N - N // 8
+    nsamp = 3 * M_guess + 777
+    v = _beam_int8(10 + N, nsamp, nchan, fcen, df * nchan, dm)
+    got, o, info = _run_both(v, fcen, df * nchan, dm, 4, N)
+    assert info["fft_len"] == N
+    _check(got, o)
+
+
+def test_cf32_single_channel_no_transpose():
+    rng = np.random.default_rng(21)
+    x = (rng.standard_normal(20_011) + 1j * rng.standard_normal(20_011)).astype(np.complex64)
+    got, o, _ = _run_both(x, 600.0, 2.0, 3.0, 2, 4096)
+    _check(got, o)
+
+
+def test_cf32_multichannel_ragged_channels():
+    rng = np.random.default_rng(22)
+    x = (rng.standard_normal((9_000, 67)) + 1j * rng.standard_normal((9_000, 67)))
+    x = x.astype(np.complex64) * 7.0
+    got, o, _ = _run_both(x, 325.0, 67 * 0.0625, 40.0, 3, 2048)
+    _check(got, o)
+
+
+def test_negative_dm_and_odd_integration():
+    v = _beam_int8(23, 15_001, 16, 325.0, 1.0, -30.0, pulse=False)
+    got, o, info = _run_both(v, 325.0, 1.0, -30.0, 5, 1024)
+    assert (info["fft_len"] - info["overlap"]) % 5 == 0
+    _check(got, o)
+
+
+def test_dm_zero_returns_input():
+    v = _beam_int8(24, 5000, 3, 325.0, 0.5, 0.0, pulse=False)
+    got, o, _ = _run_both(v, 325.0, 0.5, 0.0, 1, 512)
+    x = (v[..., 0].astype(float) + 1j * v[..., 1]).T
+    assert rel_l2(got["y"], x) < 1e-6
+    _check(got, o)
+
+
+def test_tiny_and_edge_shapes():
+    # one sample, n_int = nsamp
+    v = _beam_int8(25, 1, 1, 325.0, 0.0625, 10.0, pulse=False)
+    got, o, _ = _run_both(v, 325.0, 0.0625, 10.0, 1, 256)
+    _check(got, o)
+    # fewer samples than one block step, integration longer than a block
+    v = _beam_int8(26, 700, 65, 325.0, 65 * 0.0625, 10.0, pulse=False)
+    got, o, _ = _run_both(v, 325.0, 65 * 0.0625, 10.0, 700, 1024)
+    _check(got, o)
+    # explicit plan: off-centre window
+    v = _beam_int8(27, 3000, 2, 325.0, 0.125, 10.0, pulse=False)
+    q = _cdd().query(0, 3000, 2, 325.0, 0.125, 10.0, 512, 2)
+    nf = q["front"] + 1
+    got, o, info = _run_both(v, 325.0, 0.125, 10.0, 2, 512, overlap=q["overlap"], nfront=nf)
+    assert info["nfront"] == nf
+    _check(got, o)
+
+
+def test_phase_fp32_variant_error_is_reported_not_hidden():
+    v = _beam_int8(28, 20_000, 8, 400.0, 8 * 0.048828125, 120.0)
+    got64, o, _ = _run_both(v, 400.0, 8 * 0.048828125, 120.0, 4, 8192, phase_mode=0)
+    got32, _, _ = _run_both(v, 400.0, 8 * 0.048828125, 120.0, 4, 8192, phase_mode=1)
+    e64, e32 = rel_l2(got64["y"], o["y"]), rel_l2(got32["y"], o["y"])
+    flush("voltage rel L2: fp64-reduced %.3g  fp32 phase %.3g" % (e64, e32))
+    assert e64 <= TOL_V
+    assert e32 > e64          # the FP32 phase is measurably worse
+    assert rel_l2(got32["I"], o["I"]) <= 1e-3
+
+
+def test_config2_full_size():
+    """512 channels x 4 s at 32 MHz, N = 8192, n_int = 4, DM 67.9, in the
+    launch shape the benchmark times: per-channel intensities of 64 sampled
+    channels against the oracle, the aligned sum against the oracle's delay
+    sum of the GPU's per-channel intensities, coverage exact."""
+    import torch
+    cdd = _cdd()
+    b = synth.config(2)
+    fc, _ = O.channel_centres(b.f_centre, b.bw, b.nchan)
+    v = synth.make_beam(b, synth.rng_for(2), arrival_law(b.dm, fc[-1]))
+    flush("config 2 full size")
+    g = cdd.dedisperse(to_dev(v), b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, want_chan=True)
+    torch.cuda.synchronize()
+    info = g["info"]
+    assert (info["fft_len"], info["overlap"], info["nfront"]) == (8192, 128, 64)
+    P = g["P"].cpu().numpy()
+    chans = list(range(3, 512, 8)) + [0, 511]
+    o = O.dedisperse(v, b.f_centre, b.bw, b.dm, b.n_int, fft_len=8192, overlap=128,
+                     nfront=64, channels=chans)
+    assert rel_l2(P[chans], o["P"]) <= TOL_I, rel_l2(P[chans], o["P"])
+    d = O.channel_delays(b.f_centre, b.bw, b.nchan, b.dm, b.n_int)
+    I, cov = O.delay_sum(P.astype(np.float64), d)
+    assert rel_l2(g["I"].cpu().numpy(), I) <= 1e-5
+    assert np.array_equal(g["cov"].cpu().numpy(), cov)
+
+
+def test_config3_sampled_channels():
+    """4096 channels x 2 s at 200 MHz, DM 120: per-channel intensities of
+    sampled channels against the oracle; the aligned sum against the oracle's
+    delay-sum of the GPU's own per-channel intensities (delays exact)."""
+    import torch
+    cdd = _cdd()
+    b = synth.config(3)
+    v = synth.make_beam(b, synth.rng_for(3))
+    g = cdd.dedisperse(to_dev(v), b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, want_chan=True)
+    torch.cuda.synchronize()
+    P = g["P"].cpu().numpy()
+    chans = list(range(0, 4096, 257)) + [4095]
+    o = O.dedisperse(v, b.f_centre, b.bw, b.dm, b.n_int, fft_len=8192, overlap=128,
+                     nfront=64, channels=chans)
+    assert rel_l2(P[chans], o["P"]) <= TOL_I
+    d = O.channel_delays(b.f_centre, b.bw, b.nchan, b.dm, b.n_int)
+    I, cov = O.delay_sum(P.astype(np.float64), d)
+    assert rel_l2(g["I"].cpu().numpy(), I) <= 1e-5
+    assert np.array_equal(g["cov"].cpu().numpy(), cov)
+
+
+def test_batched_dm_trials_equal_single_calls_and_oracle():
+    import torch
+    cdd = _cdd()
+    fcen, bw, nchan, nsamp, n_int = 325.0, 16 * 0.0625, 16, 30_000, 4
+    dms = [60.0 + 0.254 * i * 8 for i in range(8)]
+    v = _beam_int8(30, nsamp, nchan, fcen, bw, 67.9)
+    vd = to_dev(v)
+    plan = cdd.Plan([dict(voltages=vd, f_centre=fcen, bw=bw, dms=dms, n_int=n_int,
+                          fft_len=4096)])
+    info = plan.info(0)
+    plan.execute()
+    torch.cuda.synchronize()
+    for i, dm in enumerate(dms):
+        one = cdd.dedisperse(vd, fcen, bw, dm, 4096, n_int, overlap=info["overlap"],
+                             nfront=info["nfront"])
+        torch.cuda.synchronize()
+        a, b1 = plan.I[0][i].cpu().numpy(), one["I"].cpu().numpy()
+        assert rel_l2(a, b1) <= 1e-6
+        o = O.dedisperse(v, fcen, bw, dm, n_int, fft_len=4096, overlap=info["overlap"],
+                         nfront=info["nfront"])
+        assert rel_l2(a, o["I"]) <= TOL_I
+        assert np.array_equal(plan.cov[0][i].cpu().numpy(), o["cov"])
+    plan.close()
+
+
+def test_multi_beam_plan_uneven_beams():
+    import torch
+    cdd = _cdd()
+    beams, raw = [], []
+    for k, (fcen, nchan, df, nsamp, dm) in enumerate([(610.0, 8, 0.03125, 12_000, 10.0),
+                                                      (325.0, 24, 0.0625, 9_000, 67.9)]):
+        v = _beam_int8(40 + k, nsamp, nchan, fcen, nchan * df, dm)
+        raw.append((v, fcen, nchan * df, [dm, dm + 1.5, dm - 2.0]))
+        beams.append(dict(voltages=to_dev(v), f_centre=fcen, bw=nchan * df,
+                          dms=[dm, dm + 1.5, dm - 2.0], n_int=2))
+    plan = cdd.Plan(beams)
+    plan.execute()
+    torch.cuda.synchronize()
+    for bi, (v, fcen, bw, dms) in enumerate(raw):
+        info = plan.info(bi)
+        for i, dm in enumerate(dms):
+            o = O.dedisperse(v, fcen, bw, dm, 2, fft_len=info["fft_len"],
+                             overlap=info["overlap"], nfront=info["nfront"])
+            assert rel_l2(plan.I[bi][i].cpu().numpy(), o["I"]) <= TOL_I
+            assert np.array_equal(plan.cov[bi][i].cpu().numpy(), o["cov"])
+    plan.close()
