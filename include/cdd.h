@@ -87,7 +87,9 @@ typedef struct {
   int32_t nfront;          /* front discard (explicit_plan only)            */
   double dm_const;         /* D of Eq. 3; 0 = 4.148808e9                    */
   int32_t phase_mode;      /* cdd_phase_mode                                */
-  int32_t reserved[7];
+  int32_t kernel_variant;  /* block-kernel schedule for this N; 0 = default,
+                              1.. = alternatives (cdd_kernel_variants)     */
+  int32_t reserved[6];
 } cdd_opts;
 
 /* Plan figures for one beam (filled by cdd_query / cdd_plan_info). */
@@ -204,6 +206,9 @@ cdd_status cdd_profile_read(cdd_profile* out);
 const char* cdd_last_error(void);         /* thread-local, never NULL      */
 const char* cdd_status_str(cdd_status s); /* static string                 */
 int32_t cdd_abi_version(void);            /* CDD_ABI_VERSION               */
+/* Number of block-kernel schedules compiled for transform length N (0 if
+ * N is not supported); valid kernel_variant values are 0 .. count-1. */
+int32_t cdd_kernel_variants(int32_t fft_len);
 
 #ifdef __cplusplus
 }

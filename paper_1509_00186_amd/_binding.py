@@ -29,7 +29,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("explicit_plan", ctypes.c_int32), ("fft_len", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("nfront", ctypes.c_int32),
                 ("dm_const", ctypes.c_double), ("phase_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("kernel_variant", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -88,6 +88,8 @@ def _load():
     lib.cdd_status_str.restype = ctypes.c_char_p
     lib.cdd_status_str.argtypes = [ctypes.c_int]
     lib.cdd_abi_version.restype = ctypes.c_int32
+    lib.cdd_kernel_variants.argtypes = [i32]
+    lib.cdd_kernel_variants.restype = ctypes.c_int32
     return lib
 
 
@@ -111,8 +113,9 @@ def profile_read():
     return {name: (p.ms[i], p.count[i]) for i, name in enumerate(STAGES)}
 
 
-def make_opts(fft_len=0, overlap=None, nfront=None, dm_const=0.0, phase_mode=0):
+def make_opts(fft_len=0, overlap=None, nfront=None, dm_const=0.0, phase_mode=0, variant=0):
     o = Opts()
+    o.kernel_variant = int(variant)
     if overlap is not None or nfront is not None:
         o.explicit_plan = 1
         o.fft_len = int(fft_len)
@@ -157,7 +160,7 @@ def _stream_handle(stream):
 
 def dedisperse(voltages, f_centre, bw, dm, fft_len=0, n_int=1, *, want_chan=False,
                want_voltages=False, overlap=None, nfront=None, dm_const=0.0, phase_mode=0,
-               stream=None, out=None):
+               variant=0, stream=None, out=None):
     """Run cdd_dedisperse on a resident device tensor.
 
     Returns a dict: I [t_int] float32, cov [t_int] int32, P [nchan][t_int]
@@ -168,7 +171,7 @@ def dedisperse(voltages, f_centre, bw, dm, fft_len=0, n_int=1, *, want_chan=Fals
     if not voltages.is_cuda or not voltages.is_contiguous():
         raise ValueError("voltages must be a contiguous device tensor")
     dt, nsamp, nchan = _layout(voltages)
-    o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode)
+    o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode, variant)
     info = PlanInfo()
     _check(lib.cdd_query(dt, nsamp, nchan, float(f_centre), float(bw), float(dm), int(fft_len),
                          int(n_int), int(want_voltages), ctypes.byref(o), ctypes.byref(info)))

@@ -8,20 +8,81 @@
 namespace cdd {
 
 // ---------------------------------------------------------------------------
-// Time-major [nsamp][nchan] -> channel-major [nchan][nsamp], one element per
-// complex sample (2 bytes for int8 pairs, 8 bytes for float pairs), through
-// a 64 x 64 LDS tile.  Grid: one workgroup per tile, flattened.
+// Time-major [nsamp][nchan] -> channel-major [nchan][nsamp].
+// int8 pairs (2 bytes per complex sample): 64 samples x 128 channels per
+// workgroup through LDS; each lane moves 8 bytes (4 complex samples) on both
+// the load (along channels) and the store (along time) side.
+// Float pairs: a 64 x 64 tile, one element per lane access.
 // ---------------------------------------------------------------------------
-template <typename E>
-__global__ __launch_bounds__(256) void transpose_kernel(const E* __restrict__ in,
-                                                        E* __restrict__ out, int64_t nsamp,
-                                                        int32_t nchan, int32_t tiles_c) {
-  __shared__ E tile[64][65];
+__global__ __launch_bounds__(256) void transpose_i8_kernel(const unsigned short* __restrict__ in,
+                                                           unsigned short* __restrict__ out,
+                                                           int64_t nsamp, int32_t nchan,
+                                                           int32_t tiles_c, int32_t in_aligned) {
+  __shared__ unsigned short tile[64][128 + 4];
   const int64_t bid = blockIdx.x;
-  const int tc = (int)(bid % tiles_c);
-  const int64_t tt = bid / tiles_c;
-  const int c0 = tc * 64;
-  const int64_t t0 = tt * 64;
+  const int c0 = (int)(bid % tiles_c) * 128;
+  const int64_t t0 = (bid / tiles_c) * 64;
+  const int l = threadIdx.x;
+  const bool full =
+      in_aligned && (c0 + 128 <= nchan) && (t0 + 64 <= nsamp) && (nchan % 4 == 0);
+  // load: 32 lanes per row, 4 channels each; 8 rows per pass of 256 lanes
+  {
+    const int cl = (l & 31) * 4, rl = l >> 5;
+#pragma unroll
+    for (int i = 0; i < 64; i += 8) {
+      const int r = rl + i;
+      const int64_t ts = t0 + r;
+      if (full) {
+        const uint2 w = *(const uint2*)(in + ts * nchan + c0 + cl);
+        tile[r][cl + 0] = (unsigned short)(w.x & 0xffff);
+        tile[r][cl + 1] = (unsigned short)(w.x >> 16);
+        tile[r][cl + 2] = (unsigned short)(w.y & 0xffff);
+        tile[r][cl + 3] = (unsigned short)(w.y >> 16);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int cs = c0 + cl + q;
+          tile[r][cl + q] = (ts < nsamp && cs < nchan) ? in[ts * nchan + cs] : (unsigned short)0;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // store: 16 lanes per channel row, 4 samples each; 16 channels per pass
+  {
+    const int tl = (l & 15) * 4, cr = l >> 4;
+#pragma unroll
+    for (int i = 0; i < 128; i += 16) {
+      const int c = cr + i;
+      const int cs = c0 + c;
+      if (cs >= nchan) continue;
+      const int64_t ts = t0 + tl;
+      if (full || ts + 4 <= nsamp) {
+        if ((nsamp & 3) == 0 || full) {
+          uint2 w;
+          w.x = (unsigned)tile[tl + 0][c] | ((unsigned)tile[tl + 1][c] << 16);
+          w.y = (unsigned)tile[tl + 2][c] | ((unsigned)tile[tl + 3][c] << 16);
+          if (((int64_t)cs * nsamp + ts) % 4 == 0) {
+            *(uint2*)(out + (int64_t)cs * nsamp + ts) = w;
+            continue;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (ts + q < nsamp) out[(int64_t)cs * nsamp + ts + q] = tile[tl + q][c];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void transpose_c8_kernel(const float2* __restrict__ in,
+                                                           float2* __restrict__ out,
+                                                           int64_t nsamp, int32_t nchan,
+                                                           int32_t tiles_c) {
+  __shared__ float2 tile[64][65];
+  const int64_t bid = blockIdx.x;
+  const int c0 = (int)(bid % tiles_c) * 64;
+  const int64_t t0 = (bid / tiles_c) * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < 64; i += 4) {
@@ -40,17 +101,21 @@ __global__ __launch_bounds__(256) void transpose_kernel(const E* __restrict__ in
 
 int launch_transpose(const void* in, void* out, int32_t dtype, int64_t nsamp, int32_t nchan,
                      void* stream) {
-  const int64_t tiles_c = (nchan + 63) / 64, tiles_t = (nsamp + 63) / 64;
-  const int64_t n = tiles_c * tiles_t;
-  if (n <= 0 || n > 0x7fffffffLL) return (int)hipErrorInvalidValue;
   hipStream_t st = (hipStream_t)stream;
-  if (dtype == CDD_CI8)
-    hipLaunchKernelGGL(transpose_kernel<unsigned short>, dim3((unsigned)n), dim3(256), 0, st,
+  if (dtype == CDD_CI8) {
+    const int64_t tiles_c = (nchan + 127) / 128, tiles_t = (nsamp + 63) / 64;
+    const int64_t n = tiles_c * tiles_t;
+    if (n <= 0 || n > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(transpose_i8_kernel, dim3((unsigned)n), dim3(256), 0, st,
                        (const unsigned short*)in, (unsigned short*)out, nsamp, nchan,
-                       (int32_t)tiles_c);
-  else
-    hipLaunchKernelGGL(transpose_kernel<float2>, dim3((unsigned)n), dim3(256), 0, st,
+                       (int32_t)tiles_c, (int32_t)(((uintptr_t)in & 7u) == 0));
+  } else {
+    const int64_t tiles_c = (nchan + 63) / 64, tiles_t = (nsamp + 63) / 64;
+    const int64_t n = tiles_c * tiles_t;
+    if (n <= 0 || n > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(transpose_c8_kernel, dim3((unsigned)n), dim3(256), 0, st,
                        (const float2*)in, (float2*)out, nsamp, nchan, (int32_t)tiles_c);
+  }
   return (int)hipGetLastError();
 }
 
@@ -83,38 +148,66 @@ int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream
 }
 
 // ---------------------------------------------------------------------------
-// I[u] = sum over channels c = 0, 1, ... with u + d_c < T_int of P_c[u + d_c]
-// (fixed order, no atomics), cov[u] = number of terms.  grid.y = DM trial.
+// I[u] = sum over channels c with u + d_c < T_int of P_c[u + d_c], cov[u] =
+// number of terms.  A workgroup covers 64 consecutive u; its G waves each sum
+// a contiguous channel range in ascending order, and the G partial sums are
+// added in ascending wave order -- a fixed order, no atomics, so results do
+// not depend on scheduling.  grid.y = DM trial.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void dsum_kernel(const float* __restrict__ P,
-                                                   const int32_t* __restrict__ d,
-                                                   float* __restrict__ I, int32_t* __restrict__ cov,
-                                                   int32_t nchan, int64_t t_int,
-                                                   int64_t out_stride) {
+template <int G>
+__global__ __launch_bounds__(64 * G) void dsum_kernel(const float* __restrict__ P,
+                                                      const int32_t* __restrict__ d,
+                                                      float* __restrict__ I,
+                                                      int32_t* __restrict__ cov, int32_t nchan,
+                                                      int64_t t_int, int64_t out_stride) {
+  __shared__ float ps[G][64];
+  __shared__ int32_t pn[G][64];
   const int i = blockIdx.y;
-  const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (u >= t_int) return;
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t u = (int64_t)blockIdx.x * 64 + lane;
   const float* Pi = P + (int64_t)i * nchan * t_int;
   const int32_t* di = d + (int64_t)i * nchan;
+  const int per = (nchan + G - 1) / G;
+  const int c_lo = g * per, c_hi = min(nchan, c_lo + per);
   float acc = 0.f;
   int32_t n = 0;
-  for (int c = 0; c < nchan; ++c) {
-    const int64_t src = u + di[c];
-    if (src < t_int) {
-      acc += Pi[(int64_t)c * t_int + src];
-      ++n;
+  if (u < t_int) {
+    for (int c = c_lo; c < c_hi; ++c) {
+      const int64_t src = u + di[c];
+      if (src < t_int) {
+        acc += Pi[(int64_t)c * t_int + src];
+        ++n;
+      }
     }
   }
-  I[(int64_t)i * out_stride + u] = acc;
-  if (cov) cov[(int64_t)i * out_stride + u] = n;
+  ps[g][lane] = acc;
+  pn[g][lane] = n;
+  __syncthreads();
+  if (g == 0 && u < t_int) {
+    float s = ps[0][lane];
+    int32_t m = pn[0][lane];
+#pragma unroll
+    for (int k = 1; k < G; ++k) {
+      s += ps[k][lane];
+      m += pn[k][lane];
+    }
+    I[(int64_t)i * out_stride + u] = s;
+    if (cov) cov[(int64_t)i * out_stride + u] = m;
+  }
 }
 
 int launch_dsum(const BeamPlan& p, int ndm, const float* P, const int32_t* d, float* I,
                 int32_t* cov, int64_t out_stride, void* stream) {
-  const int64_t nb = (p.t_int + 255) / 256;
-  if (nb <= 0 || nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(dsum_kernel, dim3((unsigned)nb, (unsigned)ndm), dim3(256), 0,
-                     (hipStream_t)stream, P, d, I, cov, p.nchan, p.t_int, out_stride);
+  const int64_t nb = (p.t_int + 63) / 64;
+  if (nb <= 0 || nb > 0x7fffffffLL || ndm < 1 || ndm > 65535) return (int)hipErrorInvalidValue;
+  dim3 grid((unsigned)nb, (unsigned)ndm);
+  hipStream_t st = (hipStream_t)stream;
+  if (p.nchan >= 64)
+    hipLaunchKernelGGL(dsum_kernel<8>, grid, dim3(512), 0, st, P, d, I, cov, p.nchan, p.t_int,
+                       out_stride);
+  else
+    hipLaunchKernelGGL(dsum_kernel<1>, grid, dim3(64), 0, st, P, d, I, cov, p.nchan, p.t_int,
+                       out_stride);
   return (int)hipGetLastError();
 }
 

@@ -22,6 +22,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -155,9 +156,13 @@ struct Dft {
 // ---------------------------------------------------------------------------
 // Schedules: threads per workgroup and forward radix order per length
 // ---------------------------------------------------------------------------
-template <int N_, int T_, int A, int B, int C, int D>
+template <int N_, int T_, int A, int B, int C, int D, bool SPLIT_ = true, bool PF_ = false,
+          int MINB_ = 1>
 struct Sched {
   static constexpr int N = N_, T = T_, E = N_ / T_;
+  static constexpr bool SPLIT = SPLIT_;  // exchange real and imaginary halves in turn
+  static constexpr bool PF = PF_;        // load a pass's twiddles before its exchange
+  static constexpr int MINB = MINB_;     // waves per SIMD the register budget targets
   static constexpr int NP = (A > 1) + (B > 1) + (C > 1) + (D > 1);
   static constexpr int rad_f(int p) { return p == 0 ? A : p == 1 ? B : p == 2 ? C : D; }
   static constexpr int rad_i(int q) { return rad_f(NP - 1 - q); }
@@ -183,78 +188,124 @@ struct Sched {
     return o;
   }
   static constexpr int tw_total() { return tw_i(NP); }
-  static constexpr int lds_floats() { return N + N / 16; }
+  static constexpr int lds_floats() { return (SPLIT ? 1 : 2) * (N + N / 16); }
 };
 
-template <int N>
+// Schedules per length; variant 0 is the default, others are autotuner
+// candidates.
+template <int N, int V>
 struct SchedFor;
-template <> struct SchedFor<256> { using type = Sched<256, 64, 4, 4, 4, 4>; };
-template <> struct SchedFor<512> { using type = Sched<512, 64, 8, 8, 8, 1>; };
-template <> struct SchedFor<1024> { using type = Sched<1024, 64, 16, 16, 4, 1>; };
-template <> struct SchedFor<2048> { using type = Sched<2048, 128, 16, 16, 8, 1>; };
-template <> struct SchedFor<4096> { using type = Sched<4096, 256, 16, 16, 16, 1>; };
-template <> struct SchedFor<8192> { using type = Sched<8192, 256, 16, 16, 32, 1>; };
-template <> struct SchedFor<16384> { using type = Sched<16384, 512, 16, 32, 32, 1>; };
+template <> struct SchedFor<256, 0> { using type = Sched<256, 64, 4, 4, 4, 4>; };
+template <> struct SchedFor<512, 0> { using type = Sched<512, 64, 8, 8, 8, 1>; };
+template <> struct SchedFor<1024, 0> { using type = Sched<1024, 64, 16, 16, 4, 1>; };
+template <> struct SchedFor<2048, 0> { using type = Sched<2048, 128, 16, 16, 8, 1>; };
+template <> struct SchedFor<4096, 0> { using type = Sched<4096, 256, 16, 16, 16, 1, true, false, 3>; };
+template <> struct SchedFor<4096, 1> { using type = Sched<4096, 256, 16, 16, 16, 1, false, false, 2>; };
+template <> struct SchedFor<8192, 0> { using type = Sched<8192, 512, 16, 16, 16, 2, true, false, 4>; };
+template <> struct SchedFor<8192, 1> { using type = Sched<8192, 512, 16, 16, 16, 2, false, false, 4>; };
+template <> struct SchedFor<8192, 2> { using type = Sched<8192, 512, 16, 16, 16, 2, false, false, 3>; };
+template <> struct SchedFor<8192, 3> { using type = Sched<8192, 512, 16, 16, 16, 2, true, true, 4>; };
+template <> struct SchedFor<8192, 4> { using type = Sched<8192, 256, 16, 16, 32, 1, false, false, 2>; };
+template <> struct SchedFor<16384, 0> { using type = Sched<16384, 1024, 16, 16, 16, 4, true, false, 4>; };
+template <> struct SchedFor<16384, 1> { using type = Sched<16384, 512, 16, 32, 32, 1, false, false, 2>; };
+constexpr int kVariants[] = {1, 1, 1, 1, 2, 5, 2};  // per log2(N) - 8
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
 // ---------------------------------------------------------------------------
 // Stockham pass pieces
 // ---------------------------------------------------------------------------
-// Butterflies of one pass (radix R, span NS): twiddle then DFT_R in place.
+// Twiddles of one pass (radix R, span NS) for this thread's butterflies,
+// loaded ahead of the exchange that precedes the pass.
+template <class S, int R, int NS, int TWOFF>
+struct PassTw {
+  static constexpr int BPT = S::N / (R * S::T);
+  static constexpr int CNT = NS > 1 ? BPT * (R - 1) : 1;
+  float2 w[CNT];
+  __device__ __forceinline__ void load(const float2* __restrict__ tw, int t) {
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int b = 0; b < BPT; ++b) {
+        const int k = (t + S::T * b) & (NS - 1);
+        const float2* row = tw + TWOFF + k * R;
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[b * (R - 1) + r - 1] = row[r];
+      }
+    }
+  }
+};
+
+// Butterflies of one pass: twiddle then DFT_R in place.
 template <class S, int R, int NS, int DIR, int TWOFF>
-__device__ __forceinline__ void butterflies(float2* v, const float2* __restrict__ tw, int t) {
+__device__ __forceinline__ void butterflies(float2* v, const PassTw<S, R, NS, TWOFF>& pt) {
   constexpr int BPT = S::N / (R * S::T);
   static_assert(BPT * R * S::T == S::N, "schedule does not tile N");
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     float2* w = v + b * R;
     if constexpr (NS > 1) {
-      const int j = t + S::T * b;
-      const int k = j & (NS - 1);
-      const float2* row = tw + TWOFF + k * R;
 #pragma unroll
-      for (int r = 1; r < R; ++r) w[r] = cmul(w[r], row[r]);
+      for (int r = 1; r < R; ++r) w[r] = cmul(w[r], pt.w[b * (R - 1) + r - 1]);
     }
     Dft<R, DIR>::run(w);
   }
 }
 
 // Move the outputs of a pass (radix RP, span NSP) to the input layout of the
-// next pass (radix RN) through LDS, real parts first, then imaginary parts.
+// next pass (radix RN) through LDS: whole complex values, or real parts then
+// imaginary parts (half the LDS, twice the barriers).
 template <class S, int RP, int NSP, int RN>
 __device__ __forceinline__ void exchange(float2* v, float* lds, int t) {
   constexpr int N = S::N, T = S::T;
   constexpr int BP = N / (RP * T), BN = N / (RN * T);
-  __syncthreads();
+  if constexpr (!S::SPLIT) {
+    float2* l2 = (float2*)lds;
+    __syncthreads();
 #pragma unroll
-  for (int b = 0; b < BP; ++b) {
-    const int j = t + T * b;
-    const int base = (j / NSP) * NSP * RP + (j % NSP);
+    for (int b = 0; b < BP; ++b) {
+      const int j = t + T * b;
+      const int base = (j / NSP) * NSP * RP + (j % NSP);
 #pragma unroll
-    for (int r = 0; r < RP; ++r) lds[lpad(base + r * NSP)] = v[b * RP + r].x;
-  }
-  __syncthreads();
+      for (int r = 0; r < RP; ++r) l2[lpad(base + r * NSP)] = v[b * RP + r];
+    }
+    __syncthreads();
 #pragma unroll
-  for (int b = 0; b < BN; ++b) {
-    const int j = t + T * b;
+    for (int b = 0; b < BN; ++b) {
+      const int j = t + T * b;
 #pragma unroll
-    for (int r = 0; r < RN; ++r) v[b * RN + r].x = lds[lpad(j + r * (N / RN))];
-  }
-  __syncthreads();
+      for (int r = 0; r < RN; ++r) v[b * RN + r] = l2[lpad(j + r * (N / RN))];
+    }
+  } else {
+    __syncthreads();
 #pragma unroll
-  for (int b = 0; b < BP; ++b) {
-    const int j = t + T * b;
-    const int base = (j / NSP) * NSP * RP + (j % NSP);
+    for (int b = 0; b < BP; ++b) {
+      const int j = t + T * b;
+      const int base = (j / NSP) * NSP * RP + (j % NSP);
 #pragma unroll
-    for (int r = 0; r < RP; ++r) lds[lpad(base + r * NSP)] = v[b * RP + r].y;
-  }
-  __syncthreads();
+      for (int r = 0; r < RP; ++r) lds[lpad(base + r * NSP)] = v[b * RP + r].x;
+    }
+    __syncthreads();
 #pragma unroll
-  for (int b = 0; b < BN; ++b) {
-    const int j = t + T * b;
+    for (int b = 0; b < BN; ++b) {
+      const int j = t + T * b;
 #pragma unroll
-    for (int r = 0; r < RN; ++r) v[b * RN + r].y = lds[lpad(j + r * (N / RN))];
+      for (int r = 0; r < RN; ++r) v[b * RN + r].x = lds[lpad(j + r * (N / RN))];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BP; ++b) {
+      const int j = t + T * b;
+      const int base = (j / NSP) * NSP * RP + (j % NSP);
+#pragma unroll
+      for (int r = 0; r < RP; ++r) lds[lpad(base + r * NSP)] = v[b * RP + r].y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BN; ++b) {
+      const int j = t + T * b;
+#pragma unroll
+      for (int r = 0; r < RN; ++r) v[b * RN + r].y = lds[lpad(j + r * (N / RN))];
+    }
   }
 }
 
@@ -263,8 +314,11 @@ __device__ __forceinline__ void fft_forward(float2* v, float* lds, const float2*
                                             int t) {
   sfor<0, S::NP>([&](auto P) {
     constexpr int p = decltype(P)::value;
+    PassTw<S, S::rad_f(p), S::ns_f(p), S::tw_f(p)> pt;
+    if constexpr (S::PF) pt.load(tw, t);
     if constexpr (p > 0) exchange<S, S::rad_f(p - 1), S::ns_f(p - 1), S::rad_f(p)>(v, lds, t);
-    butterflies<S, S::rad_f(p), S::ns_f(p), -1, S::tw_f(p)>(v, tw, t);
+    if constexpr (!S::PF) pt.load(tw, t);
+    butterflies<S, S::rad_f(p), S::ns_f(p), -1, S::tw_f(p)>(v, pt);
   });
 }
 
@@ -273,8 +327,11 @@ __device__ __forceinline__ void fft_inverse(float2* v, float* lds, const float2*
                                             int t) {
   sfor<0, S::NP>([&](auto Q) {
     constexpr int q = decltype(Q)::value;
+    PassTw<S, S::rad_i(q), S::ns_i(q), S::tw_i(q)> pt;
+    if constexpr (S::PF) pt.load(tw, t);
     if constexpr (q > 0) exchange<S, S::rad_i(q - 1), S::ns_i(q - 1), S::rad_i(q)>(v, lds, t);
-    butterflies<S, S::rad_i(q), S::ns_i(q), +1, S::tw_i(q)>(v, tw, t);
+    if constexpr (!S::PF) pt.load(tw, t);
+    butterflies<S, S::rad_i(q), S::ns_i(q), +1, S::tw_i(q)>(v, pt);
   });
 }
 
@@ -287,36 +344,86 @@ struct BlockArgs {
   float2* vout;         // [nchan][nsamp] or null (single DM only)
   const float2* tw;     // twiddle tables
   int64_t nsamp, t_int, nblocks;
-  int32_t nchan, M, nfront, n_int, phase_mode, pad0;
+  int32_t nchan, M, nfront, n_int, phase_mode, exact_div;
   double f_lo, df, dconst;
   DmTile dms;
 };
 
-// Bin i of the forward transform holds the spectrum at offset s*df/N from
-// the channel centre, s = i (i < N/2) or i - N.  Multiply by exp(-2 pi i q)/N.
+// cos and sin of 2 pi k / 64 for the 64 octant-of-an-octant rotations.
+struct RotTable {
+  float c[64], s[64];
+};
+constexpr RotTable make_rot() {
+  RotTable t{};
+  for (int i = 0; i < 64; ++i) {
+    t.c[i] = (float)ct_cos2pi(i, 64);
+    t.s[i] = (float)ct_sin2pi(i, 64);
+  }
+  return t;
+}
+__constant__ RotTable kRot = make_rot();
+
+// exp(-2 pi i r) for r in [-1/2, 1/2] turns given in FP64: r = (k + d)/64
+// with k integer and |d| <= 1/2; exp(-2 pi i k/64) from the table, the rest
+// from short Taylor series of cos and sin of x = 2 pi d / 64 (|x| <= pi/64,
+// truncation below 2e-11).
+__device__ __forceinline__ float2 expi_neg_turns(double r) {
+  const double r64 = r * 64.0;
+  const double k = rint(r64);
+  const float x = (float)(r64 - k) * (float)(2.0 * kPi / 64.0);
+  const int ki = (int)k & 63;
+  const float x2 = x * x;
+  const float cs = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24.0f));
+  const float sn = x * (1.0f + x2 * (-1.0f / 6.0f + x2 * (1.0f / 120.0f)));
+  const float C = kRot.c[ki], Sn = kRot.s[ki];
+  // cos(a+b) - i sin(a+b)
+  return make_float2(C * cs - Sn * sn, -(Sn * cs + C * sn));
+}
+
+// Bin i of the forward transform holds the spectrum at offset f = s*df/N from
+// the channel centre fc, s = i (i < N/2) or i - N.  Multiply it by
+// exp(-2 pi i q)/N with q = D*DM*f^2/(fc^2 (fc + f)) turns (Eq. 3), evaluated
+// in FP64 as q = B s^2 / (1 + x), B = D*DM*(df/N)^2/fc^3, x = s*(df/N)/fc.
+// When the channel is narrow enough that q*x^3 stays below 1e-9 turns, 1/(1+x)
+// is replaced by 1 - x + x^2 (no division); otherwise the division is exact.
+// The phase is reduced to [-1/2, 1/2] turns before the FP32 rotation.
 template <class S>
 __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, const BlockArgs& a,
                                             int t) {
   constexpr int N = S::N, R = S::rad_f(S::NP - 1), BPT = N / (R * S::T);
   const float inv_n = 1.0f / (float)N;
   if (a.phase_mode == CDD_PHASE_FP64_REDUCED) {
-    const double A = a.dconst * dm / (fc * fc);
     const double dfn = a.df / (double)N;
+    const double B = a.dconst * dm * dfn * dfn / (fc * fc * fc);
+    const double beta = dfn / fc;
+    if (a.exact_div == 0) {
 #pragma unroll
-    for (int b = 0; b < BPT; ++b) {
+      for (int b = 0; b < BPT; ++b) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = t + S::T * b + r * (N / R);
-        const int s = i < N / 2 ? i : i - N;
-        const double f = (double)s * dfn;
-        const double q = A * (f * f) / (fc + f);
-        const float red = (float)(q - rint(q));
-        float sn, cs;
-        sincospif(2.0f * red, &sn, &cs);
-        v[b * R + r] = cmul(v[b * R + r], make_float2(cs * inv_n, -sn * inv_n));
+        for (int r = 0; r < R; ++r) {
+          const int i = t + S::T * b + r * (N / R);
+          const double sd = (double)(i < N / 2 ? i : i - N);
+          const double x = beta * sd;
+          const double q = (B * (sd * sd)) * fma(x, x, 1.0 - x);
+          const float2 h = expi_neg_turns(q - rint(q));
+          v[b * R + r] = cmul(v[b * R + r], make_float2(h.x * inv_n, h.y * inv_n));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < BPT; ++b) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = t + S::T * b + r * (N / R);
+          const double sd = (double)(i < N / 2 ? i : i - N);
+          const double q = (B * (sd * sd)) / fma(beta, sd, 1.0);
+          const float2 h = expi_neg_turns(q - rint(q));
+          v[b * R + r] = cmul(v[b * R + r], make_float2(h.x * inv_n, h.y * inv_n));
+        }
       }
     }
   } else {
+    // all-FP32 phase (precision study): q straight from Eq. 3 in FP32
     const float fcf = (float)fc;
     const float Af = (float)(a.dconst * dm) / (fcf * fcf);
     const float dfn = (float)a.df / (float)N;
@@ -403,7 +510,7 @@ __device__ __forceinline__ void epilogue(const float2* v, float* lds, const Bloc
 }
 
 template <class S, int DT, bool MULTI>
-__global__ __launch_bounds__(S::T) void block_kernel(const BlockArgs a) {
+__global__ __launch_bounds__(S::T, MULTI ? (S::MINB + 1) / 2 : S::MINB) void block_kernel(const BlockArgs a) {
   __shared__ float lds[S::lds_floats()];
   const int t = threadIdx.x;
   const int64_t item = blockIdx.x;
@@ -432,7 +539,8 @@ __global__ __launch_bounds__(S::T) void block_kernel(const BlockArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Host side: FP64 twiddle tables (cached per device and length) and launch
+// Host side: FP64 twiddle tables (cached per device, length and schedule)
+// and launch
 // ---------------------------------------------------------------------------
 template <class S>
 static std::vector<float2> make_twiddles() {
@@ -457,15 +565,15 @@ static std::vector<float2> make_twiddles() {
 }
 
 static std::mutex g_tw_mu;
-static std::map<std::pair<int, int>, float2*> g_tw;  // (device, N) -> table
+static std::map<std::tuple<int, int, int>, float2*> g_tw;  // (device, N, variant)
 
-template <class S>
+template <class S, int V>
 static int twiddles_for(const float2** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return (int)e;
   std::lock_guard<std::mutex> lk(g_tw_mu);
-  auto key = std::make_pair(dev, S::N);
+  auto key = std::make_tuple(dev, S::N, V);
   auto it = g_tw.find(key);
   if (it != g_tw.end()) {
     *out = it->second;
@@ -485,11 +593,24 @@ static int twiddles_for(const float2** out) {
   return 0;
 }
 
-template <class S>
+// Whether 1/(1+x) needs the exact division: the series 1 - x + x^2 is used
+// when its truncation, q*x^3/(1-x), stays below 1e-9 turns over the beam's
+// channels and DMs (x = f/fc, |f| <= df/2).
+static int needs_exact_division(const BeamPlan& p, const DmTile& dms) {
+  const double fmin = p.f_lo + 0.5 * p.df;
+  const double xm = 0.5 * p.df / fmin;
+  double dmax = 0;
+  for (int i = 0; i < dms.ndm; ++i) dmax = std::fmax(dmax, std::fabs(dms.dm[i]));
+  const double qmax = p.dconst * dmax * 0.25 * p.df * p.df / (fmin * fmin * (fmin - 0.5 * p.df));
+  return qmax * xm * xm * xm / (1.0 - xm) > 1e-9 ? 1 : 0;
+}
+
+template <int N, int V>
 static int launch_block_t(const BeamPlan& p, const void* xt, const DmTile& dms, float* P,
                           void* vout, void* stream) {
+  using S = typename SchedFor<N, V>::type;
   BlockArgs a{};
-  int err = twiddles_for<S>(&a.tw);
+  int err = twiddles_for<S, V>(&a.tw);
   if (err) return err;
   a.x = xt;
   a.P = P;
@@ -502,6 +623,7 @@ static int launch_block_t(const BeamPlan& p, const void* xt, const DmTile& dms, 
   a.nfront = p.nfront;
   a.n_int = p.n_int;
   a.phase_mode = p.phase_mode;
+  a.exact_div = needs_exact_division(p, dms);
   a.f_lo = p.f_lo;
   a.df = p.df;
   a.dconst = p.dconst;
@@ -521,22 +643,41 @@ static int launch_block_t(const BeamPlan& p, const void* xt, const DmTile& dms, 
   return (int)hipGetLastError();
 }
 
-bool block_supported(int N) {
-  return N == 256 || N == 512 || N == 1024 || N == 2048 || N == 4096 || N == 8192 ||
-         N == 16384;
+static int log2i(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
 }
+
+bool block_supported(int N) {
+  return N >= 256 && N <= 16384 && (N & (N - 1)) == 0;
+}
+
+int block_variants(int N) { return block_supported(N) ? kVariants[log2i(N) - 8] : 0; }
 
 int launch_block(const BeamPlan& p, const void* xt, const DmTile& dms, float* P, void* vout,
                  void* stream) {
   if (dms.ndm < 1 || dms.ndm > kMaxDmTile) return (int)hipErrorInvalidValue;
+  const int v = p.variant;
   switch (p.N) {
-    case 256: return launch_block_t<SchedFor<256>::type>(p, xt, dms, P, vout, stream);
-    case 512: return launch_block_t<SchedFor<512>::type>(p, xt, dms, P, vout, stream);
-    case 1024: return launch_block_t<SchedFor<1024>::type>(p, xt, dms, P, vout, stream);
-    case 2048: return launch_block_t<SchedFor<2048>::type>(p, xt, dms, P, vout, stream);
-    case 4096: return launch_block_t<SchedFor<4096>::type>(p, xt, dms, P, vout, stream);
-    case 8192: return launch_block_t<SchedFor<8192>::type>(p, xt, dms, P, vout, stream);
-    case 16384: return launch_block_t<SchedFor<16384>::type>(p, xt, dms, P, vout, stream);
+    case 256: return launch_block_t<256, 0>(p, xt, dms, P, vout, stream);
+    case 512: return launch_block_t<512, 0>(p, xt, dms, P, vout, stream);
+    case 1024: return launch_block_t<1024, 0>(p, xt, dms, P, vout, stream);
+    case 2048: return launch_block_t<2048, 0>(p, xt, dms, P, vout, stream);
+    case 4096:
+      return v == 1 ? launch_block_t<4096, 1>(p, xt, dms, P, vout, stream)
+                    : launch_block_t<4096, 0>(p, xt, dms, P, vout, stream);
+    case 8192:
+      switch (v) {
+        case 1: return launch_block_t<8192, 1>(p, xt, dms, P, vout, stream);
+        case 2: return launch_block_t<8192, 2>(p, xt, dms, P, vout, stream);
+        case 3: return launch_block_t<8192, 3>(p, xt, dms, P, vout, stream);
+        case 4: return launch_block_t<8192, 4>(p, xt, dms, P, vout, stream);
+        default: return launch_block_t<8192, 0>(p, xt, dms, P, vout, stream);
+      }
+    case 16384:
+      return v == 1 ? launch_block_t<16384, 1>(p, xt, dms, P, vout, stream)
+                    : launch_block_t<16384, 0>(p, xt, dms, P, vout, stream);
   }
   return (int)hipErrorInvalidValue;
 }

@@ -27,6 +27,7 @@ struct BeamPlan {
   double f_centre = 0, bw = 0, df = 0, f_lo = 0, dconst = kDefaultD;
   int32_t n_int = 1;
   int32_t phase_mode = CDD_PHASE_FP64_REDUCED;
+  int32_t variant = 0;  // block-kernel schedule (autotuner choice)
   std::vector<double> dms;
   int32_t N = 0, L = 0, nfront = 0, M = 0;
   int32_t front = 0, back = 0;
@@ -70,6 +71,7 @@ int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream
 int launch_dsum(const BeamPlan& p, int ndm, const float* P, const int32_t* d,
                 float* I, int32_t* cov, int64_t out_stride, void* stream);
 bool block_supported(int N);
+int block_variants(int N);  // number of schedules compiled for N
 
 // Stage timing (cdd_profile.hip): no-ops unless profiling is enabled.
 bool profiling();

@@ -97,6 +97,7 @@ cdd_status make_plan(int32_t dtype, int64_t nsamp, int32_t nchan,
     if (opts->phase_mode != CDD_PHASE_FP64_REDUCED && opts->phase_mode != CDD_PHASE_FP32)
       return fail(CDD_EINVAL, "unknown phase_mode %d", opts->phase_mode);
     p.phase_mode = opts->phase_mode;
+    p.variant = opts->kernel_variant;
   }
 
   // Reach of the impulse response and widest dispersion, over channels/DMs.
@@ -160,6 +161,8 @@ cdd_status make_plan(int32_t dtype, int64_t nsamp, int32_t nchan,
     p.L = (int32_t)L;
     p.nfront = p.front + (p.L - p.front - p.back) / 2;
   }
+  if (p.variant < 0 || (block_supported(p.N) && p.variant >= block_variants(p.N)))
+    return fail(CDD_EINVAL, "kernel_variant %d not available for fft_len %d", p.variant, p.N);
   p.M = p.N - p.L;
   p.nblocks = (nsamp + p.M - 1) / p.M;
   p.t_int = nsamp / n_int;
@@ -217,6 +220,8 @@ const char* cdd_status_str(cdd_status s) {
 }
 
 int32_t cdd_abi_version(void) { return CDD_ABI_VERSION; }
+
+int32_t cdd_kernel_variants(int32_t fft_len) { return cdd::block_variants(fft_len); }
 
 cdd_status cdd_query(int32_t dtype, int64_t nsamp, int32_t nchan,
                      double f_centre_mhz, double bw_mhz, double dm,
