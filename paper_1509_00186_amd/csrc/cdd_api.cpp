@@ -47,7 +47,18 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
   if ((e = launch_delays(p, tile, d, stream))) return device_fail("delay launch", e);
   if ((e = stage_end(kStageDelays, stream, tok))) return device_fail("event record", e);
   if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
-  if ((e = launch_block(p, xt, tile, P, volt_out, stream))) return device_fail("block kernel launch", e);
+  if (block_supported(p.N)) {
+    if ((e = launch_block(p, xt, tile, P, volt_out, stream)))
+      return device_fail("block kernel launch", e);
+  } else {
+    // long transforms: one DM trial at a time through the four-step kernels
+    for (int i = 0; i < tile.ndm; ++i) {
+      if ((e = launch_large(p, xt, tile.dm[i], ws + lay.s_off, (float*)(ws + lay.pb_off),
+                            P + (int64_t)i * p.nchan * p.t_int, tile.ndm == 1 ? volt_out : nullptr,
+                            stream)))
+        return device_fail("long-transform launch", e);
+    }
+  }
   if ((e = stage_end(kStageBlock, stream, tok))) return device_fail("event record", e);
   if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
   if ((e = launch_dsum(p, tile.ndm, P, d, intensity, coverage, out_stride, stream)))
@@ -78,7 +89,7 @@ cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp, in
     cdd_status s = make_plan(dtype, nsamp, nchan, f_centre_mhz, bw_mhz, &dm, 1, fft_len, n_int,
                              opts, &p);
     if (s != CDD_OK) return s;
-    if (!block_supported(p.N))
+    if (!block_supported(p.N) && !large_supported(p.N))
       return fail(CDD_ENOTSUP, "fft_len %d is not supported by this build", p.N);
     WsLayout lay = ws_layout(p, 1, true);
     if (!workspace || ws_bytes < lay.total)
@@ -120,7 +131,7 @@ cdd_status cdd_plan_create(const cdd_beam* beams, int32_t nbeam, const cdd_opts*
         delete pl;
         return fail(s, "beam %d: %s", b, msg.c_str());
       }
-      if (!block_supported(p.N)) {
+      if (!block_supported(p.N) && !large_supported(p.N)) {
         delete pl;
         return fail(CDD_ENOTSUP, "beam %d: fft_len %d is not supported", b, p.N);
       }

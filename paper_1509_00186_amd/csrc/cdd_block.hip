@@ -22,174 +22,16 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <type_traits>
 #include <utility>
 #include <vector>
 
+#include "cdd_fft.h"
 #include "cdd_internal.h"
 
 namespace cdd {
-
-// ---------------------------------------------------------------------------
-// Compile-time helpers
-// ---------------------------------------------------------------------------
-template <int B, int E, class F>
-__device__ __forceinline__ void sfor(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    sfor<B + 1, E>(f);
-  }
-}
-
-constexpr double kPi = 3.141592653589793238462643383279502884;
-constexpr double ct_sin(double x) {  // Taylor series, |x| <= pi
-  double term = x, sum = x;
-  for (int n = 1; n < 32; ++n) {
-    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
-    sum += term;
-  }
-  return sum;
-}
-constexpr double ct_cos(double x) {
-  double term = 1.0, sum = 1.0;
-  for (int n = 1; n < 32; ++n) {
-    term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
-    sum += term;
-  }
-  return sum;
-}
-constexpr int ct_wrap(int m, int R) {  // m mod R mapped to (-R/2, R/2]
-  int mm = ((m % R) + R) % R;
-  return 2 * mm > R ? mm - R : mm;
-}
-constexpr double ct_cos2pi(int m, int R) { return ct_cos(2.0 * kPi * ct_wrap(m, R) / R); }
-constexpr double ct_sin2pi(int m, int R) { return ct_sin(2.0 * kPi * ct_wrap(m, R) / R); }
-
-// ---------------------------------------------------------------------------
-// Complex arithmetic on float2
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// multiply by s*i, s = +1 or -1
-template <int S>
-__device__ __forceinline__ float2 mul_i(float2 a) {
-  if constexpr (S > 0) return make_float2(-a.y, a.x);
-  else return make_float2(a.y, -a.x);
-}
-// multiply by W_R^m = exp(DIR * 2 pi i m / R), constants folded
-template <int R, int M, int DIR>
-__device__ __forceinline__ float2 twc(float2 a) {
-  constexpr int m = ((M % R) + R) % R;
-  if constexpr (m == 0) {
-    return a;
-  } else if constexpr (4 * m == R) {
-    return mul_i<DIR>(a);
-  } else if constexpr (2 * m == R) {
-    return make_float2(-a.x, -a.y);
-  } else if constexpr (4 * m == 3 * R) {
-    return mul_i<-DIR>(a);
-  } else {
-    constexpr float c = (float)ct_cos2pi(m, R);
-    constexpr float s = (float)(DIR * ct_sin2pi(m, R));
-    return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
-  }
-}
-
-// In-register DFT of R points, natural order in and out.
-template <int R, int DIR>
-struct Dft;
-template <int DIR>
-struct Dft<1, DIR> {
-  static __device__ __forceinline__ void run(float2*) {}
-};
-template <int DIR>
-struct Dft<2, DIR> {
-  static __device__ __forceinline__ void run(float2* v) {
-    float2 a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
-  }
-};
-template <int DIR>
-struct Dft<4, DIR> {
-  static __device__ __forceinline__ void run(float2* v) {
-    float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-    float2 t2 = cadd(v[1], v[3]), t3 = mul_i<DIR>(csub(v[1], v[3]));
-    v[0] = cadd(t0, t2);
-    v[2] = csub(t0, t2);
-    v[1] = cadd(t1, t3);
-    v[3] = csub(t1, t3);
-  }
-};
-// R = 4 Q: x[Q n1 + n2] -> DFT_4 over n1, twiddle W_R^(n2 k1), DFT_Q over n2,
-// output X[k1 + 4 k2].
-template <int R, int DIR>
-struct Dft {
-  static __device__ __forceinline__ void run(float2* v) {
-    constexpr int Q = R / 4;
-    float2 y[R];
-    sfor<0, Q>([&](auto N2) {
-      constexpr int n2 = decltype(N2)::value;
-      float2 t[4] = {v[n2], v[Q + n2], v[2 * Q + n2], v[3 * Q + n2]};
-      Dft<4, DIR>::run(t);
-      y[n2 * 4 + 0] = t[0];
-      y[n2 * 4 + 1] = twc<R, n2 * 1, DIR>(t[1]);
-      y[n2 * 4 + 2] = twc<R, n2 * 2, DIR>(t[2]);
-      y[n2 * 4 + 3] = twc<R, n2 * 3, DIR>(t[3]);
-    });
-    sfor<0, 4>([&](auto K1) {
-      constexpr int k1 = decltype(K1)::value;
-      float2 s[Q];
-#pragma unroll
-      for (int n2 = 0; n2 < Q; ++n2) s[n2] = y[n2 * 4 + k1];
-      Dft<Q, DIR>::run(s);
-#pragma unroll
-      for (int k2 = 0; k2 < Q; ++k2) v[k1 + 4 * k2] = s[k2];
-    });
-  }
-};
-
-// ---------------------------------------------------------------------------
-// Schedules: threads per workgroup and forward radix order per length
-// ---------------------------------------------------------------------------
-template <int N_, int T_, int A, int B, int C, int D, bool SPLIT_ = true, bool PF_ = false,
-          int MINB_ = 1>
-struct Sched {
-  static constexpr int N = N_, T = T_, E = N_ / T_;
-  static constexpr bool SPLIT = SPLIT_;  // exchange real and imaginary halves in turn
-  static constexpr bool PF = PF_;        // load a pass's twiddles before its exchange
-  static constexpr int MINB = MINB_;     // waves per SIMD the register budget targets
-  static constexpr int NP = (A > 1) + (B > 1) + (C > 1) + (D > 1);
-  static constexpr int rad_f(int p) { return p == 0 ? A : p == 1 ? B : p == 2 ? C : D; }
-  static constexpr int rad_i(int q) { return rad_f(NP - 1 - q); }
-  static constexpr int ns_f(int p) {
-    int s = 1;
-    for (int i = 0; i < p; ++i) s *= rad_f(i);
-    return s;
-  }
-  static constexpr int ns_i(int q) {
-    int s = 1;
-    for (int i = 0; i < q; ++i) s *= rad_i(i);
-    return s;
-  }
-  // twiddle rows of R entries for every pass after the first
-  static constexpr int tw_f(int p) {
-    int o = 0;
-    for (int i = 1; i < p; ++i) o += ns_f(i) * rad_f(i);
-    return o;
-  }
-  static constexpr int tw_i(int q) {
-    int o = tw_f(NP);
-    for (int i = 1; i < q; ++i) o += ns_i(i) * rad_i(i);
-    return o;
-  }
-  static constexpr int tw_total() { return tw_i(NP); }
-  static constexpr int lds_floats() { return (SPLIT ? 1 : 2) * (N + N / 16); }
-};
 
 // Schedules per length; variant 0 is the default, others are autotuner
 // candidates.
@@ -210,131 +52,6 @@ template <> struct SchedFor<16384, 0> { using type = Sched<16384, 1024, 16, 16, 
 template <> struct SchedFor<16384, 1> { using type = Sched<16384, 512, 16, 32, 32, 1, false, false, 2>; };
 constexpr int kVariants[] = {1, 1, 1, 1, 2, 5, 2};  // per log2(N) - 8
 
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
-
-// ---------------------------------------------------------------------------
-// Stockham pass pieces
-// ---------------------------------------------------------------------------
-// Twiddles of one pass (radix R, span NS) for this thread's butterflies,
-// loaded ahead of the exchange that precedes the pass.
-template <class S, int R, int NS, int TWOFF>
-struct PassTw {
-  static constexpr int BPT = S::N / (R * S::T);
-  static constexpr int CNT = NS > 1 ? BPT * (R - 1) : 1;
-  float2 w[CNT];
-  __device__ __forceinline__ void load(const float2* __restrict__ tw, int t) {
-    if constexpr (NS > 1) {
-#pragma unroll
-      for (int b = 0; b < BPT; ++b) {
-        const int k = (t + S::T * b) & (NS - 1);
-        const float2* row = tw + TWOFF + k * R;
-#pragma unroll
-        for (int r = 1; r < R; ++r) w[b * (R - 1) + r - 1] = row[r];
-      }
-    }
-  }
-};
-
-// Butterflies of one pass: twiddle then DFT_R in place.
-template <class S, int R, int NS, int DIR, int TWOFF>
-__device__ __forceinline__ void butterflies(float2* v, const PassTw<S, R, NS, TWOFF>& pt) {
-  constexpr int BPT = S::N / (R * S::T);
-  static_assert(BPT * R * S::T == S::N, "schedule does not tile N");
-#pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    float2* w = v + b * R;
-    if constexpr (NS > 1) {
-#pragma unroll
-      for (int r = 1; r < R; ++r) w[r] = cmul(w[r], pt.w[b * (R - 1) + r - 1]);
-    }
-    Dft<R, DIR>::run(w);
-  }
-}
-
-// Move the outputs of a pass (radix RP, span NSP) to the input layout of the
-// next pass (radix RN) through LDS: whole complex values, or real parts then
-// imaginary parts (half the LDS, twice the barriers).
-template <class S, int RP, int NSP, int RN>
-__device__ __forceinline__ void exchange(float2* v, float* lds, int t) {
-  constexpr int N = S::N, T = S::T;
-  constexpr int BP = N / (RP * T), BN = N / (RN * T);
-  if constexpr (!S::SPLIT) {
-    float2* l2 = (float2*)lds;
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < BP; ++b) {
-      const int j = t + T * b;
-      const int base = (j / NSP) * NSP * RP + (j % NSP);
-#pragma unroll
-      for (int r = 0; r < RP; ++r) l2[lpad(base + r * NSP)] = v[b * RP + r];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < BN; ++b) {
-      const int j = t + T * b;
-#pragma unroll
-      for (int r = 0; r < RN; ++r) v[b * RN + r] = l2[lpad(j + r * (N / RN))];
-    }
-  } else {
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < BP; ++b) {
-      const int j = t + T * b;
-      const int base = (j / NSP) * NSP * RP + (j % NSP);
-#pragma unroll
-      for (int r = 0; r < RP; ++r) lds[lpad(base + r * NSP)] = v[b * RP + r].x;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < BN; ++b) {
-      const int j = t + T * b;
-#pragma unroll
-      for (int r = 0; r < RN; ++r) v[b * RN + r].x = lds[lpad(j + r * (N / RN))];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < BP; ++b) {
-      const int j = t + T * b;
-      const int base = (j / NSP) * NSP * RP + (j % NSP);
-#pragma unroll
-      for (int r = 0; r < RP; ++r) lds[lpad(base + r * NSP)] = v[b * RP + r].y;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < BN; ++b) {
-      const int j = t + T * b;
-#pragma unroll
-      for (int r = 0; r < RN; ++r) v[b * RN + r].y = lds[lpad(j + r * (N / RN))];
-    }
-  }
-}
-
-template <class S>
-__device__ __forceinline__ void fft_forward(float2* v, float* lds, const float2* __restrict__ tw,
-                                            int t) {
-  sfor<0, S::NP>([&](auto P) {
-    constexpr int p = decltype(P)::value;
-    PassTw<S, S::rad_f(p), S::ns_f(p), S::tw_f(p)> pt;
-    if constexpr (S::PF) pt.load(tw, t);
-    if constexpr (p > 0) exchange<S, S::rad_f(p - 1), S::ns_f(p - 1), S::rad_f(p)>(v, lds, t);
-    if constexpr (!S::PF) pt.load(tw, t);
-    butterflies<S, S::rad_f(p), S::ns_f(p), -1, S::tw_f(p)>(v, pt);
-  });
-}
-
-template <class S>
-__device__ __forceinline__ void fft_inverse(float2* v, float* lds, const float2* __restrict__ tw,
-                                            int t) {
-  sfor<0, S::NP>([&](auto Q) {
-    constexpr int q = decltype(Q)::value;
-    PassTw<S, S::rad_i(q), S::ns_i(q), S::tw_i(q)> pt;
-    if constexpr (S::PF) pt.load(tw, t);
-    if constexpr (q > 0) exchange<S, S::rad_i(q - 1), S::ns_i(q - 1), S::rad_i(q)>(v, lds, t);
-    if constexpr (!S::PF) pt.load(tw, t);
-    butterflies<S, S::rad_i(q), S::ns_i(q), +1, S::tw_i(q)>(v, pt);
-  });
-}
-
 // ---------------------------------------------------------------------------
 // Kernel
 // ---------------------------------------------------------------------------
@@ -348,37 +65,6 @@ struct BlockArgs {
   double f_lo, df, dconst;
   DmTile dms;
 };
-
-// cos and sin of 2 pi k / 64 for the 64 octant-of-an-octant rotations.
-struct RotTable {
-  float c[64], s[64];
-};
-constexpr RotTable make_rot() {
-  RotTable t{};
-  for (int i = 0; i < 64; ++i) {
-    t.c[i] = (float)ct_cos2pi(i, 64);
-    t.s[i] = (float)ct_sin2pi(i, 64);
-  }
-  return t;
-}
-__constant__ RotTable kRot = make_rot();
-
-// exp(-2 pi i r) for r in [-1/2, 1/2] turns given in FP64: r = (k + d)/64
-// with k integer and |d| <= 1/2; exp(-2 pi i k/64) from the table, the rest
-// from short Taylor series of cos and sin of x = 2 pi d / 64 (|x| <= pi/64,
-// truncation below 2e-11).
-__device__ __forceinline__ float2 expi_neg_turns(double r) {
-  const double r64 = r * 64.0;
-  const double k = rint(r64);
-  const float x = (float)(r64 - k) * (float)(2.0 * kPi / 64.0);
-  const int ki = (int)k & 63;
-  const float x2 = x * x;
-  const float cs = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24.0f));
-  const float sn = x * (1.0f + x2 * (-1.0f / 6.0f + x2 * (1.0f / 120.0f)));
-  const float C = kRot.c[ki], Sn = kRot.s[ki];
-  // cos(a+b) - i sin(a+b)
-  return make_float2(C * cs - Sn * sn, -(Sn * cs + C * sn));
-}
 
 // Bin i of the forward transform holds the spectrum at offset f = s*df/N from
 // the channel centre fc, s = i (i < N/2) or i - N.  Multiply it by
@@ -542,44 +228,21 @@ __global__ __launch_bounds__(S::T, MULTI ? (S::MINB + 1) / 2 : S::MINB) void blo
 // Host side: FP64 twiddle tables (cached per device, length and schedule)
 // and launch
 // ---------------------------------------------------------------------------
-template <class S>
-static std::vector<float2> make_twiddles() {
-  std::vector<float2> tw(S::tw_total() > 0 ? S::tw_total() : 1);
-  for (int p = 1; p < S::NP; ++p) {
-    const int R = S::rad_f(p), ns = S::ns_f(p), off = S::tw_f(p);
-    for (int k = 0; k < ns; ++k)
-      for (int r = 0; r < R; ++r) {
-        const double ang = -2.0 * M_PI * (double)(r * k) / (double)(ns * R);
-        tw[off + k * R + r] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-      }
-  }
-  for (int q = 1; q < S::NP; ++q) {
-    const int R = S::rad_i(q), ns = S::ns_i(q), off = S::tw_i(q);
-    for (int k = 0; k < ns; ++k)
-      for (int r = 0; r < R; ++r) {
-        const double ang = 2.0 * M_PI * (double)(r * k) / (double)(ns * R);
-        tw[off + k * R + r] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-      }
-  }
-  return tw;
-}
+static std::mutex g_tab_mu;
+static std::map<std::pair<int, std::string>, float2*> g_tab;  // (device, key)
 
-static std::mutex g_tw_mu;
-static std::map<std::tuple<int, int, int>, float2*> g_tw;  // (device, N, variant)
-
-template <class S, int V>
-static int twiddles_for(const float2** out) {
+int cached_table(const char* key, std::vector<float2> (*make)(), const float2** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return (int)e;
-  std::lock_guard<std::mutex> lk(g_tw_mu);
-  auto key = std::make_tuple(dev, S::N, V);
-  auto it = g_tw.find(key);
-  if (it != g_tw.end()) {
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  auto k = std::make_pair(dev, std::string(key));
+  auto it = g_tab.find(k);
+  if (it != g_tab.end()) {
     *out = it->second;
     return 0;
   }
-  std::vector<float2> h = make_twiddles<S>();
+  std::vector<float2> h = make();
   float2* d = nullptr;
   e = hipMalloc(&d, h.size() * sizeof(float2));
   if (e != hipSuccess) return (int)e;
@@ -588,21 +251,26 @@ static int twiddles_for(const float2** out) {
     (void)hipFree(d);
     return (int)e;
   }
-  g_tw[key] = d;
+  g_tab[k] = d;
   *out = d;
   return 0;
 }
 
 // Whether 1/(1+x) needs the exact division: the series 1 - x + x^2 is used
 // when its truncation, q*x^3/(1-x), stays below 1e-9 turns over the beam's
-// channels and DMs (x = f/fc, |f| <= df/2).
-static int needs_exact_division(const BeamPlan& p, const DmTile& dms) {
+// channels for DMs up to dm_abs_max (x = f/fc, |f| <= df/2).
+int exact_division_needed(const BeamPlan& p, double dm_abs_max) {
   const double fmin = p.f_lo + 0.5 * p.df;
   const double xm = 0.5 * p.df / fmin;
+  const double qmax =
+      p.dconst * dm_abs_max * 0.25 * p.df * p.df / (fmin * fmin * (fmin - 0.5 * p.df));
+  return qmax * xm * xm * xm / (1.0 - xm) > 1e-9 ? 1 : 0;
+}
+
+static int needs_exact_division(const BeamPlan& p, const DmTile& dms) {
   double dmax = 0;
   for (int i = 0; i < dms.ndm; ++i) dmax = std::fmax(dmax, std::fabs(dms.dm[i]));
-  const double qmax = p.dconst * dmax * 0.25 * p.df * p.df / (fmin * fmin * (fmin - 0.5 * p.df));
-  return qmax * xm * xm * xm / (1.0 - xm) > 1e-9 ? 1 : 0;
+  return exact_division_needed(p, dmax);
 }
 
 template <int N, int V>
@@ -610,7 +278,7 @@ static int launch_block_t(const BeamPlan& p, const void* xt, const DmTile& dms, 
                           void* vout, void* stream) {
   using S = typename SchedFor<N, V>::type;
   BlockArgs a{};
-  int err = twiddles_for<S, V>(&a.tw);
+  int err = twiddles_of<S>(&a.tw);
   if (err) return err;
   a.x = xt;
   a.P = P;

@@ -51,6 +51,8 @@ struct WsLayout {
   size_t xt_off = 0, xt_bytes = 0;   // channel-major copy of the input
   size_t p_off = 0, p_bytes = 0;     // per-channel intensities [ndm][C][T_int]
   size_t d_off = 0, d_bytes = 0;     // delays [ndm][C] int32
+  size_t s_off = 0, s_bytes = 0;     // long transforms: spectra of one chunk
+  size_t pb_off = 0, pb_bytes = 0;   // long transforms: |y|^2 per sample [C][nsamp]
   size_t total = 0;
 };
 WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p);
@@ -71,6 +73,10 @@ int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream
 int launch_dsum(const BeamPlan& p, int ndm, const float* P, const int32_t* d,
                 float* I, int32_t* cov, int64_t out_stride, void* stream);
 bool block_supported(int N);
+bool large_supported(int N);
+int64_t large_chunk_items(const BeamPlan& p);  // (channel, block) items per chunk
+int launch_large(const BeamPlan& p, const void* xt, double dm, void* S, float* pbuf,
+                 float* P, void* vout, void* stream);
 int block_variants(int N);  // number of schedules compiled for N
 
 // Stage timing (cdd_profile.hip): no-ops unless profiling is enabled.

@@ -217,3 +217,72 @@ def test_multi_beam_plan_uneven_beams():
             assert rel_l2(plan.I[bi][i].cpu().numpy(), o["I"]) <= TOL_I
             assert np.array_equal(plan.cov[bi][i].cpu().numpy(), o["cov"])
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Long transforms (four-step kernels, N >= 2^15)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lgN", [15, 16, 17, 19, 20, 22])
+def test_long_transform_lengths_cf32(lgN):
+    N = 1 << lgN
+    fcen, bw = 300.0, 4.0
+    dm = 1.5 * N / (1 << 15)          # impulse response about N/4 samples
+    nsamp = 2 * N + N // 2 + 1234
+    rng = np.random.default_rng(50 + lgN)
+    x = (rng.standard_normal(nsamp) + 1j * rng.standard_normal(nsamp)).astype(np.complex64)
+    got, o, info = _run_both(x, fcen, bw, dm, 8, N)
+    assert info["fft_len"] == N
+    _check(got, o)
+
+
+def test_long_transform_multichannel_int8():
+    v = _beam_int8(60, 70_000, 3, 300.0, 3 * 1.0, 3.0, pulse=False)
+    got, o, info = _run_both(v, 300.0, 3.0, 3.0, 4, 1 << 15)
+    _check(got, o)
+
+
+def test_config1_full_size_and_pulse():
+    """2^23 complex samples of a 16 MHz band at 610 MHz, one pulse dispersed
+    at DM 10; N = 2^18, L = 2^17: voltages and intensities against the
+    oracle, and the dedispersed pulse back at its emission time."""
+    import torch
+    cdd = _cdd()
+    b = synth.config(1)
+    t0_us = (1 << 22) / b.bw
+    rng = synth.rng_for(1)
+    x = synth.single_pulse_cf32(rng, b.nsamp, b.bw, b.f_centre, t0_us,
+                                arrival_law(b.dm, b.f_centre), fwhm_us=20.0,
+                                amp=b.amp_sigma, nsub=256).astype(np.complex64)
+    flush("config 1 full size")
+    g = cdd.dedisperse(to_dev(x), b.f_centre, b.bw, b.dm, 0, b.n_int, want_voltages=True,
+                       want_chan=True)
+    torch.cuda.synchronize()
+    info = g["info"]
+    assert (info["fft_len"], info["overlap"], info["nfront"]) == (1 << 18, 1 << 17, 64615)
+    y = g["y"].cpu().numpy()[0]
+    o = O.dedisperse(x, b.f_centre, b.bw, b.dm, b.n_int, fft_len=1 << 18, overlap=1 << 17,
+                     nfront=64615, want_voltages=True)
+    ev, ei = rel_l2(y, o["y"][0]), rel_l2(g["I"].cpu().numpy(), o["I"])
+    flush("config 1 voltage rel L2 %.3g intensity rel L2 %.3g" % (ev, ei))
+    assert ev <= TOL_V and ei <= TOL_I
+    p = np.convolve(np.abs(y) ** 2, np.ones(320) / 320, mode="same")
+    assert abs(int(np.argmax(p)) - (1 << 22)) < 200
+
+
+def test_long_transform_batched_plan():
+    import torch
+    cdd = _cdd()
+    rng = np.random.default_rng(61)
+    nsamp = 90_000
+    x = (rng.standard_normal(nsamp) + 1j * rng.standard_normal(nsamp)).astype(np.complex64)
+    dms = [1.0, 1.4]
+    plan = cdd.Plan([dict(voltages=to_dev(x), f_centre=300.0, bw=4.0, dms=dms, n_int=2,
+                          fft_len=1 << 15)])
+    plan.execute()
+    torch.cuda.synchronize()
+    info = plan.info(0)
+    for i, dm in enumerate(dms):
+        o = O.dedisperse(x, 300.0, 4.0, dm, 2, fft_len=1 << 15, overlap=info["overlap"],
+                         nfront=info["nfront"])
+        assert rel_l2(plan.I[0][i].cpu().numpy(), o["I"]) <= TOL_I
+    plan.close()
