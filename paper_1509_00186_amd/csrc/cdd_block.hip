@@ -207,19 +207,26 @@ __global__ __launch_bounds__(S::T, MULTI ? (S::MINB + 1) / 2 : S::MINB) void blo
   load_block<S, DT>(v, a, c, k, t);
   fft_forward<S>(v, lds, a.tw, t);
   if constexpr (!MULTI) {
-    apply_chirp<S>(v, a.dms.dm[0], fc, a, t);
-    fft_inverse<S>(v, lds, a.tw, t);
-    epilogue<S, true>(v, lds, a, c, k, 0, t);
+    int tt = t;  // opaque copy: keeps per-bin index math next to its use
+    asm volatile("" : "+v"(tt));
+    apply_chirp<S>(v, a.dms.dm[0], fc, a, tt);
+    fft_inverse<S>(v, lds, a.tw, tt);
+    epilogue<S, true>(v, lds, a, c, k, 0, tt);
   } else {
     float2 X[S::E];
 #pragma unroll
     for (int e = 0; e < S::E; ++e) X[e] = v[e];
     for (int i = 0; i < a.dms.ndm; ++i) {
+      // Per-bin indices do not depend on the DM; an opaque copy of the
+      // thread index keeps the compiler from hoisting them (and holding them
+      // in registers) across the whole loop.
+      int tt = t;
+      asm volatile("" : "+v"(tt));
 #pragma unroll
       for (int e = 0; e < S::E; ++e) v[e] = X[e];
-      apply_chirp<S>(v, a.dms.dm[i], fc, a, t);
-      fft_inverse<S>(v, lds, a.tw, t);
-      epilogue<S, false>(v, lds, a, c, k, i, t);
+      apply_chirp<S>(v, a.dms.dm[i], fc, a, tt);
+      fft_inverse<S>(v, lds, a.tw, tt);
+      epilogue<S, false>(v, lds, a, c, k, i, tt);
     }
   }
 }
