@@ -95,6 +95,44 @@ def cpu_baseline(v, b, seconds: float):
                       % (len(chans), b.nchan, b.nsamp, dt)}
 
 
+def dm_trials(cdd, torch, vd, b, info, reps: int = 3):
+    """64 DM trials (60.0 + 0.254 i) on the same resident beam: the batched
+    plan (forward transform shared, one persistent launch per 64 trials)
+    against a plain loop of single-DM calls at the same (N, L, nfront)."""
+    import synth
+    dms = synth.config(4).dms
+    plan = cdd.Plan([dict(voltages=vd, f_centre=b.f_centre, bw=b.bw, dms=dms, n_int=b.n_int,
+                          fft_len=b.fft_len)])
+    pi = plan.info(0)
+    plan.execute()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.execute()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    outs = [cdd.dedisperse(vd, b.f_centre, b.bw, dm, pi["fft_len"], b.n_int,
+                           overlap=pi["overlap"], nfront=pi["nfront"]) for dm in dms]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for dm, o in zip(dms, outs):
+            cdd.dedisperse(vd, b.f_centre, b.bw, dm, pi["fft_len"], b.n_int,
+                           overlap=pi["overlap"], nfront=pi["nfront"], out=o)
+    torch.cuda.synchronize()
+    t_loop = (time.perf_counter() - t0) / reps
+    I_loop = torch.stack([o["I"] for o in outs])
+    diff = float(torch.linalg.norm(plan.I[0] - I_loop) / torch.linalg.norm(I_loop))
+    plan.close()
+    sdm = b.nchan * b.nsamp * len(dms)
+    return {"ndm": len(dms), "dm_range": [dms[0], dms[-1]],
+            "plan": {"fft_len": pi["fft_len"], "overlap": pi["overlap"], "nfront": pi["nfront"]},
+            "batched_ms": round(t_batch * 1e3, 3), "loop_ms": round(t_loop * 1e3, 3),
+            "batched_msamples_dm_per_s": round(sdm / t_batch / 1e6, 1),
+            "loop_msamples_dm_per_s": round(sdm / t_loop / 1e6, 1),
+            "speedup": round(t_loop / t_batch, 3), "rel_l2_batched_vs_loop": diff}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +141,7 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dm-trials", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -184,6 +223,8 @@ def main():
                      "alg_hbm_frac": round(alg_bytes / (blk_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
         "gflops_paper_eq5": round(flops / (blk_avg * 1e-3) / 1e9, 1),
     }
+    if args.config == 2 and not args.no_dm_trials:
+        res["dm_trials"] = dm_trials(cdd, torch, vd, b, info)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(v, b, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -1,4 +1,5 @@
 // C-ABI entry points: one-shot dedispersion and batched plans.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -72,8 +73,52 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
 struct cdd_plan {
   std::vector<BeamPlan> beams;
   std::vector<cdd_beam> desc;
+  std::vector<int> tile;         // DM trials per launch, per beam
+  std::vector<WsLayout> lay;     // per-beam workspace regions (offsets from ws_base)
+  std::vector<size_t> ws_base;
+  size_t tab_off = 0, cnt_off = 0;
+  int rounds = 0;
   size_t ws = 0;
 };
+
+namespace {
+constexpr size_t kPlanPBudget = (size_t)8 << 30;  // per-channel intensities held at once
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// DM tiles and workspace layout of a plan: each beam gets its own channel-major
+// copy, intensity and delay regions; then one launch table per round and the
+// work counter.
+void layout_plan(cdd_plan* pl) {
+  const size_t nb = pl->beams.size();
+  pl->tile.assign(nb, 1);
+  pl->lay.assign(nb, WsLayout());
+  pl->ws_base.assign(nb, 0);
+  size_t off = 0;
+  pl->rounds = 0;
+  for (size_t b = 0; b < nb; ++b) {
+    const BeamPlan& p = pl->beams[b];
+    const int ndm = (int)p.dms.size();
+    int t = 1;
+    if (block_supported(p.N)) {
+      const size_t per_dm = (size_t)p.nchan * p.t_int * sizeof(float);
+      const size_t budget = kPlanPBudget / nb;
+      t = (int)std::min<size_t>((size_t)std::min(ndm, kMaxDmTile),
+                                std::max<size_t>(1, budget / std::max<size_t>(per_dm, 1)));
+    }
+    pl->tile[b] = t;
+    pl->lay[b] = ws_layout(p, t, true);
+    pl->ws_base[b] = off;
+    off = align256(off + pl->lay[b].total);
+    pl->rounds = std::max(pl->rounds, (ndm + t - 1) / t);
+  }
+  pl->tab_off = off;
+  off = align256(off + batch_table_bytes((int)nb) * (size_t)std::max(pl->rounds, 1));
+  pl->cnt_off = off;
+  off = align256(off + 256);
+  pl->ws = off;
+}
+}  // namespace
 
 extern "C" {
 
@@ -135,13 +180,12 @@ cdd_status cdd_plan_create(const cdd_beam* beams, int32_t nbeam, const cdd_opts*
         delete pl;
         return fail(CDD_ENOTSUP, "beam %d: fft_len %d is not supported", b, p.N);
       }
-      int tile = std::min<int>((int)p.dms.size(), kMaxDmTile);
-      pl->ws = std::max(pl->ws, ws_layout(p, tile, true).total);
       pl->beams.push_back(p);
       cdd_beam copy = d;
       copy.host_dms = nullptr;
       pl->desc.push_back(copy);
     }
+    layout_plan(pl);
     *out = pl;
     clear_error();
     return CDD_OK;
@@ -179,33 +223,97 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
       return fail(CDD_EINVAL, "workspace too small: need %zu bytes", plan->ws);
     if (!aligned256(workspace)) return fail(CDD_EINVAL, "workspace must be 256-byte aligned");
     char* ws = (char*)workspace;
-    for (size_t b = 0; b < plan->beams.size(); ++b) {
+    const size_t nb = plan->beams.size();
+    std::vector<const void*> xt(nb, nullptr);
+    int e = 0;
+    // layout change once per beam
+    for (size_t b = 0; b < nb; ++b) {
       const BeamPlan& p = plan->beams[b];
-      const cdd_beam& d = plan->desc[b];
-      const int ndm = (int)p.dms.size();
-      const int tmax = std::min(ndm, kMaxDmTile);
-      WsLayout lay = ws_layout(p, tmax, true);
-      const void* xt = nullptr;
+      char* wb = ws + plan->ws_base[b];
       if (p.nchan > 1) {
-        int e = launch_transposed(p, d.voltages, ws + lay.xt_off, stream);
-        if (e) return device_fail("transpose launch", e);
-        xt = ws + lay.xt_off;
+        if ((e = launch_transposed(p, plan->desc[b].voltages, wb + plan->lay[b].xt_off, stream)))
+          return device_fail("transpose launch", e);
+        xt[b] = wb + plan->lay[b].xt_off;
       } else {
-        xt = d.voltages;
+        xt[b] = plan->desc[b].voltages;
       }
-      for (int i0 = 0; i0 < ndm; i0 += kMaxDmTile) {
-        DmTile tile;
-        tile.ndm = std::min(kMaxDmTile, ndm - i0);
-        for (int i = 0; i < tile.ndm; ++i) tile.dm[i] = p.dms[i0 + i];
-        cdd_status s = run_tile(p, d.voltages, tile, xt, ws, lay, nullptr, nullptr,
-                                d.intensity + (int64_t)i0 * p.t_int,
-                                d.coverage ? d.coverage + (int64_t)i0 * p.t_int : nullptr,
-                                p.t_int, stream);
-        if (s != CDD_OK) return s;
+    }
+    std::vector<BatchBeam> group;
+    std::vector<std::vector<char>> host_tabs;  // kept until return
+    for (int r = 0; r < plan->rounds; ++r) {
+      // tiles of this round
+      std::vector<DmTile> tiles(nb);
+      for (size_t b = 0; b < nb; ++b) {
+        const BeamPlan& p = plan->beams[b];
+        const int i0 = r * plan->tile[b];
+        tiles[b].ndm = std::max(0, std::min(plan->tile[b], (int)p.dms.size() - i0));
+        for (int i = 0; i < tiles[b].ndm; ++i) tiles[b].dm[i] = p.dms[i0 + i];
+      }
+      // one persistent launch per transform length among the block-kernel beams
+      std::vector<bool> done(nb, false);
+      void* tab_dev = ws + plan->tab_off + batch_table_bytes((int)nb) * (size_t)r;
+      size_t tab_used = 0;
+      for (size_t b0 = 0; b0 < nb; ++b0) {
+        if (done[b0] || tiles[b0].ndm == 0 || !block_supported(plan->beams[b0].N)) continue;
+        group.clear();
+        for (size_t b = b0; b < nb; ++b) {
+          if (done[b] || tiles[b].ndm == 0 || plan->beams[b].N != plan->beams[b0].N) continue;
+          done[b] = true;
+          BatchBeam bb;
+          bb.p = &plan->beams[b];
+          bb.xt = xt[b];
+          bb.dms = tiles[b];
+          bb.P = (float*)(ws + plan->ws_base[b] + plan->lay[b].p_off);
+          group.push_back(bb);
+        }
+        // longest work first
+        std::stable_sort(group.begin(), group.end(), [](const BatchBeam& x, const BatchBeam& y) {
+          return x.dms.ndm > y.dms.ndm;
+        });
+        host_tabs.emplace_back(batch_table_bytes((int)group.size()), 0);
+        void* tok = nullptr;
+        if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
+        if ((e = launch_batch(group.data(), (int)group.size(), host_tabs.back().data(),
+                              (char*)tab_dev + tab_used,
+                              (unsigned int*)(ws + plan->cnt_off), stream)))
+          return device_fail("batched launch", e);
+        if ((e = stage_end(kStageBlock, stream, tok))) return device_fail("event record", e);
+        tab_used += batch_table_bytes((int)group.size());
+      }
+      // long transforms, then delays and aligned sums per beam
+      for (size_t b = 0; b < nb; ++b) {
+        if (tiles[b].ndm == 0) continue;
+        const BeamPlan& p = plan->beams[b];
+        const cdd_beam& d = plan->desc[b];
+        char* wb = ws + plan->ws_base[b];
+        const WsLayout& lay = plan->lay[b];
+        float* P = (float*)(wb + lay.p_off);
+        void* tok = nullptr;
+        if (!block_supported(p.N)) {
+          if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
+          for (int i = 0; i < tiles[b].ndm; ++i)
+            if ((e = launch_large(p, xt[b], tiles[b].dm[i], wb + lay.s_off,
+                                  (float*)(wb + lay.pb_off), P + (int64_t)i * p.nchan * p.t_int,
+                                  nullptr, stream)))
+              return device_fail("long-transform launch", e);
+          if ((e = stage_end(kStageBlock, stream, tok))) return device_fail("event record", e);
+        }
+        int32_t* dl = (int32_t*)(wb + lay.d_off);
+        const int64_t i0 = (int64_t)r * plan->tile[b];
+        if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
+        if ((e = launch_delays(p, tiles[b], dl, stream))) return device_fail("delay launch", e);
+        if ((e = stage_end(kStageDelays, stream, tok))) return device_fail("event record", e);
+        if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
+        if ((e = launch_dsum(p, tiles[b].ndm, P, dl, d.intensity + i0 * p.t_int,
+                             d.coverage ? d.coverage + i0 * p.t_int : nullptr, p.t_int, stream)))
+          return device_fail("delay-sum launch", e);
+        if ((e = stage_end(kStageDsum, stream, tok))) return device_fail("event record", e);
       }
     }
     clear_error();
     return CDD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(CDD_ENOMEM, "host allocation failed");
   } catch (...) {
     return fail(CDD_EINTERNAL, "unexpected exception");
   }

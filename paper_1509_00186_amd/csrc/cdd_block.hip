@@ -43,11 +43,11 @@ template <> struct SchedFor<1024, 0> { using type = Sched<1024, 64, 16, 16, 4, 1
 template <> struct SchedFor<2048, 0> { using type = Sched<2048, 128, 16, 16, 8, 1>; };
 template <> struct SchedFor<4096, 0> { using type = Sched<4096, 256, 16, 16, 16, 1, true, false, 3>; };
 template <> struct SchedFor<4096, 1> { using type = Sched<4096, 256, 16, 16, 16, 1, false, false, 2>; };
-template <> struct SchedFor<8192, 0> { using type = Sched<8192, 512, 16, 16, 16, 2, true, false, 4>; };
-template <> struct SchedFor<8192, 1> { using type = Sched<8192, 512, 16, 16, 16, 2, false, false, 4>; };
-template <> struct SchedFor<8192, 2> { using type = Sched<8192, 512, 16, 16, 16, 2, false, false, 3>; };
-template <> struct SchedFor<8192, 3> { using type = Sched<8192, 512, 16, 16, 16, 2, true, true, 4>; };
-template <> struct SchedFor<8192, 4> { using type = Sched<8192, 256, 16, 16, 32, 1, false, false, 2>; };
+template <> struct SchedFor<8192, 0> { using type = Sched<8192, 512, 16, 16, 16, 2, true, true, 4>; };
+template <> struct SchedFor<8192, 1> { using type = Sched<8192, 512, 16, 16, 16, 2, true, true, 6>; };
+template <> struct SchedFor<8192, 2> { using type = Sched<8192, 512, 16, 16, 16, 2, true, false, 6>; };
+template <> struct SchedFor<8192, 3> { using type = Sched<8192, 512, 16, 16, 16, 2, false, true, 4>; };
+template <> struct SchedFor<8192, 4> { using type = Sched<8192, 256, 16, 16, 32, 1, true, true, 3>; };
 template <> struct SchedFor<16384, 0> { using type = Sched<16384, 1024, 16, 16, 16, 4, true, false, 4>; };
 template <> struct SchedFor<16384, 1> { using type = Sched<16384, 512, 16, 32, 32, 1, false, false, 2>; };
 constexpr int kVariants[] = {1, 1, 1, 1, 2, 5, 2};  // per log2(N) - 8
@@ -55,13 +55,20 @@ constexpr int kVariants[] = {1, 1, 1, 1, 2, 5, 2};  // per log2(N) - 8
 // ---------------------------------------------------------------------------
 // Kernel
 // ---------------------------------------------------------------------------
+// One beam's launch description.  Coordinates are relative to this launch:
+// block k reads input samples k*M - load_off + n (valid in [0, x_len)) and
+// yields output samples o = k*M + m, m < M, and integrated samples
+// u = k*M/n_int + ul.
 struct BlockArgs {
-  const void* x;        // channel-major input [nchan][nsamp] (int8x2 or float2)
-  float* P;             // [ndm][nchan][t_int]
-  float2* vout;         // [nchan][nsamp] or null (single DM only)
+  const void* x;        // channel-major input, channel stride x_stride (int8x2 or float2)
+  float* P;             // P[dmi*p_dm_stride + c*p_stride + u]
+  float2* vout;         // vout[c*v_stride + o] or null (single DM only)
   const float2* tw;     // twiddle tables
-  int64_t nsamp, t_int, nblocks;
-  int32_t nchan, M, nfront, n_int, phase_mode, exact_div;
+  int64_t x_stride, x_len, load_off;
+  int64_t p_stride, p_dm_stride, u_lim;
+  int64_t v_stride, o_lim;
+  int64_t nblocks, item0;   // blocks per channel; first work item of this beam
+  int32_t nchan, M, nfront, n_int, dtype, phase_mode, exact_div, pad;
   double f_lo, df, dconst;
   DmTile dms;
 };
@@ -77,33 +84,36 @@ template <class S>
 __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, const BlockArgs& a,
                                             int t) {
   constexpr int N = S::N, R = S::rad_f(S::NP - 1), BPT = N / (R * S::T);
+  // This thread holds bins i = (t + T b) + r N/R with t + T b < N/R, so
+  // i >= N/2 exactly when r >= R/2: the signed bin is a per-b base plus a
+  // compile-time constant per r.
   const float inv_n = 1.0f / (float)N;
   if (a.phase_mode == CDD_PHASE_FP64_REDUCED) {
     const double dfn = a.df / (double)N;
-    const double B = a.dconst * dm * dfn * dfn / (fc * fc * fc);
+    const double B64 = 64.0 * a.dconst * dm * dfn * dfn / (fc * fc * fc);  // 1/64 turns
     const double beta = dfn / fc;
     if (a.exact_div == 0) {
 #pragma unroll
       for (int b = 0; b < BPT; ++b) {
+        const double s0 = (double)(t + S::T * b);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const int i = t + S::T * b + r * (N / R);
-          const double sd = (double)(i < N / 2 ? i : i - N);
+          const double sd = s0 + (double)(r * (N / R) - (2 * r >= R ? N : 0));
           const double x = beta * sd;
-          const double q = (B * (sd * sd)) * fma(x, x, 1.0 - x);
-          const float2 h = expi_neg_turns(q - rint(q));
+          const double q64 = (B64 * (sd * sd)) * fma(x, x, 1.0 - x);
+          const float2 h = expi_neg_turns64(q64);
           v[b * R + r] = cmul(v[b * R + r], make_float2(h.x * inv_n, h.y * inv_n));
         }
       }
     } else {
 #pragma unroll
       for (int b = 0; b < BPT; ++b) {
+        const double s0 = (double)(t + S::T * b);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const int i = t + S::T * b + r * (N / R);
-          const double sd = (double)(i < N / 2 ? i : i - N);
-          const double q = (B * (sd * sd)) / fma(beta, sd, 1.0);
-          const float2 h = expi_neg_turns(q - rint(q));
+          const double sd = s0 + (double)(r * (N / R) - (2 * r >= R ? N : 0));
+          const double q64 = (B64 * (sd * sd)) / fma(beta, sd, 1.0);
+          const float2 h = expi_neg_turns64(q64);
           v[b * R + r] = cmul(v[b * R + r], make_float2(h.x * inv_n, h.y * inv_n));
         }
       }
@@ -129,10 +139,37 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
   }
 }
 
+// Load block k of channel c: sample n of the block is input sample
+// k*M - load_off + n, zero outside [0, x_len).  Blocks that start inside the
+// data read through a buffer resource whose range ends at the data's end, so
+// the hardware returns zeros past it and no per-sample test is needed.
 template <class S, int DT>
 __device__ __forceinline__ void load_block(float2* v, const BlockArgs& a, int c, int64_t k, int t) {
   constexpr int N = S::N, R = S::rad_f(0), BPT = N / (R * S::T);
-  const int64_t t0 = k * a.M - a.nfront;
+  constexpr int ES = DT == CDD_CI8 ? 2 : 8;
+  const int64_t t0 = k * a.M - a.load_off;
+  if (t0 >= 0) {
+    const int64_t avail = a.x_len - t0;
+    const int nrec = (int)(avail < N ? avail * ES : (int64_t)N * ES);
+    const char* base = (const char*)a.x + ((int64_t)c * a.x_stride + t0) * ES;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, nrec, 0x00020000);
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int soff = (S::T * b + r * (N / R)) * ES;
+        if constexpr (DT == CDD_CI8) {
+          const unsigned short w = __builtin_amdgcn_raw_buffer_load_b16(rs, t * ES, soff, 0);
+          v[b * R + r] = make_float2((float)(signed char)(w & 0xff), (float)(signed char)(w >> 8));
+        } else {
+          const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, t * ES, soff, 0);
+          v[b * R + r] = make_float2(__builtin_bit_cast(float, w[0]), __builtin_bit_cast(float, w[1]));
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
 #pragma unroll
@@ -140,12 +177,12 @@ __device__ __forceinline__ void load_block(float2* v, const BlockArgs& a, int c,
       const int n = t + S::T * b + r * (N / R);
       const int64_t tt = t0 + n;
       float2 z = make_float2(0.f, 0.f);
-      if (tt >= 0 && tt < a.nsamp) {
+      if (tt >= 0 && tt < a.x_len) {
         if constexpr (DT == CDD_CI8) {
-          const short w = ((const short*)a.x)[(int64_t)c * a.nsamp + tt];
+          const short w = ((const short*)a.x)[(int64_t)c * a.x_stride + tt];
           z = make_float2((float)(signed char)(w & 0xff), (float)(signed char)(w >> 8));
         } else {
-          z = ((const float2*)a.x)[(int64_t)c * a.nsamp + tt];
+          z = ((const float2*)a.x)[(int64_t)c * a.x_stride + tt];
         }
       }
       v[b * R + r] = z;
@@ -166,11 +203,13 @@ __device__ __forceinline__ void epilogue(const float2* v, float* lds, const Bloc
           const int n = t + S::T * b + r * (N / R);
           const int m = n - a.nfront;
           const int64_t o = k * a.M + m;
-          if (m >= 0 && m < a.M && o < a.nsamp) a.vout[(int64_t)c * a.nsamp + o] = v[b * R + r];
+          if (m >= 0 && m < a.M && o < a.o_lim) a.vout[(int64_t)c * a.v_stride + o] = v[b * R + r];
         }
       }
     }
   }
+  // |z|^2 to LDS in natural order (unpadded: consecutive lanes write
+  // consecutive words), then each output sums n_int consecutive words.
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
@@ -178,30 +217,35 @@ __device__ __forceinline__ void epilogue(const float2* v, float* lds, const Bloc
     for (int r = 0; r < R; ++r) {
       const int n = t + S::T * b + r * (N / R);
       const float2 z = v[b * R + r];
-      lds[lpad(n)] = z.x * z.x + z.y * z.y;
+      lds[n] = z.x * z.x + z.y * z.y;
     }
   }
   __syncthreads();
   const int nu = a.M / a.n_int;
   const int64_t u0 = k * (a.M / a.n_int);
-  float* P = a.P + ((int64_t)dmi * a.nchan + c) * a.t_int;
-  for (int ul = t; ul < nu; ul += S::T) {
-    const int64_t u = u0 + ul;
-    if (u >= a.t_int) break;
-    const int base = a.nfront + ul * a.n_int;
-    float s = 0.f;
-    for (int r = 0; r < a.n_int; ++r) s += lds[lpad(base + r)];
-    P[u] = s;
+  float* P = a.P + (int64_t)dmi * a.p_dm_stride + (int64_t)c * a.p_stride;
+  if (a.n_int == 4 && (a.nfront & 3) == 0) {
+    for (int ul = t; ul < nu; ul += S::T) {
+      const int64_t u = u0 + ul;
+      if (u >= a.u_lim) break;
+      const float4 q = *(const float4*)&lds[a.nfront + 4 * ul];
+      P[u] = ((q.x + q.y) + q.z) + q.w;
+    }
+  } else {
+    for (int ul = t; ul < nu; ul += S::T) {
+      const int64_t u = u0 + ul;
+      if (u >= a.u_lim) break;
+      const int base = a.nfront + ul * a.n_int;
+      float s = 0.f;
+      for (int r = 0; r < a.n_int; ++r) s += lds[base + r];
+      P[u] = s;
+    }
   }
 }
 
 template <class S, int DT, bool MULTI>
-__global__ __launch_bounds__(S::T, MULTI ? (S::MINB + 1) / 2 : S::MINB) void block_kernel(const BlockArgs a) {
-  __shared__ float lds[S::lds_floats()];
-  const int t = threadIdx.x;
-  const int64_t item = blockIdx.x;
-  const int c = (int)(item / a.nblocks);
-  const int64_t k = item - (int64_t)c * a.nblocks;
+__device__ __forceinline__ void process_item(const BlockArgs& a, int c, int64_t k, float* lds,
+                                             int t) {
   const double fc = a.f_lo + ((double)c + 0.5) * a.df;
   float2 v[S::E];
   load_block<S, DT>(v, a, c, k, t);
@@ -230,6 +274,48 @@ __global__ __launch_bounds__(S::T, MULTI ? (S::MINB + 1) / 2 : S::MINB) void blo
     }
   }
 }
+
+// One workgroup per (channel, block) of one beam.
+template <class S, int DT, bool MULTI>
+__global__ __launch_bounds__(S::T, MULTI ? (S::MINB + 1) / 2 : S::MINB) void block_kernel(
+    const BlockArgs a) {
+  __shared__ __align__(16) float lds[S::lds_floats()];
+  const int64_t item = blockIdx.x;
+  const int c = (int)(item / a.nblocks);
+  const int64_t k = item - (int64_t)c * a.nblocks;
+  process_item<S, DT, MULTI>(a, c, k, lds, threadIdx.x);
+}
+
+// Persistent form for several beams sharing one transform length: a grid
+// sized to the machine pulls work items (beam, channel, block) from a
+// counter until all are taken; beams are listed longest work first.  Every
+// wave leaves the loop once the counter passes the item count.
+template <class S>
+__global__ __launch_bounds__(S::T, (S::MINB + 1) / 2) void batch_kernel(
+    const BlockArgs* __restrict__ beams, int32_t nbeams, int64_t total,
+    unsigned int* __restrict__ counter) {
+  __shared__ __align__(16) float lds[S::lds_floats()];
+  __shared__ unsigned int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+    __syncthreads();
+    const int64_t item = s_item;
+    __syncthreads();
+    if (item >= total) break;
+    int b = 0;
+    while (b + 1 < nbeams && item >= beams[b + 1].item0) ++b;
+    const BlockArgs& a = beams[b];
+    const int64_t local = item - a.item0;
+    const int c = (int)(local / a.nblocks);
+    const int64_t k = local - (int64_t)c * a.nblocks;
+    if (a.dtype == CDD_CI8)
+      process_item<S, CDD_CI8, true>(a, c, k, lds, threadIdx.x);
+    else
+      process_item<S, CDD_CF32, true>(a, c, k, lds, threadIdx.x);
+  }
+}
+
+__global__ void zero_counter_kernel(unsigned int* c) { *c = 0u; }
 
 // ---------------------------------------------------------------------------
 // Host side: FP64 twiddle tables (cached per device, length and schedule)
@@ -280,41 +366,90 @@ static int needs_exact_division(const BeamPlan& p, const DmTile& dms) {
   return exact_division_needed(p, dmax);
 }
 
-template <int N, int V>
-static int launch_block_t(const BeamPlan& p, const void* xt, const DmTile& dms, float* P,
-                          void* vout, void* stream) {
-  using S = typename SchedFor<N, V>::type;
+// Launch description of one beam for the offline (whole-record) form.
+static BlockArgs offline_args(const BeamPlan& p, const void* xt, const DmTile& dms, float* P,
+                              void* vout) {
   BlockArgs a{};
-  int err = twiddles_of<S>(&a.tw);
-  if (err) return err;
   a.x = xt;
   a.P = P;
   a.vout = (float2*)vout;
-  a.nsamp = p.nsamp;
-  a.t_int = p.t_int;
+  a.x_stride = p.nsamp;
+  a.x_len = p.nsamp;
+  a.load_off = p.nfront;
+  a.p_stride = p.t_int;
+  a.p_dm_stride = (int64_t)p.nchan * p.t_int;
+  a.u_lim = p.t_int;
+  a.v_stride = p.nsamp;
+  a.o_lim = p.nsamp;
   a.nblocks = p.nblocks;
+  a.item0 = 0;
   a.nchan = p.nchan;
   a.M = p.M;
   a.nfront = p.nfront;
   a.n_int = p.n_int;
+  a.dtype = p.dtype;
   a.phase_mode = p.phase_mode;
   a.exact_div = needs_exact_division(p, dms);
   a.f_lo = p.f_lo;
   a.df = p.df;
   a.dconst = p.dconst;
   a.dms = dms;
-  const int64_t items = (int64_t)p.nchan * p.nblocks;
+  return a;
+}
+
+template <int N, int V>
+static int launch_block_t(const BlockArgs& a0, void* stream) {
+  using S = typename SchedFor<N, V>::type;
+  BlockArgs a = a0;
+  int err = twiddles_of<S>(&a.tw);
+  if (err) return err;
+  const int64_t items = (int64_t)a.nchan * a.nblocks;
   if (items <= 0 || items > 0x7fffffffLL) return (int)hipErrorInvalidValue;
   dim3 grid((unsigned)items), block(S::T);
   hipStream_t st = (hipStream_t)stream;
-  const bool multi = dms.ndm > 1;
-  if (p.dtype == CDD_CI8) {
+  const bool multi = a.dms.ndm > 1;
+  if (a.dtype == CDD_CI8) {
     if (multi) hipLaunchKernelGGL((block_kernel<S, CDD_CI8, true>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((block_kernel<S, CDD_CI8, false>), grid, block, 0, st, a);
   } else {
     if (multi) hipLaunchKernelGGL((block_kernel<S, CDD_CF32, true>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((block_kernel<S, CDD_CF32, false>), grid, block, 0, st, a);
   }
+  return (int)hipGetLastError();
+}
+
+// Persistent batched launch; host_tab is pinned host memory that stays
+// unchanged while the copy is in flight, dev_tab and counter are device memory.
+template <int N, int V>
+static int launch_batch_t(BlockArgs* host_tab, int nbeams, int64_t total, BlockArgs* dev_tab,
+                          unsigned int* counter, void* stream) {
+  using S = typename SchedFor<N, V>::type;
+  const float2* tw = nullptr;
+  int err = twiddles_of<S>(&tw);
+  if (err) return err;
+  for (int b = 0; b < nbeams; ++b) host_tab[b].tw = tw;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(dev_tab, host_tab, sizeof(BlockArgs) * nbeams,
+                                hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+  static int per_cu = 0;
+  static int ncu = 0;
+  if (per_cu == 0) {
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return (int)e;
+    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+      return (int)e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<S>, S::T, 0)) !=
+        hipSuccess)
+      return (int)e;
+    if (per_cu < 1) per_cu = 1;
+  }
+  const int64_t grid = std::min<int64_t>(total, (int64_t)ncu * per_cu);
+  if (grid <= 0) return 0;
+  hipLaunchKernelGGL(batch_kernel<S>, dim3((unsigned)grid), dim3(S::T), 0, st, dev_tab, nbeams,
+                     total, counter);
   return (int)hipGetLastError();
 }
 
@@ -333,26 +468,57 @@ int block_variants(int N) { return block_supported(N) ? kVariants[log2i(N) - 8] 
 int launch_block(const BeamPlan& p, const void* xt, const DmTile& dms, float* P, void* vout,
                  void* stream) {
   if (dms.ndm < 1 || dms.ndm > kMaxDmTile) return (int)hipErrorInvalidValue;
+  const BlockArgs a = offline_args(p, xt, dms, P, vout);
   const int v = p.variant;
   switch (p.N) {
-    case 256: return launch_block_t<256, 0>(p, xt, dms, P, vout, stream);
-    case 512: return launch_block_t<512, 0>(p, xt, dms, P, vout, stream);
-    case 1024: return launch_block_t<1024, 0>(p, xt, dms, P, vout, stream);
-    case 2048: return launch_block_t<2048, 0>(p, xt, dms, P, vout, stream);
+    case 256: return launch_block_t<256, 0>(a, stream);
+    case 512: return launch_block_t<512, 0>(a, stream);
+    case 1024: return launch_block_t<1024, 0>(a, stream);
+    case 2048: return launch_block_t<2048, 0>(a, stream);
     case 4096:
-      return v == 1 ? launch_block_t<4096, 1>(p, xt, dms, P, vout, stream)
-                    : launch_block_t<4096, 0>(p, xt, dms, P, vout, stream);
+      return v == 1 ? launch_block_t<4096, 1>(a, stream) : launch_block_t<4096, 0>(a, stream);
     case 8192:
       switch (v) {
-        case 1: return launch_block_t<8192, 1>(p, xt, dms, P, vout, stream);
-        case 2: return launch_block_t<8192, 2>(p, xt, dms, P, vout, stream);
-        case 3: return launch_block_t<8192, 3>(p, xt, dms, P, vout, stream);
-        case 4: return launch_block_t<8192, 4>(p, xt, dms, P, vout, stream);
-        default: return launch_block_t<8192, 0>(p, xt, dms, P, vout, stream);
+        case 1: return launch_block_t<8192, 1>(a, stream);
+        case 2: return launch_block_t<8192, 2>(a, stream);
+        case 3: return launch_block_t<8192, 3>(a, stream);
+        case 4: return launch_block_t<8192, 4>(a, stream);
+        default: return launch_block_t<8192, 0>(a, stream);
       }
     case 16384:
-      return v == 1 ? launch_block_t<16384, 1>(p, xt, dms, P, vout, stream)
-                    : launch_block_t<16384, 0>(p, xt, dms, P, vout, stream);
+      return v == 1 ? launch_block_t<16384, 1>(a, stream) : launch_block_t<16384, 0>(a, stream);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+size_t batch_table_bytes(int nbeams) { return sizeof(BlockArgs) * (size_t)nbeams; }
+
+int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_tab,
+                 unsigned int* counter, void* stream) {
+  if (nbeams < 1) return 0;
+  const int N = beams[0].p->N, v = beams[0].p->variant;
+  BlockArgs* ht = (BlockArgs*)host_tab;
+  int64_t total = 0;
+  for (int b = 0; b < nbeams; ++b) {
+    const BeamPlan& p = *beams[b].p;
+    if (p.N != N || beams[b].dms.ndm < 1 || beams[b].dms.ndm > kMaxDmTile)
+      return (int)hipErrorInvalidValue;
+    ht[b] = offline_args(p, beams[b].xt, beams[b].dms, beams[b].P, nullptr);
+    ht[b].item0 = total;
+    total += (int64_t)p.nchan * p.nblocks;
+  }
+  if (total > 0xffffffffLL) return (int)hipErrorInvalidValue;
+  BlockArgs* dt = (BlockArgs*)dev_tab;
+  switch (N) {
+    case 256: return launch_batch_t<256, 0>(ht, nbeams, total, dt, counter, stream);
+    case 512: return launch_batch_t<512, 0>(ht, nbeams, total, dt, counter, stream);
+    case 1024: return launch_batch_t<1024, 0>(ht, nbeams, total, dt, counter, stream);
+    case 2048: return launch_batch_t<2048, 0>(ht, nbeams, total, dt, counter, stream);
+    case 4096: return launch_batch_t<4096, 0>(ht, nbeams, total, dt, counter, stream);
+    case 8192:
+      return v == 2 ? launch_batch_t<8192, 2>(ht, nbeams, total, dt, counter, stream)
+                    : launch_batch_t<8192, 0>(ht, nbeams, total, dt, counter, stream);
+    case 16384: return launch_batch_t<16384, 0>(ht, nbeams, total, dt, counter, stream);
   }
   return (int)hipErrorInvalidValue;
 }

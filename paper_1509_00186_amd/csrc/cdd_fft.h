@@ -215,6 +215,12 @@ __device__ __forceinline__ void butterflies(float2* v, const PassTw<S, R, NS, TW
   }
 }
 
+// Padded LDS index of element i: one spare word after every 16.  For the
+// strided patterns of the passes, lpad(base + x) = lpad(base) + loff(x) with
+// loff a compile-time constant (the low 4 bits of base plus those of x never
+// carry), so each access is one LDS instruction with an immediate offset.
+__device__ __forceinline__ constexpr int loff(int x) { return 17 * (x >> 4) + (x & 15); }
+
 // Move the outputs of a pass (radix RP, span NSP) to the input layout of the
 // next pass (radix RN) through LDS: whole complex values, or real parts then
 // imaginary parts (half the LDS, twice the barriers).
@@ -222,54 +228,47 @@ template <class S, int RP, int NSP, int RN>
 __device__ __forceinline__ void exchange(float2* v, float* lds, int t) {
   constexpr int N = S::N, T = S::T;
   constexpr int BP = N / (RP * T), BN = N / (RN * T);
+  int wb[BP], rb[BN];
+#pragma unroll
+  for (int b = 0; b < BP; ++b) {
+    const int j = t + T * b;
+    wb[b] = lpad((j / NSP) * NSP * RP + (j % NSP));
+  }
+#pragma unroll
+  for (int b = 0; b < BN; ++b) rb[b] = lpad(t + T * b);
   if constexpr (!S::SPLIT) {
     float2* l2 = (float2*)lds;
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < BP; ++b) {
-      const int j = t + T * b;
-      const int base = (j / NSP) * NSP * RP + (j % NSP);
+    for (int b = 0; b < BP; ++b)
 #pragma unroll
-      for (int r = 0; r < RP; ++r) l2[lpad(base + r * NSP)] = v[b * RP + r];
-    }
+      for (int r = 0; r < RP; ++r) l2[wb[b] + loff(r * NSP)] = v[b * RP + r];
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < BN; ++b) {
-      const int j = t + T * b;
+    for (int b = 0; b < BN; ++b)
 #pragma unroll
-      for (int r = 0; r < RN; ++r) v[b * RN + r] = l2[lpad(j + r * (N / RN))];
-    }
+      for (int r = 0; r < RN; ++r) v[b * RN + r] = l2[rb[b] + loff(r * (N / RN))];
   } else {
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < BP; ++b) {
-      const int j = t + T * b;
-      const int base = (j / NSP) * NSP * RP + (j % NSP);
+    for (int b = 0; b < BP; ++b)
 #pragma unroll
-      for (int r = 0; r < RP; ++r) lds[lpad(base + r * NSP)] = v[b * RP + r].x;
-    }
+      for (int r = 0; r < RP; ++r) lds[wb[b] + loff(r * NSP)] = v[b * RP + r].x;
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < BN; ++b) {
-      const int j = t + T * b;
+    for (int b = 0; b < BN; ++b)
 #pragma unroll
-      for (int r = 0; r < RN; ++r) v[b * RN + r].x = lds[lpad(j + r * (N / RN))];
-    }
+      for (int r = 0; r < RN; ++r) v[b * RN + r].x = lds[rb[b] + loff(r * (N / RN))];
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < BP; ++b) {
-      const int j = t + T * b;
-      const int base = (j / NSP) * NSP * RP + (j % NSP);
+    for (int b = 0; b < BP; ++b)
 #pragma unroll
-      for (int r = 0; r < RP; ++r) lds[lpad(base + r * NSP)] = v[b * RP + r].y;
-    }
+      for (int r = 0; r < RP; ++r) lds[wb[b] + loff(r * NSP)] = v[b * RP + r].y;
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < BN; ++b) {
-      const int j = t + T * b;
+    for (int b = 0; b < BN; ++b)
 #pragma unroll
-      for (int r = 0; r < RN; ++r) v[b * RN + r].y = lds[lpad(j + r * (N / RN))];
-    }
+      for (int r = 0; r < RN; ++r) v[b * RN + r].y = lds[rb[b] + loff(r * (N / RN))];
   }
 }
 
@@ -301,33 +300,38 @@ __device__ __forceinline__ void fft_inverse(float2* v, float* lds, const float2*
 
 // cos and sin of 2 pi k / 64 for the 64 octant-of-an-octant rotations.
 struct RotTable {
-  float c[64], s[64];
+  float cs[64][2];  // cos, sin of 2 pi k / 64
 };
 constexpr RotTable make_rot() {
   RotTable t{};
   for (int i = 0; i < 64; ++i) {
-    t.c[i] = (float)ct_cos2pi(i, 64);
-    t.s[i] = (float)ct_sin2pi(i, 64);
+    t.cs[i][0] = (float)ct_cos2pi(i, 64);
+    t.cs[i][1] = (float)ct_sin2pi(i, 64);
   }
   return t;
 }
 static __constant__ RotTable kRot = make_rot();
 
-// exp(-2 pi i r) for r in [-1/2, 1/2] turns given in FP64: r = (k + d)/64
-// with k integer and |d| <= 1/2; exp(-2 pi i k/64) from the table, the rest
-// from short Taylor series of cos and sin of x = 2 pi d / 64 (|x| <= pi/64,
-// truncation below 2e-11).
-__device__ __forceinline__ float2 expi_neg_turns(double r) {
-  const double r64 = r * 64.0;
+// exp(-2 pi i r) for r given as r64 = 64 r turns in FP64 (any magnitude
+// below 2^31): r64 = k + d with k integer and |d| <= 1/2; exp(-2 pi i k/64)
+// from the table, the rest from short Taylor series of cos and sin of
+// x = 2 pi d / 64 (|x| <= pi/64, truncation below 2e-11).
+__device__ __forceinline__ float2 expi_neg_turns64(double r64) {
   const double k = rint(r64);
   const float x = (float)(r64 - k) * (float)(2.0 * kPi / 64.0);
   const int ki = (int)k & 63;
   const float x2 = x * x;
   const float cs = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24.0f));
   const float sn = x * (1.0f + x2 * (-1.0f / 6.0f + x2 * (1.0f / 120.0f)));
-  const float C = kRot.c[ki], Sn = kRot.s[ki];
+  const float2 CS = *(const float2*)kRot.cs[ki];
   // cos(a+b) - i sin(a+b)
-  return make_float2(C * cs - Sn * sn, -(Sn * cs + C * sn));
+  return make_float2(CS.x * cs - CS.y * sn, -(CS.y * cs + CS.x * sn));
+}
+
+// The same for r in turns (reduced internally).
+__device__ __forceinline__ float2 expi_neg_turns(double r) {
+  const double q = r - rint(r);
+  return expi_neg_turns64(q * 64.0);
 }
 
 // Host: FP64 twiddle tables of a schedule, rows of R entries per pass after

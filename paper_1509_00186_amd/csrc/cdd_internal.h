@@ -69,6 +69,17 @@ int launch_transpose(const void* in, void* out, int32_t dtype, int64_t nsamp,
                      int32_t nchan, void* stream);
 int launch_block(const BeamPlan& p, const void* xt, const DmTile& dms,
                  float* P, void* vout, void* stream);
+// Batched form: beams that share one transform length, each with its DM
+// tile, in one persistent launch.
+struct BatchBeam {
+  const BeamPlan* p;
+  const void* xt;    // channel-major input
+  DmTile dms;
+  float* P;          // [ndm][nchan][t_int]
+};
+size_t batch_table_bytes(int nbeams);
+int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_tab,
+                 unsigned int* counter, void* stream);
 int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream);
 int launch_dsum(const BeamPlan& p, int ndm, const float* P, const int32_t* d,
                 float* I, int32_t* cov, int64_t out_stride, void* stream);

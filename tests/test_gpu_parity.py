@@ -286,3 +286,50 @@ def test_long_transform_batched_plan():
                          nfront=info["nfront"])
         assert rel_l2(plan.I[0][i].cpu().numpy(), o["I"]) <= TOL_I
     plan.close()
+
+
+def test_persistent_launch_several_beams_same_length():
+    """Three beams of different width and channel count, one transform
+    length: one persistent launch; each beam's DM trials against the oracle."""
+    import torch
+    cdd = _cdd()
+    specs = [(610.0, 8, 0.03125, 11_000, [10.0, 12.0]),
+             (325.0, 20, 0.0625, 9_500, [67.9, 60.0, 70.0]),
+             (400.0, 33, 0.048828125, 7_000, [120.0])]
+    beams, raw = [], []
+    for k, (fcen, nchan, df, nsamp, dms) in enumerate(specs):
+        v = _beam_int8(70 + k, nsamp, nchan, fcen, nchan * df, dms[0])
+        raw.append((v, fcen, nchan * df, dms))
+        beams.append(dict(voltages=to_dev(v), f_centre=fcen, bw=nchan * df, dms=dms,
+                          n_int=4, fft_len=2048))
+    plan = cdd.Plan(beams)
+    for rep in range(2):          # the plan runs again with the same buffers
+        plan.execute()
+        torch.cuda.synchronize()
+        for bi, (v, fcen, bw, dms) in enumerate(raw):
+            info = plan.info(bi)
+            assert info["fft_len"] == 2048
+            for i, dm in enumerate(dms):
+                o = O.dedisperse(v, fcen, bw, dm, 4, fft_len=2048, overlap=info["overlap"],
+                                 nfront=info["nfront"])
+                assert rel_l2(plan.I[bi][i].cpu().numpy(), o["I"]) <= TOL_I
+                assert np.array_equal(plan.cov[bi][i].cpu().numpy(), o["cov"])
+    plan.close()
+
+
+def test_dm_tiles_beyond_one_launch():
+    """More DM trials than one launch holds (70 > 64): two rounds."""
+    import torch
+    cdd = _cdd()
+    v = _beam_int8(80, 6_000, 4, 325.0, 0.25, 30.0, pulse=False)
+    dms = [20.0 + 0.3 * i for i in range(70)]
+    plan = cdd.Plan([dict(voltages=to_dev(v), f_centre=325.0, bw=0.25, dms=dms, n_int=2,
+                          fft_len=1024)])
+    plan.execute()
+    torch.cuda.synchronize()
+    info = plan.info(0)
+    for i in (0, 33, 63, 64, 69):
+        o = O.dedisperse(v, 325.0, 0.25, dms[i], 2, fft_len=1024, overlap=info["overlap"],
+                         nfront=info["nfront"])
+        assert rel_l2(plan.I[0][i].cpu().numpy(), o["I"]) <= TOL_I
+    plan.close()
