@@ -186,6 +186,97 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes,
 void cdd_plan_destroy(cdd_plan* plan);
 
 /* ---------------------------------------------------------------------
+ * Real-time serving.  A server accepts many concurrent streams, each a
+ * voltage beam that arrives in blocks of any size (the paper's pipeline reads
+ * consecutive blocks from a ring and must not lose any, Sec. 4.3 and 4.5).
+ * Per stream the server keeps, in device memory, the overlap tail of the
+ * input (the samples a block loses to overlap-save are prefixed to the next
+ * block, Sec. 4.3) and the per-channel intensities still needed by the
+ * delay-aligned sum.  A scheduler thread folds every block that is ready,
+ * from every stream, into the next launch (one persistent launch per
+ * transform length), so streams that arrive while others are on the GPU are
+ * served as slots and memory free up, and their work overlaps on the device.
+ * The result of a stream depends only on its own data and plan: the same
+ * alone or in any mix, and equal to cdd_dedisperse on the whole record.
+ * Host pointers below are host memory; the server owns all device memory.
+ * ------------------------------------------------------------------- */
+typedef struct cdd_server cdd_server;
+
+typedef struct {
+  size_t hbm_budget;      /* device bytes open streams may hold; 0 = 8 GiB   */
+  int32_t max_streams;    /* 0 = 64                                          */
+  int32_t queue_depth;    /* blocks per stream pushed but not yet consumed;
+                             0 = 4                                           */
+  int32_t reserved[6];
+} cdd_server_opts;
+
+typedef struct {
+  int32_t dtype;          /* cdd_dtype; blocks are time-major as for
+                             cdd_dedisperse                                  */
+  int32_t nchan;
+  double f_centre_mhz;
+  double bw_mhz;
+  double dm;
+  int32_t fft_len;        /* 0 = length rule; must be <= 16384             */
+  int32_t n_int;
+  int64_t max_block;      /* largest block a push may carry (samples/chan)   */
+  int32_t phase_mode;
+  int32_t reserved[5];
+} cdd_stream_desc;
+
+typedef struct {
+  int64_t blocks_in;      /* blocks accepted                                 */
+  int64_t blocks_done;    /* blocks whose results are on the host            */
+  int64_t rejected;       /* duplicate or out-of-order pushes refused        */
+  int64_t gaps;           /* pushes that skipped sequence numbers            */
+  int64_t admitted;       /* streams opened                                  */
+  int64_t refused;        /* stream opens refused for budget or slots        */
+  int64_t batches;        /* launches formed by the scheduler                */
+  double lat_p50_ms;      /* block arrival -> its results on the host        */
+  double lat_p99_ms;
+  double lat_max_ms;
+  double data_s;          /* seconds of data consumed, summed over streams   */
+  double wall_s;          /* wall seconds from first push to last completion */
+  size_t hbm_used;        /* device bytes held by admitted streams           */
+  size_t hbm_budget;
+} cdd_server_stats;
+
+/* Create a server on the current device.  ENOMEM, EDEVICE. */
+cdd_status cdd_server_create(const cdd_server_opts* opts, cdd_server** out);
+/* Finish all queued work, then free everything. */
+void cdd_server_destroy(cdd_server* server);
+/* Admit a stream (plan as cdd_query with nsamp = max_block).  EAGAIN when
+ * its device memory would exceed the budget or all slots are taken; EINVAL
+ * as cdd_query; ENOTSUP for fft_len > 16384. */
+cdd_status cdd_stream_open(cdd_server* server, const cdd_stream_desc* desc,
+                           int32_t* stream_id);
+/* Queue the next block: host_block [nsamp][nchan] (time-major), copied
+ * before return.  seq must be the stream's next sequence number (first 0):
+ * a smaller seq is refused (EINVAL, counted as rejected); a larger one means
+ * blocks were lost -- it is accepted, counted as a gap, and the block is
+ * processed as if preceded by zeros (the overlap tail and any samples not
+ * yet part of a complete block are dropped; absolute sample numbering
+ * continues without the lost span).  EAGAIN
+ * when queue_depth blocks are already waiting (retry later); EINVAL for
+ * nsamp < 1 or > max_block, or a closed stream. */
+cdd_status cdd_stream_push(cdd_server* server, int32_t stream_id,
+                           const void* host_block, int64_t nsamp, uint64_t seq);
+/* Copy up to cap finished samples of the stream's aligned sum I[u] (FP32,
+ * in order) to host_out; *n receives the count and *u_first the absolute
+ * index of the first.  Samples are finished once every channel's delayed
+ * intensity is known (after the dispersion sweep), or at close. */
+cdd_status cdd_stream_poll(cdd_server* server, int32_t stream_id, float* host_out,
+                           int64_t cap, int64_t* n, int64_t* u_first);
+/* End of stream: the tail is processed with zeros after the last sample and
+ * every I[u], u < total/n_int, becomes available (with partial coverage at
+ * the end, as cdd_dedisperse).  The stream's memory is returned to the
+ * budget once its last sample has been polled. */
+cdd_status cdd_stream_close(cdd_server* server, int32_t stream_id);
+/* Wait until every pushed block is finished. */
+cdd_status cdd_server_sync(cdd_server* server);
+cdd_status cdd_server_stats_get(cdd_server* server, cdd_server_stats* out);
+
+/* ---------------------------------------------------------------------
  * Stage timing.  When enabled, every call records a pair of HIP events on
  * its stream around each kernel it launches; cdd_profile_read waits for the
  * recorded events, returns the accumulated time per stage and starts over.

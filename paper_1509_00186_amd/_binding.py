@@ -60,6 +60,32 @@ class Profile(ctypes.Structure):
 STAGES = ("transpose", "delays", "block", "dsum")
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_streams", ctypes.c_int32),
+                ("queue_depth", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+class StreamDesc(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("nchan", ctypes.c_int32),
+                ("f_centre_mhz", ctypes.c_double), ("bw_mhz", ctypes.c_double),
+                ("dm", ctypes.c_double), ("fft_len", ctypes.c_int32), ("n_int", ctypes.c_int32),
+                ("max_block", ctypes.c_int64), ("phase_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("blocks_in", ctypes.c_int64), ("blocks_done", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("gaps", ctypes.c_int64),
+                ("admitted", ctypes.c_int64), ("refused", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("lat_p50_ms", ctypes.c_double),
+                ("lat_p99_ms", ctypes.c_double), ("lat_max_ms", ctypes.c_double),
+                ("data_s", ctypes.c_double), ("wall_s", ctypes.c_double),
+                ("hbm_used", ctypes.c_size_t), ("hbm_budget", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError("libcdd.so is not built (%s); run __graft_entry__.build()" % _LIB_PATH)
@@ -83,6 +109,18 @@ def _load():
     lib.cdd_profile_enable.restype = ctypes.c_int
     lib.cdd_profile_read.argtypes = [ctypes.POINTER(Profile)]
     lib.cdd_profile_read.restype = ctypes.c_int
+    lib.cdd_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    lib.cdd_server_destroy.argtypes = [vp]
+    lib.cdd_server_destroy.restype = None
+    lib.cdd_stream_open.argtypes = [vp, ctypes.POINTER(StreamDesc), ctypes.POINTER(i32)]
+    lib.cdd_stream_push.argtypes = [vp, i32, vp, i64, ctypes.c_uint64]
+    lib.cdd_stream_poll.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.cdd_stream_close.argtypes = [vp, i32]
+    lib.cdd_server_sync.argtypes = [vp]
+    lib.cdd_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    for f in ("cdd_server_create", "cdd_stream_open", "cdd_stream_push", "cdd_stream_poll",
+              "cdd_stream_close", "cdd_server_sync", "cdd_server_stats_get"):
+        getattr(lib, f).restype = ctypes.c_int
     lib.cdd_last_error.restype = ctypes.c_char_p
     lib.cdd_last_error.argtypes = []
     lib.cdd_status_str.restype = ctypes.c_char_p
@@ -249,6 +287,70 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             lib.cdd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Real-time serving (cdd_server_* / cdd_stream_*): host numpy blocks in,
+    aligned intensities out."""
+
+    def __init__(self, hbm_budget=0, max_streams=0, queue_depth=0):
+        o = ServerOpts()
+        o.hbm_budget, o.max_streams, o.queue_depth = int(hbm_budget), int(max_streams), \
+            int(queue_depth)
+        h = ctypes.c_void_p()
+        _check(lib.cdd_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def open(self, dtype, nchan, f_centre, bw, dm, n_int, max_block, fft_len=0, phase_mode=0):
+        d = StreamDesc()
+        d.dtype, d.nchan, d.f_centre_mhz, d.bw_mhz, d.dm = int(dtype), int(nchan), \
+            float(f_centre), float(bw), float(dm)
+        d.fft_len, d.n_int, d.max_block, d.phase_mode = int(fft_len), int(n_int), \
+            int(max_block), int(phase_mode)
+        sid = ctypes.c_int32()
+        _check(lib.cdd_stream_open(self._h, ctypes.byref(d), ctypes.byref(sid)))
+        return sid.value
+
+    def push(self, sid, block, seq):
+        """block: numpy [nsamp][nchan][2] int8 or [nsamp][nchan] complex64
+        (C-contiguous).  Returns the status (0, or -5 when the queue is full)."""
+        import numpy as np
+        b = np.ascontiguousarray(block)
+        st = lib.cdd_stream_push(self._h, int(sid), ctypes.c_void_p(b.ctypes.data),
+                                 int(b.shape[0]), ctypes.c_uint64(int(seq)))
+        if st not in (0, -5):
+            _check(st)
+        return st
+
+    def poll(self, sid, cap=1 << 20):
+        import numpy as np
+        out = np.empty(cap, dtype=np.float32)
+        n, u0 = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.cdd_stream_poll(self._h, int(sid), ctypes.c_void_p(out.ctypes.data), cap,
+                                   ctypes.byref(n), ctypes.byref(u0)))
+        return u0.value, out[:n.value].copy()
+
+    def close_stream(self, sid):
+        _check(lib.cdd_stream_close(self._h, int(sid)))
+
+    def sync(self):
+        _check(lib.cdd_server_sync(self._h))
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib.cdd_server_stats_get(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.cdd_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -22,7 +22,7 @@ int launch_transposed(const BeamPlan& p, const void* in, void* out, void* stream
   void* tok = nullptr;
   int e = stage_begin(stream, &tok);
   if (e) return e;
-  if ((e = launch_transpose(in, out, p.dtype, p.nsamp, p.nchan, stream))) return e;
+  if ((e = launch_transpose(in, out, p.dtype, p.nsamp, p.nchan, p.nsamp, stream))) return e;
   return stage_end(kStageTranspose, stream, tok);
 }
 
@@ -264,6 +264,7 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
           bb.xt = xt[b];
           bb.dms = tiles[b];
           bb.P = (float*)(ws + plan->ws_base[b] + plan->lay[b].p_off);
+          bb.co = offline_coords(plan->beams[b]);
           group.push_back(bb);
         }
         // longest work first

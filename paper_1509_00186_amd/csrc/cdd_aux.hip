@@ -17,7 +17,8 @@ namespace cdd {
 __global__ __launch_bounds__(256) void transpose_i8_kernel(const unsigned short* __restrict__ in,
                                                            unsigned short* __restrict__ out,
                                                            int64_t nsamp, int32_t nchan,
-                                                           int32_t tiles_c, int32_t in_aligned) {
+                                                           int32_t tiles_c, int32_t in_aligned,
+                                                           int64_t ostr) {
   __shared__ unsigned short tile[64][128 + 4];
   const int64_t bid = blockIdx.x;
   const int c0 = (int)(bid % tiles_c) * 128;
@@ -62,15 +63,15 @@ __global__ __launch_bounds__(256) void transpose_i8_kernel(const unsigned short*
           uint2 w;
           w.x = (unsigned)tile[tl + 0][c] | ((unsigned)tile[tl + 1][c] << 16);
           w.y = (unsigned)tile[tl + 2][c] | ((unsigned)tile[tl + 3][c] << 16);
-          if (((int64_t)cs * nsamp + ts) % 4 == 0) {
-            *(uint2*)(out + (int64_t)cs * nsamp + ts) = w;
+          if (((int64_t)cs * ostr + ts) % 4 == 0) {
+            *(uint2*)(out + (int64_t)cs * ostr + ts) = w;
             continue;
           }
         }
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (ts + q < nsamp) out[(int64_t)cs * nsamp + ts + q] = tile[tl + q][c];
+        if (ts + q < nsamp) out[(int64_t)cs * ostr + ts + q] = tile[tl + q][c];
     }
   }
 }
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(256) void transpose_i8_kernel(const unsigned short*
 __global__ __launch_bounds__(256) void transpose_c8_kernel(const float2* __restrict__ in,
                                                            float2* __restrict__ out,
                                                            int64_t nsamp, int32_t nchan,
-                                                           int32_t tiles_c) {
+                                                           int32_t tiles_c, int64_t ostr) {
   __shared__ float2 tile[64][65];
   const int64_t bid = blockIdx.x;
   const int c0 = (int)(bid % tiles_c) * 64;
@@ -95,12 +96,12 @@ __global__ __launch_bounds__(256) void transpose_c8_kernel(const float2* __restr
   for (int i = 0; i < 64; i += 4) {
     const int cs = c0 + ty + i;
     const int64_t ts = t0 + tx;
-    if (cs < nchan && ts < nsamp) out[(int64_t)cs * nsamp + ts] = tile[tx][ty + i];
+    if (cs < nchan && ts < nsamp) out[(int64_t)cs * ostr + ts] = tile[tx][ty + i];
   }
 }
 
 int launch_transpose(const void* in, void* out, int32_t dtype, int64_t nsamp, int32_t nchan,
-                     void* stream) {
+                     int64_t out_stride, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (dtype == CDD_CI8) {
     const int64_t tiles_c = (nchan + 127) / 128, tiles_t = (nsamp + 63) / 64;
@@ -108,13 +109,14 @@ int launch_transpose(const void* in, void* out, int32_t dtype, int64_t nsamp, in
     if (n <= 0 || n > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(transpose_i8_kernel, dim3((unsigned)n), dim3(256), 0, st,
                        (const unsigned short*)in, (unsigned short*)out, nsamp, nchan,
-                       (int32_t)tiles_c, (int32_t)(((uintptr_t)in & 7u) == 0));
+                       (int32_t)tiles_c, (int32_t)(((uintptr_t)in & 7u) == 0), out_stride);
   } else {
     const int64_t tiles_c = (nchan + 63) / 64, tiles_t = (nsamp + 63) / 64;
     const int64_t n = tiles_c * tiles_t;
     if (n <= 0 || n > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(transpose_c8_kernel, dim3((unsigned)n), dim3(256), 0, st,
-                       (const float2*)in, (float2*)out, nsamp, nchan, (int32_t)tiles_c);
+                       (const float2*)in, (float2*)out, nsamp, nchan, (int32_t)tiles_c,
+                       out_stride);
   }
   return (int)hipGetLastError();
 }
@@ -159,23 +161,26 @@ __global__ __launch_bounds__(64 * G) void dsum_kernel(const float* __restrict__ 
                                                       const int32_t* __restrict__ d,
                                                       float* __restrict__ I,
                                                       int32_t* __restrict__ cov, int32_t nchan,
-                                                      int64_t t_int, int64_t out_stride) {
+                                                      int64_t p_stride, int64_t p_dm_stride,
+                                                      int64_t src_lim, int64_t u_begin,
+                                                      int64_t u_count, int64_t out_stride) {
   __shared__ float ps[G][64];
   __shared__ int32_t pn[G][64];
   const int i = blockIdx.y;
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int64_t u = (int64_t)blockIdx.x * 64 + lane;
-  const float* Pi = P + (int64_t)i * nchan * t_int;
+  const int64_t uo = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t u = u_begin + uo;
+  const float* Pi = P + (int64_t)i * p_dm_stride;
   const int32_t* di = d + (int64_t)i * nchan;
   const int per = (nchan + G - 1) / G;
   const int c_lo = g * per, c_hi = min(nchan, c_lo + per);
   float acc = 0.f;
   int32_t n = 0;
-  if (u < t_int) {
+  if (uo < u_count) {
     for (int c = c_lo; c < c_hi; ++c) {
       const int64_t src = u + di[c];
-      if (src < t_int) {
-        acc += Pi[(int64_t)c * t_int + src];
+      if (src < src_lim) {
+        acc += Pi[(int64_t)c * p_stride + src];
         ++n;
       }
     }
@@ -183,7 +188,7 @@ __global__ __launch_bounds__(64 * G) void dsum_kernel(const float* __restrict__ 
   ps[g][lane] = acc;
   pn[g][lane] = n;
   __syncthreads();
-  if (g == 0 && u < t_int) {
+  if (g == 0 && uo < u_count) {
     float s = ps[0][lane];
     int32_t m = pn[0][lane];
 #pragma unroll
@@ -191,24 +196,32 @@ __global__ __launch_bounds__(64 * G) void dsum_kernel(const float* __restrict__ 
       s += ps[k][lane];
       m += pn[k][lane];
     }
-    I[(int64_t)i * out_stride + u] = s;
-    if (cov) cov[(int64_t)i * out_stride + u] = m;
+    I[(int64_t)i * out_stride + uo] = s;
+    if (cov) cov[(int64_t)i * out_stride + uo] = m;
   }
+}
+
+int launch_dsum_range(int nchan, int ndm, const float* P, int64_t p_stride, int64_t p_dm_stride,
+                      int64_t src_lim, int64_t u_begin, int64_t u_count, const int32_t* d,
+                      float* I, int32_t* cov, int64_t out_stride, void* stream) {
+  if (u_count <= 0) return 0;
+  const int64_t nb = (u_count + 63) / 64;
+  if (nb > 0x7fffffffLL || ndm < 1 || ndm > 65535) return (int)hipErrorInvalidValue;
+  dim3 grid((unsigned)nb, (unsigned)ndm);
+  hipStream_t st = (hipStream_t)stream;
+  if (nchan >= 64)
+    hipLaunchKernelGGL(dsum_kernel<8>, grid, dim3(512), 0, st, P, d, I, cov, nchan, p_stride,
+                       p_dm_stride, src_lim, u_begin, u_count, out_stride);
+  else
+    hipLaunchKernelGGL(dsum_kernel<1>, grid, dim3(64), 0, st, P, d, I, cov, nchan, p_stride,
+                       p_dm_stride, src_lim, u_begin, u_count, out_stride);
+  return (int)hipGetLastError();
 }
 
 int launch_dsum(const BeamPlan& p, int ndm, const float* P, const int32_t* d, float* I,
                 int32_t* cov, int64_t out_stride, void* stream) {
-  const int64_t nb = (p.t_int + 63) / 64;
-  if (nb <= 0 || nb > 0x7fffffffLL || ndm < 1 || ndm > 65535) return (int)hipErrorInvalidValue;
-  dim3 grid((unsigned)nb, (unsigned)ndm);
-  hipStream_t st = (hipStream_t)stream;
-  if (p.nchan >= 64)
-    hipLaunchKernelGGL(dsum_kernel<8>, grid, dim3(512), 0, st, P, d, I, cov, p.nchan, p.t_int,
-                       out_stride);
-  else
-    hipLaunchKernelGGL(dsum_kernel<1>, grid, dim3(64), 0, st, P, d, I, cov, p.nchan, p.t_int,
-                       out_stride);
-  return (int)hipGetLastError();
+  return launch_dsum_range(p.nchan, ndm, P, p.t_int, (int64_t)p.nchan * p.t_int, p.t_int, 0,
+                           p.t_int, d, I, cov, out_stride, stream);
 }
 
 }  // namespace cdd

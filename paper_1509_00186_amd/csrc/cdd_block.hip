@@ -366,22 +366,35 @@ static int needs_exact_division(const BeamPlan& p, const DmTile& dms) {
   return exact_division_needed(p, dmax);
 }
 
-// Launch description of one beam for the offline (whole-record) form.
-static BlockArgs offline_args(const BeamPlan& p, const void* xt, const DmTile& dms, float* P,
-                              void* vout) {
+Coords offline_coords(const BeamPlan& p) {
+  Coords co;
+  co.x_stride = p.nsamp;
+  co.x_len = p.nsamp;
+  co.load_off = p.nfront;
+  co.p_stride = p.t_int;
+  co.p_dm_stride = (int64_t)p.nchan * p.t_int;
+  co.u_lim = p.t_int;
+  co.v_stride = p.nsamp;
+  co.o_lim = p.nsamp;
+  co.nblocks = p.nblocks;
+  return co;
+}
+
+static BlockArgs make_args(const BeamPlan& p, const Coords& co, const void* xt, const DmTile& dms,
+                           float* P, void* vout) {
   BlockArgs a{};
   a.x = xt;
   a.P = P;
   a.vout = (float2*)vout;
-  a.x_stride = p.nsamp;
-  a.x_len = p.nsamp;
-  a.load_off = p.nfront;
-  a.p_stride = p.t_int;
-  a.p_dm_stride = (int64_t)p.nchan * p.t_int;
-  a.u_lim = p.t_int;
-  a.v_stride = p.nsamp;
-  a.o_lim = p.nsamp;
-  a.nblocks = p.nblocks;
+  a.x_stride = co.x_stride;
+  a.x_len = co.x_len;
+  a.load_off = co.load_off;
+  a.p_stride = co.p_stride;
+  a.p_dm_stride = co.p_dm_stride;
+  a.u_lim = co.u_lim;
+  a.v_stride = co.v_stride;
+  a.o_lim = co.o_lim;
+  a.nblocks = co.nblocks;
   a.item0 = 0;
   a.nchan = p.nchan;
   a.M = p.M;
@@ -468,7 +481,7 @@ int block_variants(int N) { return block_supported(N) ? kVariants[log2i(N) - 8] 
 int launch_block(const BeamPlan& p, const void* xt, const DmTile& dms, float* P, void* vout,
                  void* stream) {
   if (dms.ndm < 1 || dms.ndm > kMaxDmTile) return (int)hipErrorInvalidValue;
-  const BlockArgs a = offline_args(p, xt, dms, P, vout);
+  const BlockArgs a = make_args(p, offline_coords(p), xt, dms, P, vout);
   const int v = p.variant;
   switch (p.N) {
     case 256: return launch_block_t<256, 0>(a, stream);
@@ -503,9 +516,9 @@ int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_t
     const BeamPlan& p = *beams[b].p;
     if (p.N != N || beams[b].dms.ndm < 1 || beams[b].dms.ndm > kMaxDmTile)
       return (int)hipErrorInvalidValue;
-    ht[b] = offline_args(p, beams[b].xt, beams[b].dms, beams[b].P, nullptr);
+    ht[b] = make_args(p, beams[b].co, beams[b].xt, beams[b].dms, beams[b].P, nullptr);
     ht[b].item0 = total;
-    total += (int64_t)p.nchan * p.nblocks;
+    total += (int64_t)p.nchan * beams[b].co.nblocks;
   }
   if (total > 0xffffffffLL) return (int)hipErrorInvalidValue;
   BlockArgs* dt = (BlockArgs*)dev_tab;

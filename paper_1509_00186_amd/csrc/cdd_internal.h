@@ -65,8 +65,22 @@ struct DmTile {
   double dm[kMaxDmTile];
 };
 
+// Launch-relative coordinates of one beam: block k reads input samples
+// k*M - load_off + n (valid in [0, x_len), channel stride x_stride), writes
+// integrated samples u = k*M/n_int + ul (u < u_lim) to
+// P[dmi*p_dm_stride + c*p_stride + u] and voltages o = k*M + m (o < o_lim) to
+// vout[c*v_stride + o].
+struct Coords {
+  int64_t x_stride = 0, x_len = 0, load_off = 0;
+  int64_t p_stride = 0, p_dm_stride = 0, u_lim = 0;
+  int64_t v_stride = 0, o_lim = 0;
+  int64_t nblocks = 0;
+};
+Coords offline_coords(const BeamPlan& p);
+
+// Time-major [nsamp][nchan] -> out[c*out_stride + t].
 int launch_transpose(const void* in, void* out, int32_t dtype, int64_t nsamp,
-                     int32_t nchan, void* stream);
+                     int32_t nchan, int64_t out_stride, void* stream);
 int launch_block(const BeamPlan& p, const void* xt, const DmTile& dms,
                  float* P, void* vout, void* stream);
 // Batched form: beams that share one transform length, each with its DM
@@ -75,7 +89,8 @@ struct BatchBeam {
   const BeamPlan* p;
   const void* xt;    // channel-major input
   DmTile dms;
-  float* P;          // [ndm][nchan][t_int]
+  float* P;          // see Coords
+  Coords co;
 };
 size_t batch_table_bytes(int nbeams);
 int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_tab,
@@ -83,6 +98,13 @@ int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_t
 int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream);
 int launch_dsum(const BeamPlan& p, int ndm, const float* P, const int32_t* d,
                 float* I, int32_t* cov, int64_t out_stride, void* stream);
+// General form: for u in [u_begin, u_begin + u_count),
+// I[i*out_stride + u - u_begin] = sum over c with u + d_c < src_lim of
+// P[i*p_dm_stride + c*p_stride + u + d_c].
+int launch_dsum_range(int nchan, int ndm, const float* P, int64_t p_stride,
+                      int64_t p_dm_stride, int64_t src_lim, int64_t u_begin,
+                      int64_t u_count, const int32_t* d, float* I, int32_t* cov,
+                      int64_t out_stride, void* stream);
 bool block_supported(int N);
 bool large_supported(int N);
 int64_t large_chunk_items(const BeamPlan& p);  // (channel, block) items per chunk
