@@ -36,7 +36,12 @@ K_DM_US = 4.148808e9       # cold-plasma constant, only to synthesise the pulses
 WORKLOADS = {
     2: "filterbank_32MHz_512ch_4s_int8_N8192_nint4_dm67.9",
     3: "filterbank_200MHz_4096ch_2s_int8_N8192_nint4_dm120",
+    5: "serving_8streams_16-32-200MHz_int8_dm5-300",
 }
+
+# Serving mix: (bandwidth MHz, channels, centre MHz) per stream.
+SERVING_MIX = [(16.0, 512, 610.0), (32.0, 512, 325.0), (200.0, 4096, 400.0), (16.0, 512, 610.0),
+               (32.0, 512, 325.0), (200.0, 4096, 400.0), (32.0, 512, 325.0), (16.0, 512, 610.0)]
 
 
 def block_flops(N: int, M: int) -> float:
@@ -133,6 +138,73 @@ def dm_trials(cdd, torch, vd, b, info, reps: int = 3):
             "speedup": round(t_loop / t_batch, 3), "rel_l2_batched_vs_loop": diff}
 
 
+def serving(cdd, seconds: float, paced: bool):
+    """Eight streams (16/32/200 MHz, DM log-uniform in [5, 300]) pushed in
+    blocks of 2^20..2^24 samples (all channels) -- at their true sample rates
+    when paced, as fast as the server accepts them otherwise.  Each stream
+    cycles through 0.5 s of seeded int8 data."""
+    import threading
+    import synth
+    rng = np.random.default_rng(synth.SEED_BASE + 5)
+    sv = cdd.Server(hbm_budget=64 << 30)
+    streams = []
+    for k, (bw, nchan, fc) in enumerate(SERVING_MIX):
+        dm = float(np.exp(rng.uniform(np.log(5.0), np.log(300.0))))
+        per_chan = [(1 << int(e)) // nchan for e in rng.integers(20, 25, size=64)]
+        rate = bw / nchan * 1e6                          # samples/s per channel
+        nbuf = int(0.5 * rate)
+        beam = synth.Beam(fc, bw, nchan, nbuf, dm)
+        data = synth.noise_int8(np.random.default_rng(synth.SEED_BASE + 50 + k), nbuf, nchan,
+                                beam.sigma)
+        sid = sv.open(0, nchan, fc, bw, dm, 4, max(per_chan))
+        streams.append(dict(sid=sid, data=data, sizes=per_chan, rate=rate, dm=dm, pos=0, seq=0,
+                            next_t=0.0, pushed=0))
+    t0 = time.perf_counter()
+    deadline = t0 + seconds
+    polled = [0] * len(streams)
+    while True:
+        now = time.perf_counter()
+        if now >= deadline:
+            break
+        did = False
+        for i, st in enumerate(streams):
+            if paced and now - t0 < st["next_t"]:
+                continue
+            n = st["sizes"][st["seq"] % len(st["sizes"])]
+            buf = st["data"]
+            if st["pos"] + n > len(buf):
+                st["pos"] = 0
+            blk = buf[st["pos"]:st["pos"] + n]
+            if sv.push(st["sid"], blk, st["seq"]) == 0:
+                st["pos"] += n
+                st["seq"] += 1
+                st["pushed"] += n
+                st["next_t"] += n / st["rate"]
+                did = True
+        for i, st in enumerate(streams):
+            polled[i] += len(sv.poll(st["sid"])[1])
+        if not did:
+            time.sleep(0.0002)
+    sv.sync()
+    wall = time.perf_counter() - t0
+    stats = sv.stats()
+    for st in streams:
+        sv.close_stream(st["sid"])
+    sv.sync()
+    sv.close()
+    agg_rate = sum(st["rate"] * SERVING_MIX[i][1] for i, st in enumerate(streams))
+    done = sum(st["pushed"] * SERVING_MIX[i][1] for i, st in enumerate(streams))
+    return {"paced": paced, "seconds": round(wall, 2), "streams": len(streams),
+            "dms": [round(st["dm"], 2) for st in streams],
+            "blocks": stats["blocks_done"], "batches": stats["batches"],
+            "lat_p50_ms": round(stats["lat_p50_ms"], 3), "lat_p99_ms": round(stats["lat_p99_ms"], 3),
+            "lat_max_ms": round(stats["lat_max_ms"], 3),
+            "msamples_per_s": round(done / wall / 1e6, 1),
+            "realtime_msamples_per_s": round(agg_rate / 1e6, 1),
+            "x_realtime": round(done / wall / agg_rate, 2),
+            "hbm_used_gb": round(stats["hbm_used"] / 2**30, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +214,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dm-trials", action="store_true")
+    ap.add_argument("--seconds", type=float, default=10.0, help="serving run length (config 5)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -162,6 +235,17 @@ def main():
                           "bytes_written_per_launch": n, "launches": args.steps}))
         return
     import paper_1509_00186_amd as cdd
+
+    if args.config == 5:
+        paced = serving(cdd, args.seconds, paced=True)
+        burst = serving(cdd, max(2.0, args.seconds / 5), paced=False)
+        res = {"metric": "Msamples/s dedispersed (serving)", "value": burst["msamples_per_s"],
+               "unit": "Msamples/s", "n_gpus": 1, "steps": 0, "warmup": 0,
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f32", "data": "synthetic",
+               "config": {"workload": WORKLOADS[5]}, "paced": paced, "unpaced": burst}
+        print(json.dumps(res), flush=True)
+        return
 
     b, v = make_input(args.config)
     dev = torch.device("cuda:0")

@@ -141,6 +141,17 @@ cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp, in
       return fail(CDD_EINVAL, "workspace too small: need %zu bytes, got %zu", lay.total,
                   workspace ? ws_bytes : (size_t)0);
     if (!aligned256(workspace)) return fail(CDD_EINVAL, "workspace must be 256-byte aligned");
+    const int chunks = (int)std::min<int64_t>(4, p.nblocks / 4);
+    if (block_supported(p.N) && p.nchan > 1 && chunks >= 2) {
+      char* ws = (char*)workspace;
+      int e = run_pipelined(p, voltages, dm, ws + lay.xt_off,
+                            chan_intensity ? chan_intensity : (float*)(ws + lay.p_off),
+                            (int32_t*)(ws + lay.d_off), volt_out, intensity, coverage, chunks,
+                            stream);
+      if (e) return device_fail("pipelined launch", e);
+      clear_error();
+      return CDD_OK;
+    }
     DmTile tile;
     tile.ndm = 1;
     tile.dm[0] = dm;

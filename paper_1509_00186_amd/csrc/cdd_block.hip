@@ -480,8 +480,13 @@ int block_variants(int N) { return block_supported(N) ? kVariants[log2i(N) - 8] 
 
 int launch_block(const BeamPlan& p, const void* xt, const DmTile& dms, float* P, void* vout,
                  void* stream) {
+  return launch_block_co(p, offline_coords(p), xt, dms, P, vout, stream);
+}
+
+int launch_block_co(const BeamPlan& p, const Coords& co, const void* xt, const DmTile& dms,
+                    float* P, void* vout, void* stream) {
   if (dms.ndm < 1 || dms.ndm > kMaxDmTile) return (int)hipErrorInvalidValue;
-  const BlockArgs a = make_args(p, offline_coords(p), xt, dms, P, vout);
+  const BlockArgs a = make_args(p, co, xt, dms, P, vout);
   const int v = p.variant;
   switch (p.N) {
     case 256: return launch_block_t<256, 0>(a, stream);

@@ -83,6 +83,12 @@ int launch_transpose(const void* in, void* out, int32_t dtype, int64_t nsamp,
                      int32_t nchan, int64_t out_stride, void* stream);
 int launch_block(const BeamPlan& p, const void* xt, const DmTile& dms,
                  float* P, void* vout, void* stream);
+int launch_block_co(const BeamPlan& p, const Coords& co, const void* xt, const DmTile& dms,
+                    float* P, void* vout, void* stream);
+// One DM, block kernel, record split into time chunks with the layout change
+// and the aligned sums on an auxiliary stream (cdd_pipeline.hip).
+int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, float* P,
+                  int32_t* d, void* volt_out, float* I, int32_t* cov, int chunks, void* stream);
 // Batched form: beams that share one transform length, each with its DM
 // tile, in one persistent launch.
 struct BatchBeam {

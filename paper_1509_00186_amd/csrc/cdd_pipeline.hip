@@ -1,0 +1,130 @@
+// One-shot path with the memory-bound stages overlapped with compute.
+//
+// The fused block kernel is bound by vector ALU and LDS and leaves HBM mostly
+// idle, while the layout change and the aligned sum are HBM-bound.  The record
+// is split into time chunks: an auxiliary HIP stream changes the layout of
+// chunk i+1 while the caller's stream transforms chunk i, and sums every
+// output range whose delayed inputs are complete as soon as they are; events
+// order the two streams, and the caller's stream waits for the auxiliary one
+// at the end, so the call stays asynchronous and stream-ordered.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "cdd_internal.h"
+
+namespace cdd {
+
+namespace {
+constexpr int kEvents = 32;
+
+struct Aux {
+  hipStream_t s = nullptr;
+  hipEvent_t ev[kEvents];
+  int next = 0;
+};
+std::mutex g_aux_mu;
+std::map<int, Aux> g_aux;
+
+hipEvent_t take(Aux& a) {
+  hipEvent_t e = a.ev[a.next];
+  a.next = (a.next + 1) % kEvents;
+  return e;
+}
+}  // namespace
+
+int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, float* P,
+                  int32_t* d, void* volt_out, float* I, int32_t* cov, int chunks, void* stream) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  Aux& ax = g_aux[dev];
+  if (!ax.s) {
+    if ((e = hipStreamCreateWithFlags(&ax.s, hipStreamNonBlocking)) != hipSuccess) return (int)e;
+    for (int i = 0; i < kEvents; ++i)
+      if ((e = hipEventCreateWithFlags(&ax.ev[i], hipEventDisableTiming)) != hipSuccess)
+        return (int)e;
+  }
+  hipStream_t S = (hipStream_t)stream, A = ax.s;
+  const size_t elem = p.dtype == CDD_CI8 ? 2 : 8;
+  const int C = chunks;
+  std::vector<int64_t> kb(C + 1), tr(C + 1);
+  for (int i = 0; i <= C; ++i) kb[i] = p.nblocks * i / C;
+  tr[0] = 0;
+  for (int i = 1; i <= C; ++i)
+    tr[i] = std::max(tr[i - 1],
+                     std::min<int64_t>(p.nsamp, kb[i] * p.M - p.nfront + p.N));
+  tr[C] = p.nsamp;
+  DmTile tile;
+  tile.ndm = 1;
+  tile.dm[0] = dm;
+  // fork: the auxiliary stream starts after everything already on the caller's
+  hipEvent_t e0 = take(ax);
+  if ((e = hipEventRecord(e0, S)) != hipSuccess) return (int)e;
+  if ((e = hipStreamWaitEvent(A, e0, 0)) != hipSuccess) return (int)e;
+  int err = 0;
+  void* tok = nullptr;
+  if ((err = stage_begin(A, &tok))) return err;
+  if ((err = launch_delays(p, tile, d, A))) return err;
+  if ((err = stage_end(kStageDelays, A, tok))) return err;
+  std::vector<hipEvent_t> evT(C), evB(C);
+  for (int i = 0; i < C; ++i) {
+    const int64_t rows = tr[i + 1] - tr[i];
+    if (rows > 0) {
+      if ((err = stage_begin(A, &tok))) return err;
+      if ((err = launch_transpose((const char*)voltages + tr[i] * p.nchan * elem,
+                                  xt + tr[i] * elem, p.dtype, rows, p.nchan, p.nsamp, A)))
+        return err;
+      if ((err = stage_end(kStageTranspose, A, tok))) return err;
+    }
+    evT[i] = take(ax);
+    if ((e = hipEventRecord(evT[i], A)) != hipSuccess) return (int)e;
+  }
+  // compute: chunk i of blocks once its rows are in place
+  const Coords full = offline_coords(p);
+  for (int i = 0; i < C; ++i) {
+    if ((e = hipStreamWaitEvent(S, evT[i], 0)) != hipSuccess) return (int)e;
+    const int64_t k0 = kb[i], nb = kb[i + 1] - kb[i];
+    if (nb > 0) {
+      Coords co = full;
+      co.load_off = p.nfront - k0 * p.M;
+      const int64_t u0 = k0 * (p.M / p.n_int);
+      co.u_lim = p.t_int - u0;
+      co.o_lim = p.nsamp - k0 * p.M;
+      co.nblocks = nb;
+      if ((err = stage_begin(S, &tok))) return err;
+      if ((err = launch_block_co(p, co, xt, tile, P + u0,
+                                 volt_out ? (char*)volt_out + k0 * p.M * 8 : nullptr, S)))
+        return err;
+      if ((err = stage_end(kStageBlock, S, tok))) return err;
+    }
+    evB[i] = take(ax);
+    if ((e = hipEventRecord(evB[i], S)) != hipSuccess) return (int)e;
+  }
+  // aligned sums: u is final once every channel's P[u + d_c] is computed
+  int64_t u_done = 0;
+  for (int i = 0; i < C; ++i) {
+    if ((e = hipStreamWaitEvent(A, evB[i], 0)) != hipSuccess) return (int)e;
+    int64_t upto = (i == C - 1) ? p.t_int
+                                : std::min<int64_t>(p.t_int, kb[i + 1] * (p.M / p.n_int) - p.d_max);
+    if (upto > u_done) {
+      if ((err = stage_begin(A, &tok))) return err;
+      if ((err = launch_dsum_range(p.nchan, 1, P, p.t_int, (int64_t)p.nchan * p.t_int, p.t_int,
+                                   u_done, upto - u_done, d, I + u_done,
+                                   cov ? cov + u_done : nullptr, p.t_int, A)))
+        return err;
+      if ((err = stage_end(kStageDsum, A, tok))) return err;
+      u_done = upto;
+    }
+  }
+  // join
+  hipEvent_t eA = take(ax);
+  if ((e = hipEventRecord(eA, A)) != hipSuccess) return (int)e;
+  if ((e = hipStreamWaitEvent(S, eA, 0)) != hipSuccess) return (int)e;
+  return 0;
+}
+
+}  // namespace cdd
