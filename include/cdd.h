@@ -89,7 +89,9 @@ typedef struct {
   int32_t phase_mode;      /* cdd_phase_mode                                */
   int32_t kernel_variant;  /* block-kernel schedule for this N; 0 = default,
                               1.. = alternatives (cdd_kernel_variants)     */
-  int32_t reserved[6];
+  int32_t autotune;        /* cdd_plan_create: beams with fft_len 0 get N and
+                              schedule from cdd_autotune (2^11 .. 2^14)    */
+  int32_t reserved[5];
 } cdd_opts;
 
 /* Plan figures for one beam (filled by cdd_query / cdd_plan_info). */
@@ -171,8 +173,9 @@ typedef struct {
 
 typedef struct cdd_plan cdd_plan;
 
-/* Create a plan (host work only; twiddle tables are uploaded on first
- * execute).  EINVAL as cdd_query for each beam; ENOMEM. */
+/* Create a plan (host work only, unless opts->autotune asks the autotuner
+ * for beams with fft_len 0; twiddle tables are uploaded on first execute).
+ * EINVAL as cdd_query for each beam; ENOMEM. */
 cdd_status cdd_plan_create(const cdd_beam* beams, int32_t nbeam,
                            const cdd_opts* opts, cdd_plan** out);
 /* Plan figures of one beam (ws_bytes is the whole plan's workspace). */
@@ -290,6 +293,27 @@ typedef struct {
 } cdd_profile;
 cdd_status cdd_profile_enable(int32_t on);  /* process-wide switch          */
 cdd_status cdd_profile_read(cdd_profile* out);
+
+/* ---------------------------------------------------------------------
+ * Autotuner: transform length and block-kernel schedule for a beam shape.
+ * Every N in [n_min, n_max] (powers of two; 0 = 2^11 and 2^14) for which the
+ * overlap fits, and every schedule compiled for that N, is timed on the
+ * current device on a random int8 record of the beam's shape (up to eight
+ * DM trials per work item); the fastest in input samples x DM trials per
+ * second wins.  Results are cached per device and shape in memory, and
+ * appended to the text file named by the environment variable CDD_TUNE_CACHE
+ * (read back on first use).  Allocates and frees its own device memory and
+ * waits for the device.  ENOTSUP for complex-float records.
+ * ------------------------------------------------------------------- */
+typedef struct {
+  int32_t fft_len;
+  int32_t kernel_variant;
+  double ms;               /* one launch over the timing record              */
+  double msamples_per_s;   /* input samples x DM trials per second           */
+} cdd_tune_result;
+cdd_status cdd_autotune(int32_t dtype, int32_t nchan, double f_centre_mhz, double bw_mhz,
+                        const double* host_dms, int32_t ndm, int32_t n_int,
+                        int32_t n_min, int32_t n_max, cdd_tune_result* best);
 
 /* ---------------------------------------------------------------------
  * Host-side helpers (no device needed)

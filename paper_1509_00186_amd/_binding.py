@@ -29,7 +29,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("explicit_plan", ctypes.c_int32), ("fft_len", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("nfront", ctypes.c_int32),
                 ("dm_const", ctypes.c_double), ("phase_mode", ctypes.c_int32),
-                ("kernel_variant", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("kernel_variant", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -86,6 +87,11 @@ class ServerStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("fft_len", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("msamples_per_s", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError("libcdd.so is not built (%s); run __graft_entry__.build()" % _LIB_PATH)
@@ -121,6 +127,9 @@ def _load():
     for f in ("cdd_server_create", "cdd_stream_open", "cdd_stream_push", "cdd_stream_poll",
               "cdd_stream_close", "cdd_server_sync", "cdd_server_stats_get"):
         getattr(lib, f).restype = ctypes.c_int
+    lib.cdd_autotune.argtypes = [i32, i32, f64, f64, ctypes.POINTER(f64), i32, i32, i32, i32,
+                                 ctypes.POINTER(TuneResult)]
+    lib.cdd_autotune.restype = ctypes.c_int
     lib.cdd_last_error.restype = ctypes.c_char_p
     lib.cdd_last_error.argtypes = []
     lib.cdd_status_str.restype = ctypes.c_char_p
@@ -151,9 +160,20 @@ def profile_read():
     return {name: (p.ms[i], p.count[i]) for i, name in enumerate(STAGES)}
 
 
-def make_opts(fft_len=0, overlap=None, nfront=None, dm_const=0.0, phase_mode=0, variant=0):
+def autotune(nchan, f_centre, bw, dms, n_int, n_min=0, n_max=0, dtype=CDD_CI8):
+    """cdd_autotune: best (fft_len, kernel_variant) for a beam shape."""
+    arr = (ctypes.c_double * len(dms))(*[float(x) for x in dms])
+    r = TuneResult()
+    _check(lib.cdd_autotune(int(dtype), int(nchan), float(f_centre), float(bw), arr, len(dms),
+                            int(n_int), int(n_min), int(n_max), ctypes.byref(r)))
+    return {k: getattr(r, k) for k, _ in r._fields_}
+
+
+def make_opts(fft_len=0, overlap=None, nfront=None, dm_const=0.0, phase_mode=0, variant=0,
+              autotune=0):
     o = Opts()
     o.kernel_variant = int(variant)
+    o.autotune = int(autotune)
     if overlap is not None or nfront is not None:
         o.explicit_plan = 1
         o.fft_len = int(fft_len)
@@ -245,7 +265,7 @@ class Plan:
     """
 
     def __init__(self, beams, dm_const=0.0, phase_mode=0, fft_len=0, overlap=None,
-                 nfront=None):
+                 nfront=None, autotune=False):
         import torch
         self._descs = (BeamDesc * len(beams))()
         self._keep = []
@@ -267,7 +287,7 @@ class Plan:
             d.host_dms, d.ndm, d.n_int = dms, len(b["dms"]), n_int
             d.fft_len = int(b.get("fft_len", fft_len))
             d.intensity, d.coverage = I.data_ptr(), cov.data_ptr()
-        o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode)
+        o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode, autotune=autotune)
         h = ctypes.c_void_p()
         _check(lib.cdd_plan_create(self._descs, len(beams), ctypes.byref(o), ctypes.byref(h)))
         self._h = h

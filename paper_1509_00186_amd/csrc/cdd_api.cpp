@@ -180,8 +180,20 @@ cdd_status cdd_plan_create(const cdd_beam* beams, int32_t nbeam, const cdd_opts*
         return fail(CDD_EINVAL, "beam %d: voltages or intensity is NULL", b);
       }
       BeamPlan p;
+      int32_t fft_len = d.fft_len;
+      cdd_opts o2 = opts ? *opts : cdd_opts{};
+      if (opts && opts->autotune && fft_len == 0 && !opts->explicit_plan &&
+          d.dtype == CDD_CI8 && d.host_dms && d.ndm > 0) {
+        cdd_tune_result tr;
+        cdd_status ts = cdd_autotune(d.dtype, d.nchan, d.f_centre_mhz, d.bw_mhz, d.host_dms,
+                                     d.ndm, d.n_int, 0, 0, &tr);
+        if (ts == CDD_OK) {
+          fft_len = tr.fft_len;
+          o2.kernel_variant = tr.kernel_variant;
+        }
+      }
       cdd_status s = make_plan(d.dtype, d.nsamp, d.nchan, d.f_centre_mhz, d.bw_mhz, d.host_dms,
-                               d.ndm, d.fft_len, d.n_int, opts, &p);
+                               d.ndm, fft_len, d.n_int, opts ? &o2 : nullptr, &p);
       if (s != CDD_OK) {
         std::string msg = cdd_last_error();
         delete pl;

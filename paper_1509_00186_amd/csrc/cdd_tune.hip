@@ -1,0 +1,193 @@
+// Autotuner: transform length and block-kernel schedule per beam shape.
+//
+// For a beam (channels, band, DM trials, integration) every valid
+// combination of N in [n_min, n_max] (powers of two, with the overlap
+// shorter than N) and compiled schedule for that N is timed on the device:
+// the fused block kernel (with up to eight DM trials per work item when the
+// beam has several) runs on a seeded random int8 record of the beam's shape,
+// once to warm up and three times timed with events.  The score is input
+// samples x DM trials per second, which weighs the work per block against
+// the overlap discarded per block (M = N - L).  Results are cached in memory
+// per device and shape, and in a text file when CDD_TUNE_CACHE names one.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "cdd_internal.h"
+
+namespace cdd {
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, cdd_tune_result> g_tune;
+bool g_file_loaded = false;
+
+std::string shape_key(int dev, int32_t dtype, int32_t nchan, double fc, double bw,
+                      const double* dms, int32_t ndm, int32_t n_int, int32_t n_min,
+                      int32_t n_max) {
+  hipDeviceProp_t prop;
+  char arch[64] = "gpu";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    std::snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    for (char* c = arch; *c; ++c)
+      if (*c == ':' || *c == ' ') *c = '_';
+  }
+  double dlo = dms[0], dhi = dms[0];
+  for (int i = 1; i < ndm; ++i) {
+    dlo = std::fmin(dlo, dms[i]);
+    dhi = std::fmax(dhi, dms[i]);
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s|t%d|c%d|f%.6f|b%.6f|dm%.4f:%.4f:%d|i%d|n%d:%d", arch, dtype,
+                nchan, fc, bw, dlo, dhi, ndm, n_int, n_min, n_max);
+  return buf;
+}
+
+void load_file() {
+  if (g_file_loaded) return;
+  g_file_loaded = true;
+  const char* path = std::getenv("CDD_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[256];
+  cdd_tune_result r;
+  while (std::fscanf(f, "%255s %d %d %lf %lf", key, &r.fft_len, &r.kernel_variant, &r.ms,
+                     &r.msamples_per_s) == 5)
+    g_tune[key] = r;
+  std::fclose(f);
+}
+
+void append_file(const std::string& key, const cdd_tune_result& r) {
+  const char* path = std::getenv("CDD_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %.6f %.3f\n", key.c_str(), r.fft_len, r.kernel_variant, r.ms,
+               r.msamples_per_s);
+  std::fclose(f);
+}
+
+__global__ void fill_random_i8(unsigned short* x, int64_t n, unsigned seed) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  unsigned h = (unsigned)i * 2654435761u ^ seed;
+  h ^= h >> 13;
+  h *= 0x5bd1e995u;
+  h ^= h >> 15;
+  // two signed bytes of moderate amplitude
+  const int a = (int)(h & 63) - 32, b = (int)((h >> 8) & 63) - 32;
+  x[i] = (unsigned short)((a & 0xff) | ((b & 0xff) << 8));
+}
+
+}  // namespace
+}  // namespace cdd
+
+using namespace cdd;
+
+extern "C" cdd_status cdd_autotune(int32_t dtype, int32_t nchan, double f_centre_mhz,
+                                   double bw_mhz, const double* host_dms, int32_t ndm,
+                                   int32_t n_int, int32_t n_min, int32_t n_max,
+                                   cdd_tune_result* best) {
+  if (!best || !host_dms || ndm < 1) return fail(CDD_EINVAL, "NULL argument or no DM");
+  if (dtype != CDD_CI8) return fail(CDD_ENOTSUP, "the autotuner times int8 records");
+  if (n_min <= 0) n_min = 1 << 11;
+  if (n_max <= 0) n_max = 1 << 14;
+  n_max = std::min(n_max, 16384);
+  if (n_min > n_max) return fail(CDD_EINVAL, "n_min > n_max");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(CDD_EDEVICE, "%s", hipGetErrorString(e));
+  const std::string key =
+      shape_key(dev, dtype, nchan, f_centre_mhz, bw_mhz, host_dms, ndm, n_int, n_min, n_max);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_file();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      *best = it->second;
+      clear_error();
+      return CDD_OK;
+    }
+  }
+  // synthetic record: eight blocks of the longest candidate, at most 256 MiB
+  const int64_t cap_samples = std::max<int64_t>(1, ((int64_t)256 << 20) / (2LL * nchan));
+  const int64_t T = std::min<int64_t>((int64_t)8 * n_max, cap_samples);
+  const int tile_n = std::min<int>(ndm, 8);
+  DmTile tile;
+  tile.ndm = tile_n;
+  for (int i = 0; i < tile_n; ++i) tile.dm[i] = host_dms[i * ndm / tile_n];
+  unsigned short* x = nullptr;
+  float* P = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  cdd_tune_result win{};
+  win.msamples_per_s = -1;
+  cdd_status status = CDD_OK;
+  do {
+    if ((e = hipMalloc(&x, (size_t)T * nchan * 2)) != hipSuccess) break;
+    if ((e = hipMalloc(&P, (size_t)tile_n * nchan * (T / n_int + 1) * 4)) != hipSuccess) break;
+    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) break;
+    if ((e = hipEventCreate(&a)) != hipSuccess) break;
+    if ((e = hipEventCreate(&b)) != hipSuccess) break;
+    const int64_t n = T * nchan;
+    hipLaunchKernelGGL(fill_random_i8, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n,
+                       0x9e3779b9u);
+    for (int N = n_min; N <= n_max; N *= 2) {
+      cdd_opts o{};
+      BeamPlan p;
+      if (make_plan(dtype, T, nchan, f_centre_mhz, bw_mhz, host_dms, ndm, N, n_int, &o, &p) !=
+          CDD_OK)
+        continue;  // DM too large for this N
+      for (int v = 0; v < block_variants(N); ++v) {
+        p.variant = v;
+        int err = launch_block(p, x, tile, P, nullptr, st);  // warm up (and twiddles)
+        if (err) {
+          e = (hipError_t)err;
+          break;
+        }
+        (void)hipEventRecord(a, st);
+        for (int r = 0; r < 3; ++r) launch_block(p, x, tile, P, nullptr, st);
+        (void)hipEventRecord(b, st);
+        if ((e = hipEventSynchronize(b)) != hipSuccess) break;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        ms /= 3.0f;
+        const double rate = (double)nchan * T * tile_n / (ms * 1e-3) / 1e6;
+        if (rate > win.msamples_per_s) {
+          win.fft_len = N;
+          win.kernel_variant = v;
+          win.ms = ms;
+          win.msamples_per_s = rate;
+        }
+      }
+      if (e != hipSuccess) break;
+    }
+  } while (false);
+  if (e != hipSuccess)
+    status = fail(e == hipErrorOutOfMemory ? CDD_ENOMEM : CDD_EDEVICE, "autotune: %s",
+                  hipGetErrorString(e));
+  else if (win.msamples_per_s < 0)
+    status = fail(CDD_EINVAL, "no transform length in [%d, %d] fits this DM", n_min, n_max);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (st) (void)hipStreamDestroy(st);
+  if (x) (void)hipFree(x);
+  if (P) (void)hipFree(P);
+  if (status != CDD_OK) return status;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = win;
+    append_file(key, win);
+  }
+  *best = win;
+  clear_error();
+  return CDD_OK;
+}

@@ -333,3 +333,26 @@ def test_dm_tiles_beyond_one_launch():
                          nfront=info["nfront"])
         assert rel_l2(plan.I[0][i].cpu().numpy(), o["I"]) <= TOL_I
     plan.close()
+
+
+def test_autotuner_picks_a_valid_plan_and_plan_uses_it():
+    import torch
+    cdd = _cdd()
+    fcen, nchan, df, dms = 325.0, 32, 0.0625, [60.0, 64.0, 68.0]
+    r = cdd.autotune(nchan, fcen, nchan * df, dms, 4)
+    flush("autotune: %s" % r)
+    assert r["fft_len"] in (2048, 4096, 8192, 16384) and r["msamples_per_s"] > 0
+    assert 0 <= r["kernel_variant"] < cdd.lib.cdd_kernel_variants(r["fft_len"])
+    assert cdd.autotune(nchan, fcen, nchan * df, dms, 4) == r      # cached
+    v = _beam_int8(120, 20_000, nchan, fcen, nchan * df, 64.0)
+    plan = cdd.Plan([dict(voltages=to_dev(v), f_centre=fcen, bw=nchan * df, dms=dms, n_int=4)],
+                    autotune=True)
+    info = plan.info(0)
+    assert info["fft_len"] == r["fft_len"]
+    plan.execute()
+    torch.cuda.synchronize()
+    for i, dm in enumerate(dms):
+        o = O.dedisperse(v, fcen, nchan * df, dm, 4, fft_len=info["fft_len"],
+                         overlap=info["overlap"], nfront=info["nfront"])
+        assert rel_l2(plan.I[0][i].cpu().numpy(), o["I"]) <= TOL_I
+    plan.close()
