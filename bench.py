@@ -273,10 +273,14 @@ def main():
     duration_s = b.nsamp / (b.bw / b.nchan * 1e6)
     blk_ms, blk_n = stages["block"]
     blk_avg = blk_ms / max(blk_n, 1)
-    flops = b.nchan * info["nblocks"] * block_flops(info["fft_len"], info["step"])
+    # the one-shot call may split the blocks over several launches (time
+    # chunks overlapped with the layout change): per-launch figures are the
+    # step's totals divided by the launches per step
+    per_step = max(1, round(blk_n / args.steps))
+    flops = b.nchan * info["nblocks"] * block_flops(info["fft_len"], info["step"]) / per_step
     achieved = flops / (blk_avg * 1e-3) / 1e12
     traffic = measured_traffic("block_kernel", WORKLOADS[args.config])
-    alg_bytes = b.nchan * b.nsamp * 2 + b.nchan * info["t_int"] * 4
+    alg_bytes = (b.nchan * b.nsamp * 2 + b.nchan * info["t_int"] * 4) / per_step
     res = {
         "metric": "Msamples/s dedispersed",
         "value": round(value, 1),
@@ -302,8 +306,9 @@ def main():
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "traffic": traffic,
                      "avg_ms": round(blk_avg, 4),
-                     "alg_flops_per_launch": flops,
-                     "alg_hbm_bytes_per_launch": alg_bytes,
+                     "launches_per_step": per_step,
+                     "alg_flops_per_launch": round(flops),
+                     "alg_hbm_bytes_per_launch": round(alg_bytes),
                      "alg_hbm_frac": round(alg_bytes / (blk_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
         "gflops_paper_eq5": round(flops / (blk_avg * 1e-3) / 1e9, 1),
     }

@@ -319,12 +319,15 @@ int issue_batch(cdd_server* sv, BatchRec& br) {
 }
 
 // Completed batches: hand results to the streams, free slots, latencies.
+// Batches are taken round the ring from the oldest (the entry after the last
+// issued one) and in issue order only, so a stream's intensities are appended
+// in time order even when several batches complete between two visits.
 void reap(cdd_server* sv, bool wait) {
-  for (int i = 0; i < kBatchRing; ++i) {
-    BatchRec& br = sv->ring[i];
+  for (int j = 0; j < kBatchRing; ++j) {
+    BatchRec& br = sv->ring[(sv->ring_next + j) % kBatchRing];
     if (!br.busy) continue;
     hipError_t q = wait ? hipEventSynchronize(br.done) : hipEventQuery(br.done);
-    if (q == hipErrorNotReady) continue;
+    if (q == hipErrorNotReady) break;
     if (q != hipSuccess) {
       sv->thread_error = hipGetErrorString(q);
       br.busy = false;
