@@ -163,8 +163,10 @@ __device__ __forceinline__ void load_block(float2* v, const BlockArgs& a, int c,
           const unsigned short w = __builtin_amdgcn_raw_buffer_load_b16(rs, t * ES, soff, 0);
           v[b * R + r] = make_float2((float)(signed char)(w & 0xff), (float)(signed char)(w >> 8));
         } else {
-          const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, t * ES, soff, 0);
-          v[b * R + r] = make_float2(__builtin_bit_cast(float, w[0]), __builtin_bit_cast(float, w[1]));
+          // the whole 64-bit result reinterpreted at once: indexing its two
+          // halves separately compiles to a single 32-bit load here
+          v[b * R + r] =
+              __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, t * ES, soff, 0));
         }
       }
     }

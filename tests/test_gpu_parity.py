@@ -317,6 +317,28 @@ def test_persistent_launch_several_beams_same_length():
     plan.close()
 
 
+def test_persistent_launch_mixed_sample_types():
+    """An int8 beam and a complex-float beam of the same transform length in
+    one persistent launch, each against the oracle."""
+    import torch
+    cdd = _cdd()
+    v0 = _beam_int8(75, 9_000, 16, 325.0, 1.0, 67.9)
+    v1 = _beam_int8(76, 8_000, 4, 325.0, 0.25, 30.0)
+    x1 = (v1[..., 0].astype(np.float32) + 1j * v1[..., 1]).astype(np.complex64)
+    raw = [(v0, 325.0, 1.0, [67.9]), (x1, 325.0, 0.25, [30.0, 31.0])]
+    plan = cdd.Plan([dict(voltages=to_dev(v), f_centre=f, bw=bw, dms=dms, n_int=4, fft_len=2048)
+                     for (v, f, bw, dms) in raw])
+    plan.execute()
+    torch.cuda.synchronize()
+    for bi, (v, fcen, bw, dms) in enumerate(raw):
+        info = plan.info(bi)
+        for i, dm in enumerate(dms):
+            o = O.dedisperse(v, fcen, bw, dm, 4, fft_len=2048, overlap=info["overlap"],
+                             nfront=info["nfront"])
+            assert rel_l2(plan.I[bi][i].cpu().numpy(), o["I"]) <= TOL_I, (bi, i)
+    plan.close()
+
+
 def test_dm_tiles_beyond_one_launch():
     """More DM trials than one launch holds (70 > 64): two rounds."""
     import torch

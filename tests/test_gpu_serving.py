@@ -69,6 +69,26 @@ def test_stream_equals_whole_record_and_oracle():
     assert st["lat_p99_ms"] > 0
 
 
+@pytest.mark.parametrize("cf", [0, 1])
+def test_narrow_stream_alone_matches_oracle(cf):
+    """Four narrow channels, int8 or complex float, pushed in ragged blocks."""
+    cdd = _cdd()
+    fcen, nchan, df, nsamp, dm, N = 325.0, 4, 0.0625, 20_000, 30.0, 2048
+    v = _beam_int8(103, nsamp, nchan, fcen, nchan * df, dm)
+    if cf:
+        v = (v[..., 0].astype(np.float32) + 1j * v[..., 1]).astype(np.complex64)
+    flush(f"narrow stream cf={cf}")
+    sv = cdd.Server()
+    sid = sv.open(cf, nchan, fcen, nchan * df, dm, 4, 3000, N)
+    u0, I = _stream_all(sv, sid, v, _sizes(np.random.default_rng(7), nsamp, 200, 3000))
+    sv.close()
+    q = cdd.query(cf, nsamp, nchan, fcen, nchan * df, dm, N, 4)
+    o = O.dedisperse(v, fcen, nchan * df, dm, 4, fft_len=N, overlap=q["overlap"],
+                     nfront=q["nfront"])
+    assert u0 == 0 and len(I) == len(o["I"])
+    assert rel_l2(I, o["I"]) <= 1e-4, rel_l2(I, o["I"])
+
+
 def test_stream_same_alone_and_in_a_mix():
     cdd = _cdd()
     specs = [(325.0, 16, 0.0625, 30_000, 67.9, 2048, 0),
