@@ -283,7 +283,8 @@ cdd_status cdd_server_stats_get(cdd_server* server, cdd_server_stats* out);
  * Stage timing.  When enabled, every call records a pair of HIP events on
  * its stream around each kernel it launches; cdd_profile_read waits for the
  * recorded events, returns the accumulated time per stage and starts over.
- * Stages: 0 layout change (time-major -> channel-major), 1 channel delays,
+ * Stages: 0 layout change (time-major -> channel-major), 1 channel delays
+ * (and, with one DM, the per-channel chirp table of the block kernel),
  * 2 fused FFT/chirp/IFFT/detect/integrate block kernel, 3 delay-aligned sum.
  * ------------------------------------------------------------------- */
 #define CDD_NSTAGES 4

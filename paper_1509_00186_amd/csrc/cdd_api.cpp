@@ -46,10 +46,17 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
   int32_t* d = (int32_t*)(ws + lay.d_off);
   if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
   if ((e = launch_delays(p, tile, d, stream))) return device_fail("delay launch", e);
+  void* H = nullptr;
+  if (block_supported(p.N) && tile.ndm == 1) {
+    if (lay.h_bytes < chirp_table_bytes(p)) return fail(CDD_EINTERNAL, "no chirp table space");
+    H = ws + lay.h_off;
+    if ((e = launch_chirp_table(p, tile.dm[0], H, stream)))
+      return device_fail("chirp table launch", e);
+  }
   if ((e = stage_end(kStageDelays, stream, tok))) return device_fail("event record", e);
   if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
   if (block_supported(p.N)) {
-    if ((e = launch_block(p, xt, tile, P, volt_out, stream)))
+    if ((e = launch_block(p, xt, tile, P, volt_out, H, stream)))
       return device_fail("block kernel launch", e);
   } else {
     // long transforms: one DM trial at a time through the four-step kernels
@@ -136,7 +143,7 @@ cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp, in
     if (s != CDD_OK) return s;
     if (!block_supported(p.N) && !large_supported(p.N))
       return fail(CDD_ENOTSUP, "fft_len %d is not supported by this build", p.N);
-    WsLayout lay = ws_layout(p, 1, true);
+    WsLayout lay = ws_layout(p, 1, true, true);
     if (!workspace || ws_bytes < lay.total)
       return fail(CDD_EINVAL, "workspace too small: need %zu bytes, got %zu", lay.total,
                   workspace ? ws_bytes : (size_t)0);
@@ -146,8 +153,8 @@ cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp, in
       char* ws = (char*)workspace;
       int e = run_pipelined(p, voltages, dm, ws + lay.xt_off,
                             chan_intensity ? chan_intensity : (float*)(ws + lay.p_off),
-                            (int32_t*)(ws + lay.d_off), volt_out, intensity, coverage, chunks,
-                            stream);
+                            (int32_t*)(ws + lay.d_off), ws + lay.h_off, volt_out, intensity,
+                            coverage, chunks, stream);
       if (e) return device_fail("pipelined launch", e);
       clear_error();
       return CDD_OK;

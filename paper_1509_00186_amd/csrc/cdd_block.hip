@@ -5,7 +5,9 @@
 //   forward FFT: Stockham autosort radix passes, butterflies in registers,
 //                exchanges through LDS (real and imaginary halves in turn)
 //   chirp:       exp(-2 pi i q_j)/N per bin, q_j from Eq. 3 evaluated in FP64
-//                and reduced to [-1/2, 1/2] turns before an FP32 sin/cos
+//                and reduced to [-1/2, 1/2] turns; with one DM it is read
+//                from a per-channel table built once per call (FP64 sin/cos),
+//                with several it is formed in the kernel (FP32 sin/cos)
 //   inverse FFT: the same passes in reverse radix order, conjugate twiddles;
 //                its first pass consumes the forward result in registers
 //   epilogue:    keep samples [nfront, nfront + M), |y|^2, sum n_int samples
@@ -43,14 +45,21 @@ template <> struct SchedFor<1024, 0> { using type = Sched<1024, 64, 16, 16, 4, 1
 template <> struct SchedFor<2048, 0> { using type = Sched<2048, 128, 16, 16, 8, 1>; };
 template <> struct SchedFor<4096, 0> { using type = Sched<4096, 256, 16, 16, 16, 1, true, false, 3>; };
 template <> struct SchedFor<4096, 1> { using type = Sched<4096, 256, 16, 16, 16, 1, false, false, 2>; };
-template <> struct SchedFor<8192, 0> { using type = Sched<8192, 512, 16, 16, 16, 2, true, true, 4>; };
-template <> struct SchedFor<8192, 1> { using type = Sched<8192, 512, 16, 16, 16, 2, true, true, 6>; };
+template <> struct SchedFor<4096, 2> { using type = Sched<4096, 256, 16, 16, 16, 1, true, true, 3>; };
+template <> struct SchedFor<4096, 3> { using type = Sched<4096, 128, 16, 16, 16, 1, true, true, 3>; };
+template <> struct SchedFor<8192, 0> { using type = Sched<8192, 256, 16, 16, 32, 1, true, true, 3>; };
+template <> struct SchedFor<8192, 1> { using type = Sched<8192, 512, 16, 16, 16, 2, true, true, 4>; };
 template <> struct SchedFor<8192, 2> { using type = Sched<8192, 512, 16, 16, 16, 2, true, false, 6>; };
 template <> struct SchedFor<8192, 3> { using type = Sched<8192, 512, 16, 16, 16, 2, false, true, 4>; };
-template <> struct SchedFor<8192, 4> { using type = Sched<8192, 256, 16, 16, 32, 1, true, true, 3>; };
+template <> struct SchedFor<8192, 4> { using type = Sched<8192, 256, 32, 16, 16, 1, true, true, 3>; };
+template <> struct SchedFor<8192, 5> { using type = Sched<8192, 256, 16, 32, 16, 1, true, true, 3>; };
+template <> struct SchedFor<8192, 6> { using type = Sched<8192, 256, 16, 16, 32, 1, true, false, 3>; };
+template <> struct SchedFor<8192, 7> { using type = Sched<8192, 256, 16, 16, 32, 1, true, true, 2>; };
 template <> struct SchedFor<16384, 0> { using type = Sched<16384, 1024, 16, 16, 16, 4, true, false, 4>; };
 template <> struct SchedFor<16384, 1> { using type = Sched<16384, 512, 16, 32, 32, 1, false, false, 2>; };
-constexpr int kVariants[] = {1, 1, 1, 1, 2, 5, 2};  // per log2(N) - 8
+template <> struct SchedFor<16384, 2> { using type = Sched<16384, 512, 16, 32, 32, 1, true, true, 2>; };
+template <> struct SchedFor<16384, 3> { using type = Sched<16384, 512, 32, 32, 16, 1, true, true, 2>; };
+constexpr int kVariants[] = {1, 1, 1, 1, 4, 8, 4};  // per log2(N) - 8
 
 // ---------------------------------------------------------------------------
 // Kernel
@@ -64,6 +73,7 @@ struct BlockArgs {
   float* P;             // P[dmi*p_dm_stride + c*p_stride + u]
   float2* vout;         // vout[c*v_stride + o] or null (single DM only)
   const float2* tw;     // twiddle tables
+  const float2* H;      // single DM: chirp table H[c*N + i] (see chirp_table_kernel)
   int64_t x_stride, x_len, load_off;
   int64_t p_stride, p_dm_stride, u_lim;
   int64_t v_stride, o_lim;
@@ -135,6 +145,27 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
         sincospif(2.0f * q, &sn, &cs);
         v[b * R + r] = cmul(v[b * R + r], make_float2(cs * inv_n, -sn * inv_n));
       }
+    }
+  }
+}
+
+// Single DM: multiply by the channel's chirp row h[i] (bins in natural order).
+// The row is read through a buffer resource so that the per-bin offsets are
+// compile-time constants in scalar registers; consecutive lanes read
+// consecutive bins.
+template <class S>
+__device__ __forceinline__ void chirp_from_table(float2* v, const float2* h, int t) {
+  constexpr int N = S::N, R = S::rad_f(S::NP - 1), BPT = N / (R * S::T);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)h, (short)0, N * 8, 0x00020000);
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int soff = (S::T * b + r * (N / R)) * 8;
+      const float2 w =
+          __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, t * 8, soff, 0));
+      v[b * R + r] = cmul(v[b * R + r], w);
     }
   }
 }
@@ -253,9 +284,10 @@ __device__ __forceinline__ void process_item(const BlockArgs& a, int c, int64_t 
   load_block<S, DT>(v, a, c, k, t);
   fft_forward<S>(v, lds, a.tw, t);
   if constexpr (!MULTI) {
+    (void)fc;
     int tt = t;  // opaque copy: keeps per-bin index math next to its use
     asm volatile("" : "+v"(tt));
-    apply_chirp<S>(v, a.dms.dm[0], fc, a, tt);
+    chirp_from_table<S>(v, a.H + (int64_t)c * S::N, tt);
     fft_inverse<S>(v, lds, a.tw, tt);
     epilogue<S, true>(v, lds, a, c, k, 0, tt);
   } else {
@@ -277,12 +309,24 @@ __device__ __forceinline__ void process_item(const BlockArgs& a, int c, int64_t 
   }
 }
 
+// Workgroups are dispatched round-robin over the XCDs (8 on this chip, each
+// with its own L2).  Workgroup w runs on XCD w % 8; giving XCD x the
+// contiguous item range [x q + min(x, r), ...) of its own (total = 8 q + r)
+// keeps the blocks of one channel, and so its chirp row and the overlap
+// between neighbouring blocks, in one L2.  A bijection for any total.
+__device__ __forceinline__ int64_t xcd_item(int64_t w, int64_t total) {
+  constexpr int X = 8;
+  const int64_t q = total / X, r = total - q * X;
+  const int64_t x = w % X, slot = w / X;
+  return x * q + (x < r ? x : r) + slot;
+}
+
 // One workgroup per (channel, block) of one beam.
 template <class S, int DT, bool MULTI>
 __global__ __launch_bounds__(S::T, MULTI ? (S::MINB + 1) / 2 : S::MINB) void block_kernel(
     const BlockArgs a) {
   __shared__ __align__(16) float lds[S::lds_floats()];
-  const int64_t item = blockIdx.x;
+  const int64_t item = xcd_item(blockIdx.x, (int64_t)gridDim.x);
   const int c = (int)(item / a.nblocks);
   const int64_t k = item - (int64_t)c * a.nblocks;
   process_item<S, DT, MULTI>(a, c, k, lds, threadIdx.x);
@@ -318,6 +362,44 @@ __global__ __launch_bounds__(S::T, (S::MINB + 1) / 2) void batch_kernel(
 }
 
 __global__ void zero_counter_kernel(unsigned int* c) { *c = 0u; }
+
+// Chirp table of one DM: H[c*N + i] = exp(-2 pi i q)/N for bin i of channel c
+// (signed bin s = i or i - N, offset f = s*df/N from the channel centre fc),
+// q = D*DM*f^2/(fc^2 (fc + f)) turns (Eq. 3).  FP64 throughout: exact
+// division, reduction to [-1/2, 1/2] turns, sin/cos of pi*2r; one rounding
+// to FP32 at the end.  The FP32 phase mode forms the same quantities in FP32
+// (precision study).
+__global__ __launch_bounds__(256) void chirp_table_kernel(float2* __restrict__ H, int32_t lgN,
+                                                          int32_t nchan, double f_lo, double df,
+                                                          double dconst, double dm,
+                                                          int32_t phase_mode) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= ((int64_t)nchan << lgN)) return;
+  const int N = 1 << lgN;
+  const int c = (int)(g >> lgN);
+  const int i = (int)(g & (N - 1));
+  const int s = i < N / 2 ? i : i - N;
+  const double fc = f_lo + ((double)c + 0.5) * df;
+  float2 h;
+  if (phase_mode == CDD_PHASE_FP64_REDUCED) {
+    const double f = (double)s * (df / (double)N);
+    const double q = dconst * dm * (f * f) / (fc * fc * (fc + f));
+    const double r = q - rint(q);
+    double sn, cs;
+    sincospi(2.0 * r, &sn, &cs);
+    h = make_float2((float)(cs / (double)N), (float)(-sn / (double)N));
+  } else {
+    const float fcf = (float)fc;
+    const float Af = (float)(dconst * dm) / (fcf * fcf);
+    const float f = (float)s * ((float)df / (float)N);
+    const float q = Af * (f * f) / (fcf + f);
+    float sn, cs;
+    sincospif(2.0f * q, &sn, &cs);
+    const float inv_n = 1.0f / (float)N;
+    h = make_float2(cs * inv_n, -sn * inv_n);
+  }
+  H[g] = h;
+}
 
 // ---------------------------------------------------------------------------
 // Host side: FP64 twiddle tables (cached per device, length and schedule)
@@ -383,9 +465,10 @@ Coords offline_coords(const BeamPlan& p) {
 }
 
 static BlockArgs make_args(const BeamPlan& p, const Coords& co, const void* xt, const DmTile& dms,
-                           float* P, void* vout) {
+                           float* P, void* vout, const float2* H) {
   BlockArgs a{};
   a.x = xt;
+  a.H = H;
   a.P = P;
   a.vout = (float2*)vout;
   a.x_stride = co.x_stride;
@@ -481,14 +564,15 @@ bool block_supported(int N) {
 int block_variants(int N) { return block_supported(N) ? kVariants[log2i(N) - 8] : 0; }
 
 int launch_block(const BeamPlan& p, const void* xt, const DmTile& dms, float* P, void* vout,
-                 void* stream) {
-  return launch_block_co(p, offline_coords(p), xt, dms, P, vout, stream);
+                 const void* H, void* stream) {
+  return launch_block_co(p, offline_coords(p), xt, dms, P, vout, H, stream);
 }
 
 int launch_block_co(const BeamPlan& p, const Coords& co, const void* xt, const DmTile& dms,
-                    float* P, void* vout, void* stream) {
+                    float* P, void* vout, const void* H, void* stream) {
   if (dms.ndm < 1 || dms.ndm > kMaxDmTile) return (int)hipErrorInvalidValue;
-  const BlockArgs a = make_args(p, co, xt, dms, P, vout);
+  if (dms.ndm == 1 && H == nullptr) return (int)hipErrorInvalidValue;  // one DM needs its table
+  const BlockArgs a = make_args(p, co, xt, dms, P, vout, (const float2*)H);
   const int v = p.variant;
   switch (p.N) {
     case 256: return launch_block_t<256, 0>(a, stream);
@@ -496,22 +580,49 @@ int launch_block_co(const BeamPlan& p, const Coords& co, const void* xt, const D
     case 1024: return launch_block_t<1024, 0>(a, stream);
     case 2048: return launch_block_t<2048, 0>(a, stream);
     case 4096:
-      return v == 1 ? launch_block_t<4096, 1>(a, stream) : launch_block_t<4096, 0>(a, stream);
+      switch (v) {
+        case 1: return launch_block_t<4096, 1>(a, stream);
+        case 2: return launch_block_t<4096, 2>(a, stream);
+        case 3: return launch_block_t<4096, 3>(a, stream);
+        default: return launch_block_t<4096, 0>(a, stream);
+      }
     case 8192:
       switch (v) {
         case 1: return launch_block_t<8192, 1>(a, stream);
         case 2: return launch_block_t<8192, 2>(a, stream);
         case 3: return launch_block_t<8192, 3>(a, stream);
         case 4: return launch_block_t<8192, 4>(a, stream);
+        case 5: return launch_block_t<8192, 5>(a, stream);
+        case 6: return launch_block_t<8192, 6>(a, stream);
+        case 7: return launch_block_t<8192, 7>(a, stream);
         default: return launch_block_t<8192, 0>(a, stream);
       }
     case 16384:
-      return v == 1 ? launch_block_t<16384, 1>(a, stream) : launch_block_t<16384, 0>(a, stream);
+      switch (v) {
+        case 1: return launch_block_t<16384, 1>(a, stream);
+        case 2: return launch_block_t<16384, 2>(a, stream);
+        case 3: return launch_block_t<16384, 3>(a, stream);
+        default: return launch_block_t<16384, 0>(a, stream);
+      }
   }
   return (int)hipErrorInvalidValue;
 }
 
 size_t batch_table_bytes(int nbeams) { return sizeof(BlockArgs) * (size_t)nbeams; }
+
+size_t chirp_table_bytes(const BeamPlan& p) {
+  return block_supported(p.N) ? (size_t)p.nchan * p.N * sizeof(float2) : 0;
+}
+
+int launch_chirp_table(const BeamPlan& p, double dm, void* H, void* stream) {
+  if (!block_supported(p.N) || H == nullptr) return (int)hipErrorInvalidValue;
+  const int64_t n = (int64_t)p.nchan * p.N;
+  const int64_t grid = (n + 255) / 256;
+  if (grid > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(chirp_table_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
+                     (float2*)H, log2i(p.N), p.nchan, p.f_lo, p.df, p.dconst, dm, p.phase_mode);
+  return (int)hipGetLastError();
+}
 
 int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_tab,
                  unsigned int* counter, void* stream) {
@@ -523,7 +634,7 @@ int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_t
     const BeamPlan& p = *beams[b].p;
     if (p.N != N || beams[b].dms.ndm < 1 || beams[b].dms.ndm > kMaxDmTile)
       return (int)hipErrorInvalidValue;
-    ht[b] = make_args(p, beams[b].co, beams[b].xt, beams[b].dms, beams[b].P, nullptr);
+    ht[b] = make_args(p, beams[b].co, beams[b].xt, beams[b].dms, beams[b].P, nullptr, nullptr);
     ht[b].item0 = total;
     total += (int64_t)p.nchan * beams[b].co.nblocks;
   }
@@ -535,9 +646,9 @@ int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_t
     case 1024: return launch_batch_t<1024, 0>(ht, nbeams, total, dt, counter, stream);
     case 2048: return launch_batch_t<2048, 0>(ht, nbeams, total, dt, counter, stream);
     case 4096: return launch_batch_t<4096, 0>(ht, nbeams, total, dt, counter, stream);
-    case 8192:
+    case 8192:  // 16x16x16x2 schedules: the radix-32 one holds too many registers with a tile
       return v == 2 ? launch_batch_t<8192, 2>(ht, nbeams, total, dt, counter, stream)
-                    : launch_batch_t<8192, 0>(ht, nbeams, total, dt, counter, stream);
+                    : launch_batch_t<8192, 1>(ht, nbeams, total, dt, counter, stream);
     case 16384: return launch_batch_t<16384, 0>(ht, nbeams, total, dt, counter, stream);
   }
   return (int)hipErrorInvalidValue;

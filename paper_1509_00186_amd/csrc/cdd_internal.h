@@ -53,9 +53,10 @@ struct WsLayout {
   size_t d_off = 0, d_bytes = 0;     // delays [ndm][C] int32
   size_t s_off = 0, s_bytes = 0;     // long transforms: spectra of one chunk
   size_t pb_off = 0, pb_bytes = 0;   // long transforms: |y|^2 per sample [C][nsamp]
+  size_t h_off = 0, h_bytes = 0;     // one DM: chirp table [C][N] complex float
   size_t total = 0;
 };
-WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p);
+WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p, bool chirp_table = false);
 
 // ---------------------------------------------------------------------
 // Launchers (defined in the .hip files).  Return hipError_t as int.
@@ -81,14 +82,20 @@ Coords offline_coords(const BeamPlan& p);
 // Time-major [nsamp][nchan] -> out[c*out_stride + t].
 int launch_transpose(const void* in, void* out, int32_t dtype, int64_t nsamp,
                      int32_t nchan, int64_t out_stride, void* stream);
+// With one DM trial the block kernel takes the chirp from a table H built
+// by launch_chirp_table (chirp_table_bytes of device memory); with several
+// it forms the chirp itself and H is ignored.
 int launch_block(const BeamPlan& p, const void* xt, const DmTile& dms,
-                 float* P, void* vout, void* stream);
+                 float* P, void* vout, const void* H, void* stream);
 int launch_block_co(const BeamPlan& p, const Coords& co, const void* xt, const DmTile& dms,
-                    float* P, void* vout, void* stream);
+                    float* P, void* vout, const void* H, void* stream);
+size_t chirp_table_bytes(const BeamPlan& p);
+int launch_chirp_table(const BeamPlan& p, double dm, void* H, void* stream);
 // One DM, block kernel, record split into time chunks with the layout change
 // and the aligned sums on an auxiliary stream (cdd_pipeline.hip).
 int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, float* P,
-                  int32_t* d, void* volt_out, float* I, int32_t* cov, int chunks, void* stream);
+                  int32_t* d, void* H, void* volt_out, float* I, int32_t* cov, int chunks,
+                  void* stream);
 // Batched form: beams that share one transform length, each with its DM
 // tile, in one persistent launch.
 struct BatchBeam {

@@ -36,7 +36,8 @@ hipEvent_t take(Aux& a) {
 }  // namespace
 
 int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, float* P,
-                  int32_t* d, void* volt_out, float* I, int32_t* cov, int chunks, void* stream) {
+                  int32_t* d, void* H, void* volt_out, float* I, int32_t* cov, int chunks,
+                  void* stream) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return (int)e;
@@ -69,6 +70,7 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
   void* tok = nullptr;
   if ((err = stage_begin(A, &tok))) return err;
   if ((err = launch_delays(p, tile, d, A))) return err;
+  if ((err = launch_chirp_table(p, dm, H, A))) return err;
   if ((err = stage_end(kStageDelays, A, tok))) return err;
   std::vector<hipEvent_t> evT(C), evB(C);
   for (int i = 0; i < C; ++i) {
@@ -97,7 +99,7 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
       co.nblocks = nb;
       if ((err = stage_begin(S, &tok))) return err;
       if ((err = launch_block_co(p, co, xt, tile, P + u0,
-                                 volt_out ? (char*)volt_out + k0 * p.M * 8 : nullptr, S)))
+                                 volt_out ? (char*)volt_out + k0 * p.M * 8 : nullptr, H, S)))
         return err;
       if ((err = stage_end(kStageBlock, S, tok))) return err;
     }

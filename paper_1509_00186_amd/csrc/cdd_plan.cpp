@@ -178,7 +178,7 @@ cdd_status make_plan(int32_t dtype, int64_t nsamp, int32_t nchan,
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p) {
+WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p, bool chirp_table) {
   WsLayout w;
   size_t off = 0;
   size_t elem = p.dtype == CDD_CI8 ? 2 : 8;
@@ -202,6 +202,11 @@ WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p) {
     w.pb_off = off;
     w.pb_bytes = (size_t)p.nchan * p.nsamp * sizeof(float);
     off = align256(off + w.pb_bytes);
+  }
+  if (chirp_table && block_supported(p.N)) {
+    w.h_off = off;
+    w.h_bytes = (size_t)p.nchan * p.N * 8;
+    off = align256(off + w.h_bytes);
   }
   w.total = off;
   return w;
@@ -251,7 +256,7 @@ cdd_status cdd_query(int32_t dtype, int64_t nsamp, int32_t nchan,
   info->front = p.front;
   info->back = p.back;
   info->d_max = p.d_max;
-  info->ws_bytes = cdd::ws_layout(p, 1, true).total;
+  info->ws_bytes = cdd::ws_layout(p, 1, true, true).total;
   cdd::clear_error();
   return CDD_OK;
 }

@@ -126,6 +126,7 @@ extern "C" cdd_status cdd_autotune(int32_t dtype, int32_t nchan, double f_centre
   for (int i = 0; i < tile_n; ++i) tile.dm[i] = host_dms[i * ndm / tile_n];
   unsigned short* x = nullptr;
   float* P = nullptr;
+  void* H = nullptr;  // chirp table when there is one DM trial
   hipStream_t st = nullptr;
   hipEvent_t a = nullptr, b = nullptr;
   cdd_tune_result win{};
@@ -134,6 +135,7 @@ extern "C" cdd_status cdd_autotune(int32_t dtype, int32_t nchan, double f_centre
   do {
     if ((e = hipMalloc(&x, (size_t)T * nchan * 2)) != hipSuccess) break;
     if ((e = hipMalloc(&P, (size_t)tile_n * nchan * (T / n_int + 1) * 4)) != hipSuccess) break;
+    if (tile_n == 1 && (e = hipMalloc(&H, (size_t)nchan * n_max * 8)) != hipSuccess) break;
     if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) break;
     if ((e = hipEventCreate(&a)) != hipSuccess) break;
     if ((e = hipEventCreate(&b)) != hipSuccess) break;
@@ -146,15 +148,22 @@ extern "C" cdd_status cdd_autotune(int32_t dtype, int32_t nchan, double f_centre
       if (make_plan(dtype, T, nchan, f_centre_mhz, bw_mhz, host_dms, ndm, N, n_int, &o, &p) !=
           CDD_OK)
         continue;  // DM too large for this N
+      if (H) {
+        const int err = launch_chirp_table(p, tile.dm[0], H, st);
+        if (err) {
+          e = (hipError_t)err;
+          break;
+        }
+      }
       for (int v = 0; v < block_variants(N); ++v) {
         p.variant = v;
-        int err = launch_block(p, x, tile, P, nullptr, st);  // warm up (and twiddles)
+        int err = launch_block(p, x, tile, P, nullptr, H, st);  // warm up (and twiddles)
         if (err) {
           e = (hipError_t)err;
           break;
         }
         (void)hipEventRecord(a, st);
-        for (int r = 0; r < 3; ++r) launch_block(p, x, tile, P, nullptr, st);
+        for (int r = 0; r < 3; ++r) launch_block(p, x, tile, P, nullptr, H, st);
         (void)hipEventRecord(b, st);
         if ((e = hipEventSynchronize(b)) != hipSuccess) break;
         float ms = 0;
@@ -181,6 +190,7 @@ extern "C" cdd_status cdd_autotune(int32_t dtype, int32_t nchan, double f_centre
   if (st) (void)hipStreamDestroy(st);
   if (x) (void)hipFree(x);
   if (P) (void)hipFree(P);
+  if (H) (void)hipFree(H);
   if (status != CDD_OK) return status;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
