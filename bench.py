@@ -52,8 +52,9 @@ def block_flops(N: int, M: int) -> float:
 
 
 def source_digest() -> str:
+    """Digest of the sources the block kernel is compiled from."""
     h = hashlib.sha256()
-    for f in ("cdd_block.hip",):
+    for f in ("cdd_block.hip", "cdd_fft.h", "cdd_internal.h"):
         with open(os.path.join(ROOT, "paper_1509_00186_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -91,7 +91,11 @@ typedef struct {
                               1.. = alternatives (cdd_kernel_variants)     */
   int32_t autotune;        /* cdd_plan_create: beams with fft_len 0 get N and
                               schedule from cdd_autotune (2^11 .. 2^14)    */
-  int32_t reserved[5];
+  int32_t time_chunks;     /* cdd_dedisperse: split the record into this many
+                              time chunks so the layout change and aligned
+                              sums overlap the block kernel; 0 = automatic,
+                              1 = no split                                 */
+  int32_t reserved[4];
 } cdd_opts;
 
 /* Plan figures for one beam (filled by cdd_query / cdd_plan_info). */

@@ -30,7 +30,7 @@ class Opts(ctypes.Structure):
                 ("overlap", ctypes.c_int32), ("nfront", ctypes.c_int32),
                 ("dm_const", ctypes.c_double), ("phase_mode", ctypes.c_int32),
                 ("kernel_variant", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("time_chunks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -170,10 +170,11 @@ def autotune(nchan, f_centre, bw, dms, n_int, n_min=0, n_max=0, dtype=CDD_CI8):
 
 
 def make_opts(fft_len=0, overlap=None, nfront=None, dm_const=0.0, phase_mode=0, variant=0,
-              autotune=0):
+              autotune=0, time_chunks=0):
     o = Opts()
     o.kernel_variant = int(variant)
     o.autotune = int(autotune)
+    o.time_chunks = int(time_chunks)
     if overlap is not None or nfront is not None:
         o.explicit_plan = 1
         o.fft_len = int(fft_len)
@@ -218,7 +219,7 @@ def _stream_handle(stream):
 
 def dedisperse(voltages, f_centre, bw, dm, fft_len=0, n_int=1, *, want_chan=False,
                want_voltages=False, overlap=None, nfront=None, dm_const=0.0, phase_mode=0,
-               variant=0, stream=None, out=None):
+               variant=0, time_chunks=0, stream=None, out=None):
     """Run cdd_dedisperse on a resident device tensor.
 
     Returns a dict: I [t_int] float32, cov [t_int] int32, P [nchan][t_int]
@@ -229,7 +230,8 @@ def dedisperse(voltages, f_centre, bw, dm, fft_len=0, n_int=1, *, want_chan=Fals
     if not voltages.is_cuda or not voltages.is_contiguous():
         raise ValueError("voltages must be a contiguous device tensor")
     dt, nsamp, nchan = _layout(voltages)
-    o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode, variant)
+    o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode, variant,
+                  time_chunks=time_chunks)
     info = PlanInfo()
     _check(lib.cdd_query(dt, nsamp, nchan, float(f_centre), float(bw), float(dm), int(fft_len),
                          int(n_int), int(want_voltages), ctypes.byref(o), ctypes.byref(info)))

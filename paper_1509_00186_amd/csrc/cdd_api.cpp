@@ -137,6 +137,7 @@ cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp, in
   try {
     if (!voltages) return fail(CDD_EINVAL, "voltages is NULL");
     if (!intensity) return fail(CDD_EINVAL, "intensity is NULL");
+    if (opts && opts->time_chunks < 0) return fail(CDD_EINVAL, "time_chunks must be >= 0");
     BeamPlan p;
     cdd_status s = make_plan(dtype, nsamp, nchan, f_centre_mhz, bw_mhz, &dm, 1, fft_len, n_int,
                              opts, &p);
@@ -148,8 +149,11 @@ cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp, in
       return fail(CDD_EINVAL, "workspace too small: need %zu bytes, got %zu", lay.total,
                   workspace ? ws_bytes : (size_t)0);
     if (!aligned256(workspace)) return fail(CDD_EINVAL, "workspace must be 256-byte aligned");
-    const int chunks = (int)std::min<int64_t>(4, p.nblocks / 4);
-    if (block_supported(p.N) && p.nchan > 1 && chunks >= 2) {
+    // time chunks of the overlapped path: one unless asked for more
+    int chunks = 1;
+    if (opts && opts->time_chunks > 0)
+      chunks = (int)std::min<int64_t>({(int64_t)opts->time_chunks, p.nblocks, kMaxChunks});
+    if (block_supported(p.N) && p.nchan > 1) {
       char* ws = (char*)workspace;
       int e = run_pipelined(p, voltages, dm, ws + lay.xt_off,
                             chan_intensity ? chan_intensity : (float*)(ws + lay.p_off),

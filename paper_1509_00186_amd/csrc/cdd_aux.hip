@@ -155,8 +155,13 @@ int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream
 // a contiguous channel range in ascending order, and the G partial sums are
 // added in ascending wave order -- a fixed order, no atomics, so results do
 // not depend on scheduling.  grid.y = DM trial.
+// Each channel row is read through a buffer resource whose range ends at
+// src_lim: a term past the end is pointed at src_lim itself and reads as zero
+// (adding +0 leaves the sum unchanged), so the loads carry no branch; eight
+// channels' loads are issued before they are added.  Rows of 2^29 floats or
+// more take the checked loop.
 // ---------------------------------------------------------------------------
-template <int G>
+template <int G, bool BUF>
 __global__ __launch_bounds__(64 * G) void dsum_kernel(const float* __restrict__ P,
                                                       const int32_t* __restrict__ d,
                                                       float* __restrict__ I,
@@ -167,7 +172,8 @@ __global__ __launch_bounds__(64 * G) void dsum_kernel(const float* __restrict__ 
   __shared__ float ps[G][64];
   __shared__ int32_t pn[G][64];
   const int i = blockIdx.y;
-  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index (uniform)
   const int64_t uo = (int64_t)blockIdx.x * 64 + lane;
   const int64_t u = u_begin + uo;
   const float* Pi = P + (int64_t)i * p_dm_stride;
@@ -176,12 +182,44 @@ __global__ __launch_bounds__(64 * G) void dsum_kernel(const float* __restrict__ 
   const int c_lo = g * per, c_hi = min(nchan, c_lo + per);
   float acc = 0.f;
   int32_t n = 0;
-  if (uo < u_count) {
-    for (int c = c_lo; c < c_hi; ++c) {
-      const int64_t src = u + di[c];
-      if (src < src_lim) {
-        acc += Pi[(int64_t)c * p_stride + src];
-        ++n;
+  if constexpr (BUF) {
+    // lanes past u_count read offset 0 (in range or zero) and are not stored
+    const bool live = uo < u_count;
+    const int ub = live ? (int)u : 0;
+    const int lim = (int)src_lim;
+    int c = c_lo;
+    for (; c + 8 <= c_hi; c += 8) {
+      float x[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(Pi + (int64_t)(c + j) * p_stride), (short)0, lim * 4, 0x00020000);
+        const int64_t src = (int64_t)ub + di[c + j];
+        const bool in = src < lim;
+        x[j] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(rs, (in ? (int)src : lim) * 4, 0, 0));
+        n += in;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc += x[j];
+    }
+    for (; c < c_hi; ++c) {
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(Pi + (int64_t)c * p_stride), (short)0, lim * 4, 0x00020000);
+      const int64_t src = (int64_t)ub + di[c];
+      const bool in = src < lim;
+      acc += __builtin_bit_cast(
+          float, __builtin_amdgcn_raw_buffer_load_b32(rs, (in ? (int)src : lim) * 4, 0, 0));
+      n += in;
+    }
+  } else {
+    if (uo < u_count) {
+      for (int c = c_lo; c < c_hi; ++c) {
+        const int64_t src = u + di[c];
+        if (src < src_lim) {
+          acc += Pi[(int64_t)c * p_stride + src];
+          ++n;
+        }
       }
     }
   }
@@ -201,6 +239,18 @@ __global__ __launch_bounds__(64 * G) void dsum_kernel(const float* __restrict__ 
   }
 }
 
+template <int G>
+static void dsum_launch(bool buf, dim3 grid, hipStream_t st, const float* P, const int32_t* d,
+                        float* I, int32_t* cov, int nchan, int64_t p_stride, int64_t p_dm_stride,
+                        int64_t src_lim, int64_t u_begin, int64_t u_count, int64_t out_stride) {
+  if (buf)
+    hipLaunchKernelGGL((dsum_kernel<G, true>), grid, dim3(64 * G), 0, st, P, d, I, cov, nchan,
+                       p_stride, p_dm_stride, src_lim, u_begin, u_count, out_stride);
+  else
+    hipLaunchKernelGGL((dsum_kernel<G, false>), grid, dim3(64 * G), 0, st, P, d, I, cov, nchan,
+                       p_stride, p_dm_stride, src_lim, u_begin, u_count, out_stride);
+}
+
 int launch_dsum_range(int nchan, int ndm, const float* P, int64_t p_stride, int64_t p_dm_stride,
                       int64_t src_lim, int64_t u_begin, int64_t u_count, const int32_t* d,
                       float* I, int32_t* cov, int64_t out_stride, void* stream) {
@@ -209,12 +259,17 @@ int launch_dsum_range(int nchan, int ndm, const float* P, int64_t p_stride, int6
   if (nb > 0x7fffffffLL || ndm < 1 || ndm > 65535) return (int)hipErrorInvalidValue;
   dim3 grid((unsigned)nb, (unsigned)ndm);
   hipStream_t st = (hipStream_t)stream;
-  if (nchan >= 64)
-    hipLaunchKernelGGL(dsum_kernel<8>, grid, dim3(512), 0, st, P, d, I, cov, nchan, p_stride,
-                       p_dm_stride, src_lim, u_begin, u_count, out_stride);
+  // 32-bit byte offsets: row lengths and output positions below 2^29
+  const bool buf = src_lim >= 0 && src_lim < (1LL << 29) && u_begin + u_count < (1LL << 29);
+  if (nchan >= 256)
+    dsum_launch<16>(buf, grid, st, P, d, I, cov, nchan, p_stride, p_dm_stride, src_lim, u_begin,
+                    u_count, out_stride);
+  else if (nchan >= 64)
+    dsum_launch<8>(buf, grid, st, P, d, I, cov, nchan, p_stride, p_dm_stride, src_lim, u_begin,
+                   u_count, out_stride);
   else
-    hipLaunchKernelGGL(dsum_kernel<1>, grid, dim3(64), 0, st, P, d, I, cov, nchan, p_stride,
-                       p_dm_stride, src_lim, u_begin, u_count, out_stride);
+    dsum_launch<1>(buf, grid, st, P, d, I, cov, nchan, p_stride, p_dm_stride, src_lim, u_begin,
+                   u_count, out_stride);
   return (int)hipGetLastError();
 }
 

@@ -6,7 +6,7 @@
 //                exchanges through LDS (real and imaginary halves in turn)
 //   chirp:       exp(-2 pi i q_j)/N per bin, q_j from Eq. 3 evaluated in FP64
 //                and reduced to [-1/2, 1/2] turns; with one DM it is read
-//                from a per-channel table built once per call (FP64 sin/cos),
+//                from a per-channel table built once per call,
 //                with several it is formed in the kernel (FP32 sin/cos)
 //   inverse FFT: the same passes in reverse radix order, conjugate twiddles;
 //                its first pass consumes the forward result in registers
@@ -43,21 +43,21 @@ template <> struct SchedFor<256, 0> { using type = Sched<256, 64, 4, 4, 4, 4>; }
 template <> struct SchedFor<512, 0> { using type = Sched<512, 64, 8, 8, 8, 1>; };
 template <> struct SchedFor<1024, 0> { using type = Sched<1024, 64, 16, 16, 4, 1>; };
 template <> struct SchedFor<2048, 0> { using type = Sched<2048, 128, 16, 16, 8, 1>; };
-template <> struct SchedFor<4096, 0> { using type = Sched<4096, 256, 16, 16, 16, 1, true, false, 3>; };
+template <> struct SchedFor<4096, 0> { using type = Sched<4096, 128, 16, 16, 16, 1, true, true, 3>; };
 template <> struct SchedFor<4096, 1> { using type = Sched<4096, 256, 16, 16, 16, 1, false, false, 2>; };
 template <> struct SchedFor<4096, 2> { using type = Sched<4096, 256, 16, 16, 16, 1, true, true, 3>; };
-template <> struct SchedFor<4096, 3> { using type = Sched<4096, 128, 16, 16, 16, 1, true, true, 3>; };
-template <> struct SchedFor<8192, 0> { using type = Sched<8192, 256, 16, 16, 32, 1, true, true, 3>; };
+template <> struct SchedFor<4096, 3> { using type = Sched<4096, 256, 16, 16, 16, 1, true, false, 3>; };
+template <> struct SchedFor<8192, 0> { using type = Sched<8192, 256, 16, 16, 32, 1, true, false, 3>; };
 template <> struct SchedFor<8192, 1> { using type = Sched<8192, 512, 16, 16, 16, 2, true, true, 4>; };
 template <> struct SchedFor<8192, 2> { using type = Sched<8192, 512, 16, 16, 16, 2, true, false, 6>; };
 template <> struct SchedFor<8192, 3> { using type = Sched<8192, 512, 16, 16, 16, 2, false, true, 4>; };
 template <> struct SchedFor<8192, 4> { using type = Sched<8192, 256, 32, 16, 16, 1, true, true, 3>; };
 template <> struct SchedFor<8192, 5> { using type = Sched<8192, 256, 16, 32, 16, 1, true, true, 3>; };
-template <> struct SchedFor<8192, 6> { using type = Sched<8192, 256, 16, 16, 32, 1, true, false, 3>; };
+template <> struct SchedFor<8192, 6> { using type = Sched<8192, 256, 16, 16, 32, 1, true, true, 3>; };
 template <> struct SchedFor<8192, 7> { using type = Sched<8192, 256, 16, 16, 32, 1, true, true, 2>; };
-template <> struct SchedFor<16384, 0> { using type = Sched<16384, 1024, 16, 16, 16, 4, true, false, 4>; };
+template <> struct SchedFor<16384, 0> { using type = Sched<16384, 512, 16, 32, 32, 1, true, true, 2>; };
 template <> struct SchedFor<16384, 1> { using type = Sched<16384, 512, 16, 32, 32, 1, false, false, 2>; };
-template <> struct SchedFor<16384, 2> { using type = Sched<16384, 512, 16, 32, 32, 1, true, true, 2>; };
+template <> struct SchedFor<16384, 2> { using type = Sched<16384, 1024, 16, 16, 16, 4, true, false, 4>; };
 template <> struct SchedFor<16384, 3> { using type = Sched<16384, 512, 32, 32, 16, 1, true, true, 2>; };
 constexpr int kVariants[] = {1, 1, 1, 1, 4, 8, 4};  // per log2(N) - 8
 
@@ -365,10 +365,10 @@ __global__ void zero_counter_kernel(unsigned int* c) { *c = 0u; }
 
 // Chirp table of one DM: H[c*N + i] = exp(-2 pi i q)/N for bin i of channel c
 // (signed bin s = i or i - N, offset f = s*df/N from the channel centre fc),
-// q = D*DM*f^2/(fc^2 (fc + f)) turns (Eq. 3).  FP64 throughout: exact
-// division, reduction to [-1/2, 1/2] turns, sin/cos of pi*2r; one rounding
-// to FP32 at the end.  The FP32 phase mode forms the same quantities in FP32
-// (precision study).
+// q = D*DM*f^2/(fc^2 (fc + f)) turns (Eq. 3).  q (up to ~1e5 turns) and its
+// reduction r = q - rint(q) to [-1/2, 1/2] turns are FP64 with an exact
+// division; sin/cos of 2 pi r are FP32.  The FP32 phase mode forms q itself
+// in FP32 (precision study).
 __global__ __launch_bounds__(256) void chirp_table_kernel(float2* __restrict__ H, int32_t lgN,
                                                           int32_t nchan, double f_lo, double df,
                                                           double dconst, double dm,
@@ -384,10 +384,11 @@ __global__ __launch_bounds__(256) void chirp_table_kernel(float2* __restrict__ H
   if (phase_mode == CDD_PHASE_FP64_REDUCED) {
     const double f = (double)s * (df / (double)N);
     const double q = dconst * dm * (f * f) / (fc * fc * (fc + f));
-    const double r = q - rint(q);
-    double sn, cs;
-    sincospi(2.0 * r, &sn, &cs);
-    h = make_float2((float)(cs / (double)N), (float)(-sn / (double)N));
+    const float r = (float)(q - rint(q));
+    float sn, cs;
+    sincospif(2.0f * r, &sn, &cs);
+    const float inv_n = 1.0f / (float)N;
+    h = make_float2(cs * inv_n, -sn * inv_n);
   } else {
     const float fcf = (float)fc;
     const float Af = (float)(dconst * dm) / (fcf * fcf);
@@ -645,11 +646,11 @@ int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_t
     case 512: return launch_batch_t<512, 0>(ht, nbeams, total, dt, counter, stream);
     case 1024: return launch_batch_t<1024, 0>(ht, nbeams, total, dt, counter, stream);
     case 2048: return launch_batch_t<2048, 0>(ht, nbeams, total, dt, counter, stream);
-    case 4096: return launch_batch_t<4096, 0>(ht, nbeams, total, dt, counter, stream);
+    case 4096: return launch_batch_t<4096, 3>(ht, nbeams, total, dt, counter, stream);
     case 8192:  // 16x16x16x2 schedules: the radix-32 one holds too many registers with a tile
       return v == 2 ? launch_batch_t<8192, 2>(ht, nbeams, total, dt, counter, stream)
                     : launch_batch_t<8192, 1>(ht, nbeams, total, dt, counter, stream);
-    case 16384: return launch_batch_t<16384, 0>(ht, nbeams, total, dt, counter, stream);
+    case 16384: return launch_batch_t<16384, 2>(ht, nbeams, total, dt, counter, stream);
   }
   return (int)hipErrorInvalidValue;
 }

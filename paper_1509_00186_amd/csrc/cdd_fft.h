@@ -139,6 +139,24 @@ struct Dft {
 // ---------------------------------------------------------------------------
 // Schedules: threads per workgroup and forward radix order per length
 // ---------------------------------------------------------------------------
+// LDS layout of a split exchange (one 4-byte word per element): word i of a
+// pass's output goes to xpad(i) = i + ((i >> 5) << TS).  The reads of the
+// next pass take 32 consecutive elements per half-wave from a 32-aligned run,
+// which stays contiguous (every bank once).  The writes of a pass of radix R
+// and span Ns put Ns consecutive lanes on consecutive words and 32/Ns such
+// groups R*Ns words apart; TS = log2(32/R) spaces the groups exactly Ns banks
+// apart when 1 < Ns < 32 and R < 32, and 0 does in the other cases.  (With
+// the LDS's 32 banks served per 32 lanes, both sides are then conflict-free
+// for the radix-16 and radix-32 passes.)
+constexpr int xpad_shift(int R, int Ns) {
+  if (Ns == 1 || Ns >= 32 || R >= 32) return 0;
+  int t = 0;
+  while ((R << t) < 32) ++t;
+  return t;
+}
+template <int TS>
+__device__ __forceinline__ constexpr int xpad(int i) { return i + ((i >> 5) << TS); }
+
 template <int N_, int T_, int A, int B, int C, int D, bool SPLIT_ = true, bool PF_ = false,
           int MINB_ = 1>
 struct Sched {
@@ -171,7 +189,20 @@ struct Sched {
     return o;
   }
   static constexpr int tw_total() { return tw_i(NP); }
-  static constexpr int lds_floats() { return (SPLIT ? 1 : 2) * (N + N / 16); }
+  // Split exchanges pad every 32 words by 2^xpad_shift words (see xpad); the
+  // largest pad over the schedule's exchanges sizes the LDS.
+  static constexpr int xpad_max() {
+    int m = 0;
+    for (int p = 0; p + 1 < NP; ++p) {
+      const int a = xpad_shift(rad_f(p), ns_f(p)), b = xpad_shift(rad_i(p), ns_i(p));
+      m = a > m ? a : m;
+      m = b > m ? b : m;
+    }
+    return m;
+  }
+  static constexpr int lds_floats() {
+    return SPLIT ? N + ((N >> 5) << xpad_max()) : 2 * (N + N / 16);
+  }
 };
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
@@ -228,15 +259,15 @@ template <class S, int RP, int NSP, int RN>
 __device__ __forceinline__ void exchange(float2* v, float* lds, int t) {
   constexpr int N = S::N, T = S::T;
   constexpr int BP = N / (RP * T), BN = N / (RN * T);
-  int wb[BP], rb[BN];
-#pragma unroll
-  for (int b = 0; b < BP; ++b) {
-    const int j = t + T * b;
-    wb[b] = lpad((j / NSP) * NSP * RP + (j % NSP));
-  }
-#pragma unroll
-  for (int b = 0; b < BN; ++b) rb[b] = lpad(t + T * b);
   if constexpr (!S::SPLIT) {
+    int wb[BP], rb[BN];
+#pragma unroll
+    for (int b = 0; b < BP; ++b) {
+      const int j = t + T * b;
+      wb[b] = lpad((j / NSP) * NSP * RP + (j % NSP));
+    }
+#pragma unroll
+    for (int b = 0; b < BN; ++b) rb[b] = lpad(t + T * b);
     float2* l2 = (float2*)lds;
     __syncthreads();
 #pragma unroll
@@ -249,26 +280,37 @@ __device__ __forceinline__ void exchange(float2* v, float* lds, int t) {
 #pragma unroll
       for (int r = 0; r < RN; ++r) v[b * RN + r] = l2[rb[b] + loff(r * (N / RN))];
   } else {
+    // The per-thread base and the compile-time offset occupy disjoint bits,
+    // so xpad(base + off) = xpad(base) + xpad(off).
+    constexpr int TS = xpad_shift(RP, NSP);
+    int xw[BP], xr[BN];
+#pragma unroll
+    for (int b = 0; b < BP; ++b) {
+      const int j = t + T * b;
+      xw[b] = xpad<TS>((j / NSP) * NSP * RP + (j % NSP));
+    }
+#pragma unroll
+    for (int b = 0; b < BN; ++b) xr[b] = xpad<TS>(t + T * b);
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < BP; ++b)
 #pragma unroll
-      for (int r = 0; r < RP; ++r) lds[wb[b] + loff(r * NSP)] = v[b * RP + r].x;
+      for (int r = 0; r < RP; ++r) lds[xw[b] + xpad<TS>(r * NSP)] = v[b * RP + r].x;
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < BN; ++b)
 #pragma unroll
-      for (int r = 0; r < RN; ++r) v[b * RN + r].x = lds[rb[b] + loff(r * (N / RN))];
+      for (int r = 0; r < RN; ++r) v[b * RN + r].x = lds[xr[b] + xpad<TS>(r * (N / RN))];
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < BP; ++b)
 #pragma unroll
-      for (int r = 0; r < RP; ++r) lds[wb[b] + loff(r * NSP)] = v[b * RP + r].y;
+      for (int r = 0; r < RP; ++r) lds[xw[b] + xpad<TS>(r * NSP)] = v[b * RP + r].y;
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < BN; ++b)
 #pragma unroll
-      for (int r = 0; r < RN; ++r) v[b * RN + r].y = lds[rb[b] + loff(r * (N / RN))];
+      for (int r = 0; r < RN; ++r) v[b * RN + r].y = lds[xr[b] + xpad<TS>(r * (N / RN))];
   }
 }
 

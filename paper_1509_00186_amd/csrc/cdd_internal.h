@@ -14,6 +14,7 @@ constexpr double kDefaultD = 4.148808e9;  // Eq. 3's D (us MHz^2 cm^3 / pc)
 constexpr int kMinFFT = 256;
 constexpr int kMaxFFT = 1 << 22;
 constexpr int kMaxDmTile = 64;            // DM trials per batched launch
+constexpr int64_t kMaxChunks = 12;        // time chunks of the pipelined one-shot path
 
 // Thread-local error message and status (set by every failing call).
 cdd_status fail(cdd_status s, const char* fmt, ...);

@@ -1,12 +1,14 @@
 // One-shot path with the memory-bound stages overlapped with compute.
 //
-// The fused block kernel is bound by vector ALU and LDS and leaves HBM mostly
-// idle, while the layout change and the aligned sum are HBM-bound.  The record
-// is split into time chunks: an auxiliary HIP stream changes the layout of
-// chunk i+1 while the caller's stream transforms chunk i, and sums every
-// output range whose delayed inputs are complete as soon as they are; events
-// order the two streams, and the caller's stream waits for the auxiliary one
-// at the end, so the call stays asynchronous and stream-ordered.
+// The layout change runs on an auxiliary HIP stream while the caller's stream
+// builds the chirp table and the channel delays.  With several time chunks
+// the auxiliary stream also changes the layout of chunk i+1 while the
+// caller's stream transforms chunk i, and sums every output range whose
+// delayed inputs are complete as soon as they are.  Events order the two
+// streams, and the caller's stream waits for the auxiliary one at the end, so
+// the call stays asynchronous and stream-ordered.  (Each chunk boundary costs
+// a partly filled last round of workgroups and the overlapped kernels slow
+// the block kernel down, so one chunk is the default.)
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -19,6 +21,7 @@ namespace cdd {
 
 namespace {
 constexpr int kEvents = 32;
+static_assert(kEvents >= 2 * kMaxChunks + 2, "one call takes 2 C + 2 events");
 
 struct Aux {
   hipStream_t s = nullptr;
@@ -68,10 +71,10 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
   if ((e = hipStreamWaitEvent(A, e0, 0)) != hipSuccess) return (int)e;
   int err = 0;
   void* tok = nullptr;
-  if ((err = stage_begin(A, &tok))) return err;
-  if ((err = launch_delays(p, tile, d, A))) return err;
-  if ((err = launch_chirp_table(p, dm, H, A))) return err;
-  if ((err = stage_end(kStageDelays, A, tok))) return err;
+  if ((err = stage_begin(S, &tok))) return err;
+  if ((err = launch_delays(p, tile, d, S))) return err;
+  if ((err = launch_chirp_table(p, dm, H, S))) return err;
+  if ((err = stage_end(kStageDelays, S, tok))) return err;
   std::vector<hipEvent_t> evT(C), evB(C);
   for (int i = 0; i < C; ++i) {
     const int64_t rows = tr[i + 1] - tr[i];
@@ -106,19 +109,22 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
     evB[i] = take(ax);
     if ((e = hipEventRecord(evB[i], S)) != hipSuccess) return (int)e;
   }
-  // aligned sums: u is final once every channel's P[u + d_c] is computed
+  // aligned sums: u is final once every channel's P[u + d_c] is computed;
+  // the last range runs on the caller's stream, right after the last chunk
   int64_t u_done = 0;
   for (int i = 0; i < C; ++i) {
-    if ((e = hipStreamWaitEvent(A, evB[i], 0)) != hipSuccess) return (int)e;
-    int64_t upto = (i == C - 1) ? p.t_int
-                                : std::min<int64_t>(p.t_int, kb[i + 1] * (p.M / p.n_int) - p.d_max);
+    const bool last = i == C - 1;
+    hipStream_t Q = last ? S : A;
+    if (!last && (e = hipStreamWaitEvent(A, evB[i], 0)) != hipSuccess) return (int)e;
+    int64_t upto = last ? p.t_int
+                        : std::min<int64_t>(p.t_int, kb[i + 1] * (p.M / p.n_int) - p.d_max);
     if (upto > u_done) {
-      if ((err = stage_begin(A, &tok))) return err;
+      if ((err = stage_begin(Q, &tok))) return err;
       if ((err = launch_dsum_range(p.nchan, 1, P, p.t_int, (int64_t)p.nchan * p.t_int, p.t_int,
                                    u_done, upto - u_done, d, I + u_done,
-                                   cov ? cov + u_done : nullptr, p.t_int, A)))
+                                   cov ? cov + u_done : nullptr, p.t_int, Q)))
         return err;
-      if ((err = stage_end(kStageDsum, A, tok))) return err;
+      if ((err = stage_end(kStageDsum, Q, tok))) return err;
       u_done = upto;
     }
   }

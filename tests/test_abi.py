@@ -127,6 +127,11 @@ def test_dedisperse_rejects_bad_workspace_without_touching_device():
                                 1024, 4, ctypes.c_void_p(0x2000), None, None, None,
                                 ctypes.byref(o), ctypes.c_void_p(0x3001), q["ws_bytes"], None)
     assert st == -1 and b"aligned" in cdd.lib.cdd_last_error()
+    o.time_chunks = -2
+    st = cdd.lib.cdd_dedisperse(ctypes.c_void_p(0x1000), 0, 10_000, 64, 325.0, 4.0, 30.0,
+                                1024, 4, ctypes.c_void_p(0x2000), None, None, None,
+                                ctypes.byref(o), ctypes.c_void_p(0x3000), q["ws_bytes"], None)
+    assert st == -1 and b"time_chunks" in cdd.lib.cdd_last_error()
 
 
 def test_last_error_is_thread_local():
