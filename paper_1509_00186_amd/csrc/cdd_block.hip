@@ -55,11 +55,13 @@ template <> struct SchedFor<8192, 4> { using type = Sched<8192, 256, 32, 16, 16,
 template <> struct SchedFor<8192, 5> { using type = Sched<8192, 256, 16, 32, 16, 1, true, true, 3>; };
 template <> struct SchedFor<8192, 6> { using type = Sched<8192, 256, 16, 16, 32, 1, true, true, 3>; };
 template <> struct SchedFor<8192, 7> { using type = Sched<8192, 256, 16, 16, 32, 1, true, true, 2>; };
+template <> struct SchedFor<8192, 8> { using type = Sched<8192, 256, 16, 16, 32, 1, true, false, 4>; };
+template <> struct SchedFor<8192, 9> { using type = Sched<8192, 256, 16, 16, 32, 1, false, false, 3>; };
 template <> struct SchedFor<16384, 0> { using type = Sched<16384, 512, 16, 32, 32, 1, true, true, 2>; };
 template <> struct SchedFor<16384, 1> { using type = Sched<16384, 512, 16, 32, 32, 1, false, false, 2>; };
 template <> struct SchedFor<16384, 2> { using type = Sched<16384, 1024, 16, 16, 16, 4, true, false, 4>; };
 template <> struct SchedFor<16384, 3> { using type = Sched<16384, 512, 32, 32, 16, 1, true, true, 2>; };
-constexpr int kVariants[] = {1, 1, 1, 1, 4, 8, 4};  // per log2(N) - 8
+constexpr int kVariants[] = {1, 1, 1, 1, 4, 10, 4};  // per log2(N) - 8
 
 // ---------------------------------------------------------------------------
 // Kernel
@@ -596,6 +598,8 @@ int launch_block_co(const BeamPlan& p, const Coords& co, const void* xt, const D
         case 5: return launch_block_t<8192, 5>(a, stream);
         case 6: return launch_block_t<8192, 6>(a, stream);
         case 7: return launch_block_t<8192, 7>(a, stream);
+        case 8: return launch_block_t<8192, 8>(a, stream);
+        case 9: return launch_block_t<8192, 9>(a, stream);
         default: return launch_block_t<8192, 0>(a, stream);
       }
     case 16384:

@@ -20,11 +20,21 @@
 namespace cdd {
 
 namespace {
-constexpr int kEvents = 32;
-static_assert(kEvents >= 2 * kMaxChunks + 2, "one call takes 2 C + 2 events");
+constexpr int kEvents = 64;
+static_assert(kEvents >= 2 * kMaxChunks + 3, "one call takes 2 C + 3 events");
+
+// Blocks of the first time chunk = nblocks / kFirstDiv (rounded up): its
+// layout change is the only one not hidden behind block work, and the layout
+// change of a block column is about four times faster than its transforms.
+constexpr int64_t kFirstDiv = 5;
+// Consecutive chunks alternate between the caller's stream and a second
+// compute stream, so one chunk's last workgroups overlap the next chunk's
+// first ones instead of draining the machine at every chunk boundary.
+constexpr bool kTwoCompute = true;
 
 struct Aux {
-  hipStream_t s = nullptr;
+  hipStream_t s = nullptr;   // layout changes and aligned sums
+  hipStream_t s2 = nullptr;  // every other block chunk
   hipEvent_t ev[kEvents];
   int next = 0;
 };
@@ -48,15 +58,21 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
   Aux& ax = g_aux[dev];
   if (!ax.s) {
     if ((e = hipStreamCreateWithFlags(&ax.s, hipStreamNonBlocking)) != hipSuccess) return (int)e;
+    if ((e = hipStreamCreateWithFlags(&ax.s2, hipStreamNonBlocking)) != hipSuccess) return (int)e;
     for (int i = 0; i < kEvents; ++i)
       if ((e = hipEventCreateWithFlags(&ax.ev[i], hipEventDisableTiming)) != hipSuccess)
         return (int)e;
   }
-  hipStream_t S = (hipStream_t)stream, A = ax.s;
+  hipStream_t S = (hipStream_t)stream, A = ax.s, S2 = ax.s2;
   const size_t elem = p.dtype == CDD_CI8 ? 2 : 8;
   const int C = chunks;
   std::vector<int64_t> kb(C + 1), tr(C + 1);
-  for (int i = 0; i <= C; ++i) kb[i] = p.nblocks * i / C;
+  kb[0] = 0;
+  if (C >= 2) {
+    kb[1] = std::max<int64_t>(1, (p.nblocks + kFirstDiv - 1) / kFirstDiv);
+    for (int i = 2; i <= C; ++i) kb[i] = kb[1] + (p.nblocks - kb[1]) * (i - 1) / (C - 1);
+  }
+  kb[C] = p.nblocks;
   tr[0] = 0;
   for (int i = 1; i <= C; ++i)
     tr[i] = std::max(tr[i - 1],
@@ -69,6 +85,8 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
   hipEvent_t e0 = take(ax);
   if ((e = hipEventRecord(e0, S)) != hipSuccess) return (int)e;
   if ((e = hipStreamWaitEvent(A, e0, 0)) != hipSuccess) return (int)e;
+  const bool two = kTwoCompute && C >= 2;
+  if (two && (e = hipStreamWaitEvent(S2, e0, 0)) != hipSuccess) return (int)e;
   int err = 0;
   void* tok = nullptr;
   if ((err = stage_begin(S, &tok))) return err;
@@ -90,8 +108,16 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
   }
   // compute: chunk i of blocks once its rows are in place
   const Coords full = offline_coords(p);
+  // the chirp table and delays (on S) come before every chunk
+  hipEvent_t eS = nullptr;
+  if (two) {
+    eS = take(ax);
+    if ((e = hipEventRecord(eS, S)) != hipSuccess) return (int)e;
+    if ((e = hipStreamWaitEvent(S2, eS, 0)) != hipSuccess) return (int)e;
+  }
   for (int i = 0; i < C; ++i) {
-    if ((e = hipStreamWaitEvent(S, evT[i], 0)) != hipSuccess) return (int)e;
+    hipStream_t Q = (two && (i & 1)) ? S2 : S;
+    if ((e = hipStreamWaitEvent(Q, evT[i], 0)) != hipSuccess) return (int)e;
     const int64_t k0 = kb[i], nb = kb[i + 1] - kb[i];
     if (nb > 0) {
       Coords co = full;
@@ -100,15 +126,19 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
       co.u_lim = p.t_int - u0;
       co.o_lim = p.nsamp - k0 * p.M;
       co.nblocks = nb;
-      if ((err = stage_begin(S, &tok))) return err;
+      if ((err = stage_begin(Q, &tok))) return err;
       if ((err = launch_block_co(p, co, xt, tile, P + u0,
-                                 volt_out ? (char*)volt_out + k0 * p.M * 8 : nullptr, H, S)))
+                                 volt_out ? (char*)volt_out + k0 * p.M * 8 : nullptr, H, Q)))
         return err;
-      if ((err = stage_end(kStageBlock, S, tok))) return err;
+      if ((err = stage_end(kStageBlock, Q, tok))) return err;
     }
     evB[i] = take(ax);
-    if ((e = hipEventRecord(evB[i], S)) != hipSuccess) return (int)e;
+    if ((e = hipEventRecord(evB[i], Q)) != hipSuccess) return (int)e;
   }
+  // the caller's stream continues after every chunk (those on S2 included)
+  if (two)
+    for (int i = 1; i < C; i += 2)
+      if ((e = hipStreamWaitEvent(S, evB[i], 0)) != hipSuccess) return (int)e;
   // aligned sums: u is final once every channel's P[u + d_c] is computed;
   // the last range runs on the caller's stream, right after the last chunk
   int64_t u_done = 0;
