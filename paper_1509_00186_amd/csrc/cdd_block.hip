@@ -56,7 +56,7 @@ template <> struct SchedFor<8192, 5> { using type = Sched<8192, 256, 16, 32, 16,
 template <> struct SchedFor<8192, 6> { using type = Sched<8192, 256, 16, 16, 32, 1, true, true, 3>; };
 template <> struct SchedFor<8192, 7> { using type = Sched<8192, 256, 16, 16, 32, 1, true, true, 2>; };
 template <> struct SchedFor<8192, 8> { using type = Sched<8192, 256, 16, 16, 32, 1, true, false, 4>; };
-template <> struct SchedFor<8192, 9> { using type = Sched<8192, 256, 16, 16, 32, 1, false, false, 3>; };
+template <> struct SchedFor<8192, 9> { using type = Sched<8192, 128, 16, 16, 32, 1, true, false, 2>; };
 template <> struct SchedFor<16384, 0> { using type = Sched<16384, 512, 16, 32, 32, 1, true, true, 2>; };
 template <> struct SchedFor<16384, 1> { using type = Sched<16384, 512, 16, 32, 32, 1, false, false, 2>; };
 template <> struct SchedFor<16384, 2> { using type = Sched<16384, 1024, 16, 16, 16, 4, true, false, 4>; };
