@@ -48,13 +48,11 @@ hipEvent_t take(Aux& a) {
 }
 }  // namespace
 
-int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, float* P,
-                  int32_t* d, void* H, void* volt_out, float* I, int32_t* cov, int chunks,
-                  void* stream) {
+// Library-owned auxiliary streams and events of the current device.
+static int aux_of(Aux** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return (int)e;
-  std::lock_guard<std::mutex> lk(g_aux_mu);
   Aux& ax = g_aux[dev];
   if (!ax.s) {
     if ((e = hipStreamCreateWithFlags(&ax.s, hipStreamNonBlocking)) != hipSuccess) return (int)e;
@@ -63,6 +61,57 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
       if ((e = hipEventCreateWithFlags(&ax.ev[i], hipEventDisableTiming)) != hipSuccess)
         return (int)e;
   }
+  *out = &ax;
+  return 0;
+}
+
+// One chunk: the layout change, the block kernel and the aligned sum run in
+// order on the caller's stream (no cross-stream wait in front of the block
+// kernel); the chirp table and the delays run meanwhile on the auxiliary
+// stream, which the caller's stream waits for before the block kernel.
+static int run_single(Aux& ax, const BeamPlan& p, const void* voltages, double dm, char* xt,
+                      float* P, int32_t* d, void* H, void* volt_out, float* I, int32_t* cov,
+                      hipStream_t S) {
+  hipStream_t A = ax.s;
+  hipError_t e;
+  int err = 0;
+  void* tok = nullptr;
+  DmTile tile;
+  tile.ndm = 1;
+  tile.dm[0] = dm;
+  // fork after the caller's earlier work (a previous call may still read H)
+  hipEvent_t e0 = take(ax);
+  if ((e = hipEventRecord(e0, S)) != hipSuccess) return (int)e;
+  if ((e = hipStreamWaitEvent(A, e0, 0)) != hipSuccess) return (int)e;
+  if ((err = stage_begin(A, &tok))) return err;
+  if ((err = launch_chirp_table(p, dm, H, A))) return err;
+  if ((err = launch_delays(p, tile, d, A))) return err;
+  if ((err = stage_end(kStageDelays, A, tok))) return err;
+  hipEvent_t eA = take(ax);
+  if ((e = hipEventRecord(eA, A)) != hipSuccess) return (int)e;
+  if ((err = stage_begin(S, &tok))) return err;
+  if ((err = launch_transpose(voltages, xt, p.dtype, p.nsamp, p.nchan, p.nsamp, S))) return err;
+  if ((err = stage_end(kStageTranspose, S, tok))) return err;
+  if ((e = hipStreamWaitEvent(S, eA, 0)) != hipSuccess) return (int)e;
+  if ((err = stage_begin(S, &tok))) return err;
+  if ((err = launch_block(p, xt, tile, P, volt_out, H, S))) return err;
+  if ((err = stage_end(kStageBlock, S, tok))) return err;
+  if ((err = stage_begin(S, &tok))) return err;
+  if ((err = launch_dsum(p, 1, P, d, I, cov, p.t_int, S))) return err;
+  return stage_end(kStageDsum, S, tok);
+}
+
+int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, float* P,
+                  int32_t* d, void* H, void* volt_out, float* I, int32_t* cov, int chunks,
+                  void* stream) {
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  Aux* axp = nullptr;
+  int aerr = aux_of(&axp);
+  if (aerr) return aerr;
+  Aux& ax = *axp;
+  hipError_t e = hipSuccess;
+  if (chunks <= 1)
+    return run_single(ax, p, voltages, dm, xt, P, d, H, volt_out, I, cov, (hipStream_t)stream);
   hipStream_t S = (hipStream_t)stream, A = ax.s, S2 = ax.s2;
   const size_t elem = p.dtype == CDD_CI8 ? 2 : 8;
   const int C = chunks;
