@@ -267,7 +267,7 @@ class Plan:
     """
 
     def __init__(self, beams, dm_const=0.0, phase_mode=0, fft_len=0, overlap=None,
-                 nfront=None, autotune=False):
+                 nfront=None, autotune=False, variant=0):
         import torch
         self._descs = (BeamDesc * len(beams))()
         self._keep = []
@@ -289,7 +289,8 @@ class Plan:
             d.host_dms, d.ndm, d.n_int = dms, len(b["dms"]), n_int
             d.fft_len = int(b.get("fft_len", fft_len))
             d.intensity, d.coverage = I.data_ptr(), cov.data_ptr()
-        o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode, autotune=autotune)
+        o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode, variant=variant,
+                      autotune=autotune)
         h = ctypes.c_void_p()
         _check(lib.cdd_plan_create(self._descs, len(beams), ctypes.byref(o), ctypes.byref(h)))
         self._h = h

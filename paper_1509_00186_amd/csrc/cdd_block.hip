@@ -91,7 +91,9 @@ struct BlockArgs {
 // in FP64 as q = B s^2 / (1 + x), B = D*DM*(df/N)^2/fc^3, x = s*(df/N)/fc.
 // When the channel is narrow enough that q*x^3 stays below 1e-9 turns, 1/(1+x)
 // is replaced by 1 - x + x^2 (no division); otherwise the division is exact.
-// The phase is reduced to [-1/2, 1/2] turns before the FP32 rotation.
+// The phase is reduced to r = q - rint(q) in [-1/2, 1/2] turns in FP64; the
+// rotation takes the hardware sine and cosine, whose argument is in turns
+// (absolute error about 1.2e-7 on [-1/2, 1/2]).
 template <class S>
 __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, const BlockArgs& a,
                                             int t) {
@@ -102,8 +104,13 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
   const float inv_n = 1.0f / (float)N;
   if (a.phase_mode == CDD_PHASE_FP64_REDUCED) {
     const double dfn = a.df / (double)N;
-    const double B64 = 64.0 * a.dconst * dm * dfn * dfn / (fc * fc * fc);  // 1/64 turns
+    const double B = a.dconst * dm * dfn * dfn / (fc * fc * fc);  // turns
     const double beta = dfn / fc;
+    auto rot = [&](float2 z, double q) {
+      const float r = (float)(q - rint(q));
+      const float c = __builtin_amdgcn_cosf(r) * inv_n, s = __builtin_amdgcn_sinf(r) * inv_n;
+      return make_float2(z.x * c + z.y * s, z.y * c - z.x * s);  // z (c - i s)
+    };
     if (a.exact_div == 0) {
 #pragma unroll
       for (int b = 0; b < BPT; ++b) {
@@ -112,9 +119,7 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
         for (int r = 0; r < R; ++r) {
           const double sd = s0 + (double)(r * (N / R) - (2 * r >= R ? N : 0));
           const double x = beta * sd;
-          const double q64 = (B64 * (sd * sd)) * fma(x, x, 1.0 - x);
-          const float2 h = expi_neg_turns64(q64);
-          v[b * R + r] = cmul(v[b * R + r], make_float2(h.x * inv_n, h.y * inv_n));
+          v[b * R + r] = rot(v[b * R + r], (B * (sd * sd)) * fma(x, x, 1.0 - x));
         }
       }
     } else {
@@ -124,9 +129,7 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const double sd = s0 + (double)(r * (N / R) - (2 * r >= R ? N : 0));
-          const double q64 = (B64 * (sd * sd)) / fma(beta, sd, 1.0);
-          const float2 h = expi_neg_turns64(q64);
-          v[b * R + r] = cmul(v[b * R + r], make_float2(h.x * inv_n, h.y * inv_n));
+          v[b * R + r] = rot(v[b * R + r], (B * (sd * sd)) / fma(beta, sd, 1.0));
         }
       }
     }
@@ -651,9 +654,12 @@ int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_t
     case 1024: return launch_batch_t<1024, 0>(ht, nbeams, total, dt, counter, stream);
     case 2048: return launch_batch_t<2048, 0>(ht, nbeams, total, dt, counter, stream);
     case 4096: return launch_batch_t<4096, 3>(ht, nbeams, total, dt, counter, stream);
-    case 8192:  // 16x16x16x2 schedules: the radix-32 one holds too many registers with a tile
-      return v == 2 ? launch_batch_t<8192, 2>(ht, nbeams, total, dt, counter, stream)
-                    : launch_batch_t<8192, 1>(ht, nbeams, total, dt, counter, stream);
+    case 8192:
+      switch (v) {
+        case 1: return launch_batch_t<8192, 1>(ht, nbeams, total, dt, counter, stream);
+        case 2: return launch_batch_t<8192, 2>(ht, nbeams, total, dt, counter, stream);
+        default: return launch_batch_t<8192, 0>(ht, nbeams, total, dt, counter, stream);
+      }
     case 16384: return launch_batch_t<16384, 2>(ht, nbeams, total, dt, counter, stream);
   }
   return (int)hipErrorInvalidValue;
