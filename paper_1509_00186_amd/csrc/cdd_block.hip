@@ -653,14 +653,18 @@ int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_t
     case 512: return launch_batch_t<512, 0>(ht, nbeams, total, dt, counter, stream);
     case 1024: return launch_batch_t<1024, 0>(ht, nbeams, total, dt, counter, stream);
     case 2048: return launch_batch_t<2048, 0>(ht, nbeams, total, dt, counter, stream);
-    case 4096: return launch_batch_t<4096, 3>(ht, nbeams, total, dt, counter, stream);
+    case 4096:
+      return v == 3 ? launch_batch_t<4096, 3>(ht, nbeams, total, dt, counter, stream)
+                    : launch_batch_t<4096, 0>(ht, nbeams, total, dt, counter, stream);
     case 8192:
       switch (v) {
         case 1: return launch_batch_t<8192, 1>(ht, nbeams, total, dt, counter, stream);
         case 2: return launch_batch_t<8192, 2>(ht, nbeams, total, dt, counter, stream);
         default: return launch_batch_t<8192, 0>(ht, nbeams, total, dt, counter, stream);
       }
-    case 16384: return launch_batch_t<16384, 2>(ht, nbeams, total, dt, counter, stream);
+    case 16384:
+      return v == 2 ? launch_batch_t<16384, 2>(ht, nbeams, total, dt, counter, stream)
+                    : launch_batch_t<16384, 0>(ht, nbeams, total, dt, counter, stream);
   }
   return (int)hipErrorInvalidValue;
 }
