@@ -27,6 +27,11 @@ design notes of the repository):
   [nfront, nfront + M) are kept, the rest (front and end wrap-around) dropped.
 * Detection and integration (Sec. 3.1, the write-to-disk routine): |y|^2
   summed over non-overlapping groups of n_int samples starting at sample 0.
+* Taper (Sec. 2.2): the chirp function is the inverse transfer function
+  multiplied by a window over the band the transform covers (here one
+  channel): none (rectangular), Hanning 1/2 (1 + cos 2 pi x) or Welch
+  1 - (2 x)^2, with x = f / df the bin's offset from the channel centre as a
+  fraction of the channel width, x in [-1/2, 1/2).
 * Incoherent alignment of channels (Sec. 1.2; the linear term of Eq. 2):
   per-channel delay d_c = floor(D*DM*(f_c^-2 - f_ref^-2)*df/n_int + 0.5)
   integrated samples, f_ref the highest channel centre (lowest for DM < 0);
@@ -74,12 +79,31 @@ def chirp_turns(f: np.ndarray, f0: float, dm: float, dconst: float = D_PAPER):
     return dconst * dm * f * f / (f0 * f0 * (f0 + f))
 
 
+TAPERS = ("none", "hann", "welch")
+
+
+def taper(n: int, kind: str = "none") -> np.ndarray:
+    """Window over the n bins of a channel transform (Sec. 2.2, the taper
+    that turns the inverse transfer function into the chirp function).
+    x = offset / df in [-1/2, 1/2) for bin j (j < n/2: j/n, else j/n - 1)."""
+    j = np.arange(n)
+    x = np.where(j < n // 2, j, j - n).astype(np.float64) / n
+    if kind == "none":
+        return np.ones(n)
+    if kind == "hann":
+        return 0.5 * (1.0 + np.cos(2.0 * np.pi * x))
+    if kind == "welch":
+        return 1.0 - (2.0 * x) ** 2
+    raise ValueError("unknown taper %r" % kind)
+
+
 def transfer(n: int, f0: float, df: float, dm: float, dconst: float = D_PAPER,
-             sign: int = -1) -> np.ndarray:
-    """The all-pass filter on the n bins: exp(sign * 2 pi i q).  sign=-1
-    dedisperses, sign=+1 disperses.  Evaluated directly in float64."""
+             sign: int = -1, window: str = "none") -> np.ndarray:
+    """The filter on the n bins: exp(sign * 2 pi i q), times the taper.
+    sign=-1 dedisperses, sign=+1 disperses.  Evaluated directly in float64;
+    without a taper it is all-pass."""
     q = chirp_turns(bin_offsets(n, df), f0, dm, dconst)
-    return np.exp(sign * 2j * np.pi * q)
+    return np.exp(sign * 2j * np.pi * q) * taper(n, window)
 
 
 # --------------------------------------------------------------------------
@@ -243,13 +267,15 @@ def as_complex(voltages: np.ndarray) -> np.ndarray:
 def dedisperse(voltages, f_centre: float, bw: float, dm: float, n_int: int,
                fft_len: int | None = None, overlap: int | None = None,
                nfront: int | None = None, dconst: float = D_PAPER,
-               channels=None, want_voltages: bool = False, sign: int = -1):
+               channels=None, want_voltages: bool = False, sign: int = -1,
+               window: str = "none"):
     """Coherent dedispersion of every channel, detection, integration and
     the delay-aligned channel sum.
 
     voltages: [T][C][2] int8 or [T][C] complex (time-major).  (N, L, nfront)
     default to ``overlap_plan``.  ``channels`` restricts the per-channel work
-    to a subset (then I and cov are not formed).  Returns a dict with
+    to a subset (then I and cov are not formed).  ``window`` selects the
+    taper ("none", "hann", "welch").  Returns a dict with
     N, L, nfront, P [C][T_int], and, over all channels, I, cov, d; and y
     [C][T] if asked.
     """
@@ -266,7 +292,7 @@ def dedisperse(voltages, f_centre: float, bw: float, dm: float, n_int: int,
     P = np.zeros((len(chans), T // n_int))
     Y = np.zeros((len(chans), T), dtype=np.complex128) if want_voltages else None
     for i, c in enumerate(chans):
-        H = transfer(fft_len, fc[c], df, dm, dconst, sign)
+        H = transfer(fft_len, fc[c], df, dm, dconst, sign, window)
         y = overlap_save(x[:, c], H, overlap, nfront)
         P[i] = detect_integrate(y, n_int)
         if want_voltages:

@@ -308,3 +308,54 @@ def test_nyquist_bin_is_lower_band_edge():
     off = O.bin_offsets(16, 2.0)
     assert off[8] == -1.0 and off[7] == 7 * 2.0 / 16 and off.min() == -1.0
     assert off.max() < 1.0
+
+
+# ---------------------------------------------------------------------------
+# Taper windows (Sec. 2.2: the window that turns the inverse transfer
+# function into the chirp function)
+# ---------------------------------------------------------------------------
+def test_hanning_at_zero_dm_is_the_three_tap_smoother():
+    """A raised-cosine window over the channel is, in time, y[t] = x[t]/2 +
+    (x[t-1] + x[t+1])/4 (the window is 1/2 + (e^{+} + e^{-})/4 in frequency).
+    With DM 0 and a block margin of at least one sample each side, the
+    whole overlap-save output must equal that three-tap filter exactly
+    (zeros before the start and after the end)."""
+    rng = np.random.default_rng(11)
+    T, N, L, nf = 3000, 256, 8, 4
+    x = rng.standard_normal(T) + 1j * rng.standard_normal(T)
+    H = O.transfer(N, 300.0, 0.5, 0.0, window="hann")
+    y = O.overlap_save(x, H, L, nf)
+    xp = np.concatenate(([0], x, [0]))
+    ref = 0.5 * xp[1:-1] + 0.25 * (xp[:-2] + xp[2:])
+    assert np.max(np.abs(y - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("window,gains", [("hann", (1.0, 0.5, 0.5, 0.0)),
+                                          ("welch", (1.0, 0.75, 0.75, 0.0))])
+def test_taper_scales_tones_by_their_place_in_the_channel(window, gains):
+    """Pure tones through the DM-0 filter: at the channel centre the gain is
+    1, a quarter of the channel width above or below it the window's value
+    there, at the lower band edge (the N/2 bin) 0 -- measured on the output amplitude
+    in the block interiors, which fixes the window's orientation and edge."""
+    T, N, L, nf = 4096, 256, 64, 32
+    t = np.arange(T)
+    for frac, g in zip((0.0, 0.25, -0.25, -0.5), gains):
+        x = np.exp(2j * np.pi * frac * t)
+        y = O.overlap_save(x, O.transfer(N, 300.0, 0.5, 0.0, window=window), L, nf)
+        mid = slice(N, T - N)
+        assert np.allclose(y[mid], g * x[mid], atol=1e-9), (window, frac)
+
+
+@pytest.mark.parametrize("window", ["hann", "welch"])
+def test_tapered_block_energy_is_the_windowed_spectral_energy(window):
+    """Parseval with the taper: for every block, the inverse transform's
+    energy equals (1/N) sum |w_j S_j|^2 -- the chirp function's magnitude is
+    exactly the window and its phase unimodular, at a large DM."""
+    rng = np.random.default_rng(12)
+    N, fc, df, dm = 2048, 330.0, 0.0625, 60.0
+    s = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    S = np.fft.fft(s)
+    z = np.fft.ifft(S * O.transfer(N, fc, df, dm, window=window))
+    w = O.taper(N, window)
+    assert abs(np.sum(np.abs(z) ** 2) - np.sum(np.abs(w * S) ** 2) / N) \
+        <= 1e-12 * np.sum(np.abs(S) ** 2) / N
