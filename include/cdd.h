@@ -79,6 +79,16 @@ typedef enum {
   CDD_PHASE_FP32 = 1          /* q and sin/cos in FP32 (precision study)     */
 } cdd_phase_mode;
 
+/* Taper of the chirp function over each channel (Sec. 2.2: the window that
+ * multiplies the inverse transfer function; it trades the ripple of the
+ * rectangular band edge for sensitivity at the edges).  x = the bin's offset
+ * from the channel centre over the channel width, in [-1/2, 1/2). */
+typedef enum {
+  CDD_TAPER_NONE = 0,  /* rectangular: |H| = 1                               */
+  CDD_TAPER_HANN = 1,  /* Hanning: (1 + cos 2 pi x) / 2                      */
+  CDD_TAPER_WELCH = 2  /* Welch: 1 - (2 x)^2                                 */
+} cdd_taper;
+
 /* Options.  Zero-initialise; zero fields take the rule-based defaults. */
 typedef struct {
   int32_t explicit_plan;   /* 1: use fft_len/overlap/nfront as given        */
@@ -95,7 +105,9 @@ typedef struct {
                               time chunks so the layout change and aligned
                               sums overlap the block kernel; 0 = automatic,
                               1 = no split                                 */
-  int32_t reserved[4];
+  int32_t taper;           /* cdd_taper; the plan (N, L, nfront) is the same
+                              with or without a taper                      */
+  int32_t reserved[3];
 } cdd_opts;
 
 /* Plan figures for one beam (filled by cdd_query / cdd_plan_info). */
@@ -228,7 +240,8 @@ typedef struct {
   int32_t n_int;
   int64_t max_block;      /* largest block a push may carry (samples/chan)   */
   int32_t phase_mode;
-  int32_t reserved[5];
+  int32_t taper;          /* cdd_taper                                      */
+  int32_t reserved[4];
 } cdd_stream_desc;
 
 typedef struct {

@@ -30,7 +30,8 @@ class Opts(ctypes.Structure):
                 ("overlap", ctypes.c_int32), ("nfront", ctypes.c_int32),
                 ("dm_const", ctypes.c_double), ("phase_mode", ctypes.c_int32),
                 ("kernel_variant", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("time_chunks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("time_chunks", ctypes.c_int32), ("taper", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -71,7 +72,7 @@ class StreamDesc(ctypes.Structure):
                 ("f_centre_mhz", ctypes.c_double), ("bw_mhz", ctypes.c_double),
                 ("dm", ctypes.c_double), ("fft_len", ctypes.c_int32), ("n_int", ctypes.c_int32),
                 ("max_block", ctypes.c_int64), ("phase_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("taper", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class ServerStats(ctypes.Structure):
@@ -169,9 +170,13 @@ def autotune(nchan, f_centre, bw, dms, n_int, n_min=0, n_max=0, dtype=CDD_CI8):
     return {k: getattr(r, k) for k, _ in r._fields_}
 
 
+TAPERS = {"none": 0, "hann": 1, "welch": 2}
+
+
 def make_opts(fft_len=0, overlap=None, nfront=None, dm_const=0.0, phase_mode=0, variant=0,
-              autotune=0, time_chunks=0):
+              autotune=0, time_chunks=0, taper="none"):
     o = Opts()
+    o.taper = TAPERS[taper] if isinstance(taper, str) else int(taper)
     o.kernel_variant = int(variant)
     o.autotune = int(autotune)
     o.time_chunks = int(time_chunks)
@@ -219,7 +224,7 @@ def _stream_handle(stream):
 
 def dedisperse(voltages, f_centre, bw, dm, fft_len=0, n_int=1, *, want_chan=False,
                want_voltages=False, overlap=None, nfront=None, dm_const=0.0, phase_mode=0,
-               variant=0, time_chunks=0, stream=None, out=None):
+               variant=0, time_chunks=0, taper="none", stream=None, out=None):
     """Run cdd_dedisperse on a resident device tensor.
 
     Returns a dict: I [t_int] float32, cov [t_int] int32, P [nchan][t_int]
@@ -231,7 +236,7 @@ def dedisperse(voltages, f_centre, bw, dm, fft_len=0, n_int=1, *, want_chan=Fals
         raise ValueError("voltages must be a contiguous device tensor")
     dt, nsamp, nchan = _layout(voltages)
     o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode, variant,
-                  time_chunks=time_chunks)
+                  time_chunks=time_chunks, taper=taper)
     info = PlanInfo()
     _check(lib.cdd_query(dt, nsamp, nchan, float(f_centre), float(bw), float(dm), int(fft_len),
                          int(n_int), int(want_voltages), ctypes.byref(o), ctypes.byref(info)))
@@ -267,7 +272,7 @@ class Plan:
     """
 
     def __init__(self, beams, dm_const=0.0, phase_mode=0, fft_len=0, overlap=None,
-                 nfront=None, autotune=False, variant=0):
+                 nfront=None, autotune=False, variant=0, taper="none"):
         import torch
         self._descs = (BeamDesc * len(beams))()
         self._keep = []
@@ -290,7 +295,7 @@ class Plan:
             d.fft_len = int(b.get("fft_len", fft_len))
             d.intensity, d.coverage = I.data_ptr(), cov.data_ptr()
         o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode, variant=variant,
-                      autotune=autotune)
+                      autotune=autotune, taper=taper)
         h = ctypes.c_void_p()
         _check(lib.cdd_plan_create(self._descs, len(beams), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -331,12 +336,14 @@ class Server:
         _check(lib.cdd_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h
 
-    def open(self, dtype, nchan, f_centre, bw, dm, n_int, max_block, fft_len=0, phase_mode=0):
+    def open(self, dtype, nchan, f_centre, bw, dm, n_int, max_block, fft_len=0, phase_mode=0,
+             taper="none"):
         d = StreamDesc()
         d.dtype, d.nchan, d.f_centre_mhz, d.bw_mhz, d.dm = int(dtype), int(nchan), \
             float(f_centre), float(bw), float(dm)
         d.fft_len, d.n_int, d.max_block, d.phase_mode = int(fft_len), int(n_int), \
             int(max_block), int(phase_mode)
+        d.taper = TAPERS[taper] if isinstance(taper, str) else int(taper)
         sid = ctypes.c_int32()
         _check(lib.cdd_stream_open(self._h, ctypes.byref(d), ctypes.byref(sid)))
         return sid.value

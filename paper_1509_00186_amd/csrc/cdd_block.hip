@@ -80,7 +80,7 @@ struct BlockArgs {
   int64_t p_stride, p_dm_stride, u_lim;
   int64_t v_stride, o_lim;
   int64_t nblocks, item0;   // blocks per channel; first work item of this beam
-  int32_t nchan, M, nfront, n_int, dtype, phase_mode, exact_div, pad;
+  int32_t nchan, M, nfront, n_int, dtype, phase_mode, exact_div, taper;
   double f_lo, df, dconst;
   DmTile dms;
 };
@@ -106,9 +106,11 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
     const double dfn = a.df / (double)N;
     const double B = a.dconst * dm * dfn * dfn / (fc * fc * fc);  // turns
     const double beta = dfn / fc;
-    auto rot = [&](float2 z, double q) {
+    // g = taper/N; the window depends on the bin only (x = sd/N)
+    auto rot = [&](float2 z, double q, double sd) {
       const float r = (float)(q - rint(q));
-      const float c = __builtin_amdgcn_cosf(r) * inv_n, s = __builtin_amdgcn_sinf(r) * inv_n;
+      const float g = a.taper ? taper_gain<true>(a.taper, (float)sd * inv_n) * inv_n : inv_n;
+      const float c = __builtin_amdgcn_cosf(r) * g, s = __builtin_amdgcn_sinf(r) * g;
       return make_float2(z.x * c + z.y * s, z.y * c - z.x * s);  // z (c - i s)
     };
     if (a.exact_div == 0) {
@@ -119,7 +121,7 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
         for (int r = 0; r < R; ++r) {
           const double sd = s0 + (double)(r * (N / R) - (2 * r >= R ? N : 0));
           const double x = beta * sd;
-          v[b * R + r] = rot(v[b * R + r], (B * (sd * sd)) * fma(x, x, 1.0 - x));
+          v[b * R + r] = rot(v[b * R + r], (B * (sd * sd)) * fma(x, x, 1.0 - x), sd);
         }
       }
     } else {
@@ -129,7 +131,7 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const double sd = s0 + (double)(r * (N / R) - (2 * r >= R ? N : 0));
-          v[b * R + r] = rot(v[b * R + r], (B * (sd * sd)) / fma(beta, sd, 1.0));
+          v[b * R + r] = rot(v[b * R + r], (B * (sd * sd)) / fma(beta, sd, 1.0), sd);
         }
       }
     }
@@ -148,7 +150,8 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
         const float q = Af * (f * f) / (fcf + f);
         float sn, cs;
         sincospif(2.0f * q, &sn, &cs);
-        v[b * R + r] = cmul(v[b * R + r], make_float2(cs * inv_n, -sn * inv_n));
+        const float g = inv_n * taper_gain<true>(a.taper, (float)s * inv_n);
+        v[b * R + r] = cmul(v[b * R + r], make_float2(cs * g, -sn * g));
       }
     }
   }
@@ -373,11 +376,12 @@ __global__ void zero_counter_kernel(unsigned int* c) { *c = 0u; }
 // q = D*DM*f^2/(fc^2 (fc + f)) turns (Eq. 3).  q (up to ~1e5 turns) and its
 // reduction r = q - rint(q) to [-1/2, 1/2] turns are FP64 with an exact
 // division; sin/cos of 2 pi r are FP32.  The FP32 phase mode forms q itself
-// in FP32 (precision study).
+// in FP32 (precision study).  The taper (Sec. 2.2) scales the entry with the
+// 1/N of the inverse transform.
 __global__ __launch_bounds__(256) void chirp_table_kernel(float2* __restrict__ H, int32_t lgN,
                                                           int32_t nchan, double f_lo, double df,
                                                           double dconst, double dm,
-                                                          int32_t phase_mode) {
+                                                          int32_t phase_mode, int32_t taper) {
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (g >= ((int64_t)nchan << lgN)) return;
   const int N = 1 << lgN;
@@ -392,8 +396,8 @@ __global__ __launch_bounds__(256) void chirp_table_kernel(float2* __restrict__ H
     const float r = (float)(q - rint(q));
     float sn, cs;
     sincospif(2.0f * r, &sn, &cs);
-    const float inv_n = 1.0f / (float)N;
-    h = make_float2(cs * inv_n, -sn * inv_n);
+    const float gn = taper_gain<false>(taper, (float)s / (float)N) / (float)N;
+    h = make_float2(cs * gn, -sn * gn);
   } else {
     const float fcf = (float)fc;
     const float Af = (float)(dconst * dm) / (fcf * fcf);
@@ -401,8 +405,8 @@ __global__ __launch_bounds__(256) void chirp_table_kernel(float2* __restrict__ H
     const float q = Af * (f * f) / (fcf + f);
     float sn, cs;
     sincospif(2.0f * q, &sn, &cs);
-    const float inv_n = 1.0f / (float)N;
-    h = make_float2(cs * inv_n, -sn * inv_n);
+    const float gn = taper_gain<false>(taper, (float)s / (float)N) / (float)N;
+    h = make_float2(cs * gn, -sn * gn);
   }
   H[g] = h;
 }
@@ -494,6 +498,7 @@ static BlockArgs make_args(const BeamPlan& p, const Coords& co, const void* xt, 
   a.dtype = p.dtype;
   a.phase_mode = p.phase_mode;
   a.exact_div = needs_exact_division(p, dms);
+  a.taper = p.taper;
   a.f_lo = p.f_lo;
   a.df = p.df;
   a.dconst = p.dconst;
@@ -628,7 +633,8 @@ int launch_chirp_table(const BeamPlan& p, double dm, void* H, void* stream) {
   const int64_t grid = (n + 255) / 256;
   if (grid > 0x7fffffffLL) return (int)hipErrorInvalidValue;
   hipLaunchKernelGGL(chirp_table_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
-                     (float2*)H, log2i(p.N), p.nchan, p.f_lo, p.df, p.dconst, dm, p.phase_mode);
+                     (float2*)H, log2i(p.N), p.nchan, p.f_lo, p.df, p.dconst, dm, p.phase_mode,
+                     p.taper);
   return (int)hipGetLastError();
 }
 

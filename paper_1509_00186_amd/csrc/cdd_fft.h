@@ -7,6 +7,8 @@
 
 #include <typeinfo>
 
+#include "cdd.h"
+
 #include <cmath>
 #include <type_traits>
 #include <utility>
@@ -386,6 +388,20 @@ __device__ __forceinline__ void fft_inverse(float2* v, float* lds, const float2*
     if constexpr (!S::PF) pt.load(tw, t);
     butterflies<S, S::rad_i(q), S::ns_i(q), +1, S::tw_i(q)>(v, pt);
   });
+}
+
+// Taper of the chirp function over the channel (Sec. 2.2) at x = the bin's
+// offset over the channel width, x in [-1/2, 1/2): Hanning (1 + cos 2 pi x)/2,
+// Welch 1 - (2x)^2, else 1.  FAST takes the hardware cosine (argument in
+// turns, absolute error about 1.2e-7) instead of cospif.
+template <bool FAST>
+__device__ __forceinline__ float taper_gain(int kind, float x) {
+  if (kind == CDD_TAPER_HANN) {
+    const float c = FAST ? __builtin_amdgcn_cosf(x) : cospif(2.0f * x);
+    return 0.5f + 0.5f * c;
+  }
+  if (kind == CDD_TAPER_WELCH) return fmaf(-4.0f * x, x, 1.0f);
+  return 1.0f;
 }
 
 // cos and sin of 2 pi k / 64 for the 64 octant-of-an-octant rotations.

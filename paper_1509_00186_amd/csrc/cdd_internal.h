@@ -28,6 +28,7 @@ struct BeamPlan {
   double f_centre = 0, bw = 0, df = 0, f_lo = 0, dconst = kDefaultD;
   int32_t n_int = 1;
   int32_t phase_mode = CDD_PHASE_FP64_REDUCED;
+  int32_t taper = CDD_TAPER_NONE;
   int32_t variant = 0;  // block-kernel schedule (autotuner choice)
   std::vector<double> dms;
   int32_t N = 0, L = 0, nfront = 0, M = 0;

@@ -44,7 +44,7 @@ struct LargeArgs {
   const float2* twr;    // row sub-transform twiddles
   const float2* tw4;    // four-step twiddles: W_N^m = lo[m & (2^sl-1)] * hi[m >> sl]
   int64_t nsamp, nblocks, item0;
-  int32_t nchan, N1, N2, M, nfront, sl, phase_mode, exact_div;
+  int32_t nchan, N1, N2, M, nfront, sl, phase_mode, exact_div, taper;
   double f_lo, df, dconst, dm;
 };
 
@@ -138,7 +138,8 @@ __global__ __launch_bounds__(SR::T * G) void rows_kernel(const LargeArgs a) {
         const double q = a.exact_div ? (B * (sd * sd)) / fma(beta, sd, 1.0)
                                      : (B * (sd * sd)) * fma(x, x, 1.0 - x);
         const float2 h = expi_neg_turns(q - rint(q));
-        v[b * RL + r] = cmul(v[b * RL + r], make_float2(h.x * inv_n, h.y * inv_n));
+        const float g = inv_n * taper_gain<false>(a.taper, (float)sd * inv_n);
+        v[b * RL + r] = cmul(v[b * RL + r], make_float2(h.x * g, h.y * g));
       }
   } else {
     const float fcf = (float)fc;
@@ -150,11 +151,13 @@ __global__ __launch_bounds__(SR::T * G) void rows_kernel(const LargeArgs a) {
       for (int r = 0; r < RL; ++r) {
         const int64_t k1 = tl + SR::T * b + r * (L / RL);
         const int64_t i = k2 + (int64_t)a.N2 * k1;
-        const float f = (float)(i < N / 2 ? i : i - N) * dfn;
+        const float sf = (float)(i < N / 2 ? i : i - N);
+        const float f = sf * dfn;
         const float q = Af * (f * f) / (fcf + f);
         float sn, cs;
         sincospif(2.0f * q, &sn, &cs);
-        v[b * RL + r] = cmul(v[b * RL + r], make_float2(cs * inv_n, -sn * inv_n));
+        const float g = inv_n * taper_gain<false>(a.taper, sf * inv_n);
+        v[b * RL + r] = cmul(v[b * RL + r], make_float2(cs * g, -sn * g));
       }
   }
   fft_inverse<SR>(v, my, a.twr, tl);
@@ -279,6 +282,7 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
   a.nfront = p.nfront;
   a.sl = (LGN + 1) / 2;
   a.phase_mode = p.phase_mode;
+  a.taper = p.taper;
   a.exact_div = exact_div;
   a.f_lo = p.f_lo;
   a.df = p.df;

@@ -97,6 +97,9 @@ cdd_status make_plan(int32_t dtype, int64_t nsamp, int32_t nchan,
     if (opts->phase_mode != CDD_PHASE_FP64_REDUCED && opts->phase_mode != CDD_PHASE_FP32)
       return fail(CDD_EINVAL, "unknown phase_mode %d", opts->phase_mode);
     p.phase_mode = opts->phase_mode;
+    if (opts->taper < CDD_TAPER_NONE || opts->taper > CDD_TAPER_WELCH)
+      return fail(CDD_EINVAL, "unknown taper %d", opts->taper);
+    p.taper = opts->taper;
     p.variant = opts->kernel_variant;
   }
 

@@ -474,6 +474,7 @@ cdd_status cdd_stream_open(cdd_server* sv, const cdd_stream_desc* d, int32_t* id
   if (d->max_block < 1) return fail(CDD_EINVAL, "max_block must be >= 1");
   cdd_opts o{};
   o.phase_mode = d->phase_mode;
+  o.taper = d->taper;
   BeamPlan p;
   cdd_status s = make_plan(d->dtype, d->max_block, d->nchan, d->f_centre_mhz, d->bw_mhz, &d->dm,
                            1, d->fft_len, d->n_int, &o, &p);

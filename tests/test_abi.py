@@ -109,6 +109,11 @@ def test_explicit_plan_validation():
         cdd.query(0, 10_000, 64, 325.0, 4.0, 30.0, 1024, 4, dm_const=-1.0)
     with pytest.raises(cdd.CddError, match="phase_mode"):
         cdd.query(0, 10_000, 64, 325.0, 4.0, 30.0, 1024, 4, phase_mode=7)
+    with pytest.raises(cdd.CddError, match="taper"):
+        cdd.query(0, 10_000, 64, 325.0, 4.0, 30.0, 1024, 4, taper=3)
+    # the taper leaves the plan unchanged
+    assert cdd.query(0, 10_000, 64, 325.0, 4.0, 30.0, 1024, 4, taper="hann") == \
+        cdd.query(0, 10_000, 64, 325.0, 4.0, 30.0, 1024, 4)
 
 
 def test_dedisperse_rejects_bad_workspace_without_touching_device():

@@ -21,17 +21,19 @@ def _cdd():
     return cdd
 
 
-def _run_both(v, fcen, bw, dm, n_int, fft_len=0, phase_mode=0, want_v=True, **plan):
+def _run_both(v, fcen, bw, dm, n_int, fft_len=0, phase_mode=0, want_v=True, taper="none",
+              **plan):
     import torch
     cdd = _cdd()
-    flush("case: shape=%s dtype=%s fcen=%g bw=%g dm=%g n_int=%d N=%d phase=%d" %
-          (tuple(v.shape), v.dtype, fcen, bw, dm, n_int, fft_len, phase_mode))
+    flush("case: shape=%s dtype=%s fcen=%g bw=%g dm=%g n_int=%d N=%d phase=%d taper=%s" %
+          (tuple(v.shape), v.dtype, fcen, bw, dm, n_int, fft_len, phase_mode, taper))
     g = cdd.dedisperse(to_dev(v), fcen, bw, dm, fft_len, n_int, want_chan=True,
-                       want_voltages=want_v, phase_mode=phase_mode, **plan)
+                       want_voltages=want_v, phase_mode=phase_mode, taper=taper, **plan)
     torch.cuda.synchronize()
     info = g["info"]
     o = O.dedisperse(v, fcen, bw, dm, n_int, fft_len=info["fft_len"],
-                     overlap=info["overlap"], nfront=info["nfront"], want_voltages=want_v)
+                     overlap=info["overlap"], nfront=info["nfront"], want_voltages=want_v,
+                     window=taper)
     got = {k: g[k].cpu().numpy() for k in ("I", "cov", "P") + (("y",) if want_v else ())}
     return got, o, info
 
@@ -122,6 +124,57 @@ def test_phase_fp32_variant_error_is_reported_not_hidden():
     assert e64 <= TOL_V
     assert e32 > e64          # the FP32 phase is measurably worse
     assert rel_l2(got32["I"], o["I"]) <= 1e-3
+
+
+@pytest.mark.parametrize("window", ["hann", "welch"])
+def test_taper_one_dm_against_oracle(window):
+    """Tapered chirp function (Sec. 2.2) through the one-DM path (table
+    built per call): voltages, per-channel and aligned intensities."""
+    v = _beam_int8(130, 30_000, 24, 325.0, 24 * 0.0625, 67.9)
+    import torch
+    cdd = _cdd()
+    g = cdd.dedisperse(to_dev(v), 325.0, 24 * 0.0625, 67.9, 2048, 4, want_chan=True,
+                       want_voltages=True, taper=window)
+    torch.cuda.synchronize()
+    info = g["info"]
+    o = O.dedisperse(v, 325.0, 24 * 0.0625, 67.9, 4, fft_len=2048, overlap=info["overlap"],
+                     nfront=info["nfront"], want_voltages=True, window=window)
+    got = {k: g[k].cpu().numpy() for k in ("I", "cov", "P", "y")}
+    _check(got, o)
+    # the taper changes the result (it is not silently ignored)
+    plain = O.dedisperse(v, 325.0, 24 * 0.0625, 67.9, 4, fft_len=2048,
+                         overlap=info["overlap"], nfront=info["nfront"])
+    assert rel_l2(got["I"], plain["I"]) > 1e-3
+
+
+@pytest.mark.parametrize("window", ["hann", "welch"])
+def test_taper_batched_dm_trials_against_oracle(window):
+    """The taper in the chirp generated inside the persistent batched kernel."""
+    import torch
+    cdd = _cdd()
+    v = _beam_int8(131, 12_000, 16, 610.0, 16 * 0.03125, 10.0)
+    dms = [10.0, 11.5, 8.0]
+    plan = cdd.Plan([dict(voltages=to_dev(v), f_centre=610.0, bw=0.5, dms=dms, n_int=2,
+                          fft_len=1024)], taper=window)
+    plan.execute()
+    torch.cuda.synchronize()
+    info = plan.info(0)
+    for i, dm in enumerate(dms):
+        o = O.dedisperse(v, 610.0, 0.5, dm, 2, fft_len=1024, overlap=info["overlap"],
+                         nfront=info["nfront"], window=window)
+        assert rel_l2(plan.I[0][i].cpu().numpy(), o["I"]) <= TOL_I, (window, dm)
+    plan.close()
+
+
+def test_taper_long_transform_against_oracle():
+    """Hanning taper on the four-step path (N = 2^15)."""
+    N = 1 << 15
+    rng = np.random.default_rng(132)
+    nsamp = 2 * N + 777
+    x = (rng.standard_normal(nsamp) + 1j * rng.standard_normal(nsamp)).astype(np.complex64)
+    got, o, info = _run_both(x, 300.0, 4.0, 1.5, 8, N, taper="hann")
+    assert info["fft_len"] == N
+    _check(got, o)
 
 
 def test_config2_full_size():

@@ -89,6 +89,26 @@ def test_narrow_stream_alone_matches_oracle(cf):
     assert rel_l2(I, o["I"]) <= 1e-4, rel_l2(I, o["I"])
 
 
+def test_tapered_stream_matches_whole_record():
+    """A Welch-tapered stream equals the tapered whole-record call and the
+    oracle."""
+    import torch
+    cdd = _cdd()
+    fcen, nchan, df, nsamp, dm, N = 325.0, 8, 0.0625, 20_000, 40.0, 2048
+    v = _beam_int8(140, nsamp, nchan, fcen, nchan * df, dm)
+    sv = cdd.Server()
+    sid = sv.open(0, nchan, fcen, nchan * df, dm, 4, 3000, N, taper="welch")
+    u0, I = _stream_all(sv, sid, v, _sizes(np.random.default_rng(8), nsamp, 500, 3000))
+    sv.close()
+    g = cdd.dedisperse(to_dev(v), fcen, nchan * df, dm, N, 4, taper="welch")
+    torch.cuda.synchronize()
+    assert u0 == 0 and rel_l2(I, g["I"].cpu().numpy()) <= 1e-6
+    q = g["info"]
+    o = O.dedisperse(v, fcen, nchan * df, dm, 4, fft_len=N, overlap=q["overlap"],
+                     nfront=q["nfront"], window="welch")
+    assert rel_l2(I, o["I"]) <= 1e-4
+
+
 def test_stream_same_alone_and_in_a_mix():
     cdd = _cdd()
     specs = [(325.0, 16, 0.0625, 30_000, 67.9, 2048, 0),
