@@ -101,14 +101,14 @@ def cpu_baseline(v, b, seconds: float):
                       % (len(chans), b.nchan, b.nsamp, dt)}
 
 
-def dm_trials(cdd, torch, vd, b, info, reps: int = 3):
+def dm_trials(cdd, torch, vd, b, info, reps: int = 3, taper: str = "none"):
     """64 DM trials (60.0 + 0.254 i) on the same resident beam: the batched
     plan (forward transform shared, one persistent launch per 64 trials)
     against a plain loop of single-DM calls at the same (N, L, nfront)."""
     import synth
     dms = synth.config(4).dms
     plan = cdd.Plan([dict(voltages=vd, f_centre=b.f_centre, bw=b.bw, dms=dms, n_int=b.n_int,
-                          fft_len=b.fft_len)])
+                          fft_len=b.fft_len)], taper=taper)
     pi = plan.info(0)
     plan.execute()
     torch.cuda.synchronize()
@@ -118,13 +118,13 @@ def dm_trials(cdd, torch, vd, b, info, reps: int = 3):
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
     outs = [cdd.dedisperse(vd, b.f_centre, b.bw, dm, pi["fft_len"], b.n_int,
-                           overlap=pi["overlap"], nfront=pi["nfront"]) for dm in dms]
+                           overlap=pi["overlap"], nfront=pi["nfront"], taper=taper) for dm in dms]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         for dm, o in zip(dms, outs):
             cdd.dedisperse(vd, b.f_centre, b.bw, dm, pi["fft_len"], b.n_int,
-                           overlap=pi["overlap"], nfront=pi["nfront"], out=o)
+                           overlap=pi["overlap"], nfront=pi["nfront"], taper=taper, out=o)
     torch.cuda.synchronize()
     t_loop = (time.perf_counter() - t0) / reps
     I_loop = torch.stack([o["I"] for o in outs])
@@ -215,13 +215,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dm-trials", action="store_true")
+    ap.add_argument("--taper", default="none", choices=["none", "hann", "welch"],
+                    help="taper of the chirp function over each channel")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving run length (config 5)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only (the path shards by channel; see the design "
-              "notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only (on several GPUs the path would shard by "
+              "channel, beam or DM trial and reduce the aligned sums); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -251,18 +254,19 @@ def main():
     b, v = make_input(args.config)
     dev = torch.device("cuda:0")
     vd = torch.from_numpy(v).to(dev)
-    out = cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int)   # allocate
+    tk = dict(taper=args.taper)
+    out = cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, **tk)   # allocate
     info = out["info"]
     torch.cuda.synchronize()
     for _ in range(args.warmup):
-        cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, out=out)
+        cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, out=out, **tk)
     torch.cuda.synchronize()
     cdd.profile_read()
     cdd.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, out=out)
+        cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, out=out, **tk)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     cdd.profile_enable(False)
@@ -298,7 +302,7 @@ def main():
         "config": {"workload": WORKLOADS[args.config], "nchan": b.nchan, "nsamp": b.nsamp,
                    "fft_len": info["fft_len"], "overlap": info["overlap"],
                    "nfront": info["nfront"], "n_int": b.n_int, "dm": b.dm,
-                   "input": "int8 time-major, resident in HBM"},
+                   "input": "int8 time-major, resident in HBM", "taper": args.taper},
         "x_realtime": round(duration_s / (ms * 1e-3), 1),
         "stages_ms_per_step": {k: round(t / args.steps, 4) for k, (t, n) in stages.items()},
         "roofline": {"kernel": "block_kernel (FFT+chirp+IFFT+detect+integrate)",
@@ -314,7 +318,7 @@ def main():
         "gflops_paper_eq5": round(flops / (blk_avg * 1e-3) / 1e9, 1),
     }
     if args.config == 2 and not args.no_dm_trials:
-        res["dm_trials"] = dm_trials(cdd, torch, vd, b, info)
+        res["dm_trials"] = dm_trials(cdd, torch, vd, b, info, taper=args.taper)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(v, b, args.cpu_seconds)
     print(json.dumps(res), flush=True)
