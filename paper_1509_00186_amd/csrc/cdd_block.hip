@@ -106,11 +106,9 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
     const double dfn = a.df / (double)N;
     const double B = a.dconst * dm * dfn * dfn / (fc * fc * fc);  // turns
     const double beta = dfn / fc;
-    // g = taper/N; the window depends on the bin only (x = sd/N)
-    auto rot = [&](float2 z, double q, double sd) {
+    auto rot = [&](float2 z, double q) {
       const float r = (float)(q - rint(q));
-      const float g = a.taper ? taper_gain<true>(a.taper, (float)sd * inv_n) * inv_n : inv_n;
-      const float c = __builtin_amdgcn_cosf(r) * g, s = __builtin_amdgcn_sinf(r) * g;
+      const float c = __builtin_amdgcn_cosf(r) * inv_n, s = __builtin_amdgcn_sinf(r) * inv_n;
       return make_float2(z.x * c + z.y * s, z.y * c - z.x * s);  // z (c - i s)
     };
     if (a.exact_div == 0) {
@@ -121,7 +119,7 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
         for (int r = 0; r < R; ++r) {
           const double sd = s0 + (double)(r * (N / R) - (2 * r >= R ? N : 0));
           const double x = beta * sd;
-          v[b * R + r] = rot(v[b * R + r], (B * (sd * sd)) * fma(x, x, 1.0 - x), sd);
+          v[b * R + r] = rot(v[b * R + r], (B * (sd * sd)) * fma(x, x, 1.0 - x));
         }
       }
     } else {
@@ -131,7 +129,7 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const double sd = s0 + (double)(r * (N / R) - (2 * r >= R ? N : 0));
-          v[b * R + r] = rot(v[b * R + r], (B * (sd * sd)) / fma(beta, sd, 1.0), sd);
+          v[b * R + r] = rot(v[b * R + r], (B * (sd * sd)) / fma(beta, sd, 1.0));
         }
       }
     }
@@ -150,9 +148,25 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
         const float q = Af * (f * f) / (fcf + f);
         float sn, cs;
         sincospif(2.0f * q, &sn, &cs);
-        const float g = inv_n * taper_gain<true>(a.taper, (float)s * inv_n);
-        v[b * R + r] = cmul(v[b * R + r], make_float2(cs * g, -sn * g));
+        v[b * R + r] = cmul(v[b * R + r], make_float2(cs * inv_n, -sn * inv_n));
       }
+    }
+  }
+}
+
+// Taper (Sec. 2.2) on the bins this thread holds after the forward transform
+// (same bin layout as apply_chirp).
+template <class S>
+__device__ __forceinline__ void apply_taper(float2* v, int kind, int t) {
+  constexpr int N = S::N, R = S::rad_f(S::NP - 1), BPT = N / (R * S::T);
+  constexpr float inv_n = 1.0f / (float)N;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int s = t + S::T * b + r * (N / R) - (2 * r >= R ? N : 0);
+      const float w = taper_gain<false>(kind, (float)s * inv_n);
+      v[b * R + r] = make_float2(v[b * R + r].x * w, v[b * R + r].y * w);
     }
   }
 }
@@ -299,6 +313,9 @@ __device__ __forceinline__ void process_item(const BlockArgs& a, int c, int64_t 
     fft_inverse<S>(v, lds, a.tw, tt);
     epilogue<S, true>(v, lds, a, c, k, 0, tt);
   } else {
+    // The taper depends on the bin only: it scales the shared spectrum once,
+    // and the per-trial chirp is a pure rotation.
+    if (a.taper) apply_taper<S>(v, a.taper, t);
     float2 X[S::E];
 #pragma unroll
     for (int e = 0; e < S::E; ++e) X[e] = v[e];
