@@ -89,6 +89,20 @@ typedef enum {
   CDD_TAPER_WELCH = 2  /* Welch: 1 - (2 x)^2                                 */
 } cdd_taper;
 
+/*
+ * cdd_incoherent -- incoherent dedispersion (Sec. 1.2): the same detection,
+ * integration and delay-aligned channel sum as cdd_dedisperse, without the
+ * coherent (chirp) step, so each channel keeps its intra-channel dispersion
+ * smear.  The baseline the coherent path improves on (Sec. 1.2, Fig. 1).
+ *   voltages, dtype, nsamp, nchan, f_centre_mhz, bw_mhz, dm, n_int,
+ *   intensity, coverage, chan_intensity: as cdd_dedisperse
+ *   workspace    device scratch of at least cdd_incoherent_ws_bytes(...)
+ *                bytes, 256-byte aligned
+ * Errors: EINVAL as cdd_dedisperse (no transform length is involved), short
+ * or misaligned workspace; EDEVICE if a launch fails.
+ */
+size_t cdd_incoherent_ws_bytes(int32_t dtype, int64_t nsamp, int32_t nchan, int32_t n_int);
+
 /* Options.  Zero-initialise; zero fields take the rule-based defaults. */
 typedef struct {
   int32_t explicit_plan;   /* 1: use fft_len/overlap/nfront as given        */
@@ -161,6 +175,12 @@ cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp,
                           double dm, int32_t fft_len, int32_t n_int,
                           float* intensity, int32_t* coverage,
                           float* chan_intensity, void* volt_out,
+                          const cdd_opts* opts, void* workspace,
+                          size_t ws_bytes, void* stream);
+cdd_status cdd_incoherent(const void* voltages, int32_t dtype, int64_t nsamp,
+                          int32_t nchan, double f_centre_mhz, double bw_mhz,
+                          double dm, int32_t n_int, float* intensity,
+                          int32_t* coverage, float* chan_intensity,
                           const cdd_opts* opts, void* workspace,
                           size_t ws_bytes, void* stream);
 

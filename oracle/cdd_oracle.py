@@ -307,6 +307,19 @@ def dedisperse(voltages, f_centre: float, bw: float, dm: float, n_int: int,
     return out
 
 
+def incoherent(voltages, f_centre: float, bw: float, dm: float, n_int: int,
+               dconst: float = D_PAPER):
+    """Incoherent dedispersion (Sec. 1.2): each channel detected and
+    integrated as recorded (its intra-channel dispersion left in place),
+    then the same delay-aligned sum.  Returns P, I, cov, d."""
+    x = as_complex(voltages)
+    P = detect_integrate(x.T, n_int)
+    nchan = x.shape[1]
+    d = channel_delays(f_centre, bw, nchan, dm, n_int, dconst)
+    I, cov = delay_sum(P, d)
+    return {"P": P, "I": I, "cov": cov, "d": d}
+
+
 def dft_direct(x: np.ndarray, sign: int = -1) -> np.ndarray:
     """O(N^2) discrete Fourier transform by explicit sums (small N only)."""
     x = np.asarray(x, dtype=np.complex128)

@@ -138,6 +138,11 @@ def _load():
     lib.cdd_abi_version.restype = ctypes.c_int32
     lib.cdd_kernel_variants.argtypes = [i32]
     lib.cdd_kernel_variants.restype = ctypes.c_int32
+    lib.cdd_incoherent_ws_bytes.argtypes = [i32, i64, i32, i32]
+    lib.cdd_incoherent_ws_bytes.restype = sz
+    lib.cdd_incoherent.argtypes = [vp, i32, i64, i32, f64, f64, f64, i32, vp, vp, vp,
+                                   ctypes.POINTER(Opts), vp, sz, vp]
+    lib.cdd_incoherent.restype = ctypes.c_int
     return lib
 
 
@@ -260,6 +265,38 @@ def dedisperse(voltages, f_centre, bw, dm, fft_len=0, n_int=1, *, want_chan=Fals
                               ptr("y") if want_voltages else None, ctypes.byref(o),
                               ptr("ws"), out["ws"].numel(), _stream_handle(stream)))
     out["info"] = info.as_dict()
+    return out
+
+
+def incoherent(voltages, f_centre, bw, dm, n_int=1, *, want_chan=False, dm_const=0.0,
+               stream=None, out=None):
+    """Run cdd_incoherent (detection, integration and the delay-aligned sum
+    without the coherent step) on a resident device tensor.  Returns a dict
+    with I, cov and, if want_chan, P."""
+    import torch
+    if not voltages.is_cuda or not voltages.is_contiguous():
+        raise ValueError("voltages must be a contiguous device tensor")
+    dt, nsamp, nchan = _layout(voltages)
+    o = make_opts(dm_const=dm_const)
+    ws = lib.cdd_incoherent_ws_bytes(dt, nsamp, nchan, int(n_int))
+    if ws == 0:
+        raise CddError(-1, "cdd_incoherent_ws_bytes: invalid shape")
+    dev = voltages.device
+    out = dict(out or {})
+    t_int = nsamp // int(n_int)
+    if "I" not in out:
+        out["I"] = torch.empty(t_int, dtype=torch.float32, device=dev)
+    if "cov" not in out:
+        out["cov"] = torch.empty(t_int, dtype=torch.int32, device=dev)
+    if want_chan and "P" not in out:
+        out["P"] = torch.empty((nchan, t_int), dtype=torch.float32, device=dev)
+    if "ws" not in out or out["ws"].numel() < ws:
+        out["ws"] = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+    ptr = lambda k: ctypes.c_void_p(out[k].data_ptr()) if k in out else None  # noqa: E731
+    _check(lib.cdd_incoherent(ctypes.c_void_p(voltages.data_ptr()), dt, nsamp, nchan,
+                              float(f_centre), float(bw), float(dm), int(n_int), ptr("I"),
+                              ptr("cov"), ptr("P") if want_chan else None, ctypes.byref(o),
+                              ptr("ws"), out["ws"].numel(), _stream_handle(stream)))
     return out
 
 

@@ -177,6 +177,102 @@ cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp, in
   }
 }
 
+// Incoherent dedispersion: the arguments of cdd_dedisperse that matter
+// without a transform (no length rule, so any DM is accepted).
+static cdd_status incoherent_plan(int32_t dtype, int64_t nsamp, int32_t nchan, double f_centre,
+                                  double bw, double dm, int32_t n_int, const cdd_opts* opts,
+                                  BeamPlan* p) {
+  if (dtype != CDD_CI8 && dtype != CDD_CF32)
+    return fail(CDD_EINVAL, "dtype %d is not CDD_CI8 or CDD_CF32", dtype);
+  if (nsamp < 1) return fail(CDD_EINVAL, "nsamp must be >= 1 (got %lld)", (long long)nsamp);
+  if (nchan < 1 || nchan > 65535)
+    return fail(CDD_EINVAL, "nchan must be in [1, 65535] (got %d)", nchan);
+  if (n_int < 1 || n_int > nsamp)
+    return fail(CDD_EINVAL, "n_int must be in [1, nsamp] (got %d)", n_int);
+  if (!std::isfinite(f_centre) || !std::isfinite(bw) || !std::isfinite(dm))
+    return fail(CDD_EINVAL, "frequencies and DM must be finite");
+  if (!(bw > 0)) return fail(CDD_EINVAL, "bw must be > 0 (got %g)", bw);
+  if (!(f_centre - bw / 2.0 > 0))
+    return fail(CDD_EINVAL, "band must lie above 0 MHz (f_centre - bw/2 = %g)",
+                f_centre - bw / 2.0);
+  p->dtype = dtype;
+  p->nsamp = nsamp;
+  p->nchan = nchan;
+  p->f_centre = f_centre;
+  p->bw = bw;
+  p->df = bw / nchan;
+  p->f_lo = f_centre - bw / 2.0;
+  p->n_int = n_int;
+  p->dms.assign(1, dm);
+  if (opts && opts->dm_const != 0) {
+    if (!std::isfinite(opts->dm_const) || opts->dm_const <= 0)
+      return fail(CDD_EINVAL, "dm_const must be finite and > 0");
+    p->dconst = opts->dm_const;
+  }
+  p->t_int = nsamp / n_int;
+  p->N = 0;  // no transform
+  return CDD_OK;
+}
+
+extern "C" size_t cdd_incoherent_ws_bytes(int32_t dtype, int64_t nsamp, int32_t nchan,
+                                          int32_t n_int) {
+  BeamPlan p;
+  if (incoherent_plan(dtype, nsamp, nchan, 325.0, 1.0, 0.0, n_int, nullptr, &p) != CDD_OK)
+    return 0;
+  clear_error();
+  return ws_layout(p, 1, true).total;
+}
+
+extern "C" cdd_status cdd_incoherent(const void* voltages, int32_t dtype, int64_t nsamp,
+                                     int32_t nchan, double f_centre_mhz, double bw_mhz,
+                                     double dm, int32_t n_int, float* intensity,
+                                     int32_t* coverage, float* chan_intensity,
+                                     const cdd_opts* opts, void* workspace, size_t ws_bytes,
+                                     void* stream) {
+  try {
+    if (!voltages) return fail(CDD_EINVAL, "voltages is NULL");
+    if (!intensity) return fail(CDD_EINVAL, "intensity is NULL");
+    BeamPlan p;
+    cdd_status s = incoherent_plan(dtype, nsamp, nchan, f_centre_mhz, bw_mhz, dm, n_int, opts, &p);
+    if (s != CDD_OK) return s;
+    const WsLayout lay = ws_layout(p, 1, true);
+    if (!workspace || ws_bytes < lay.total)
+      return fail(CDD_EINVAL, "workspace too small: need %zu bytes, got %zu", lay.total,
+                  workspace ? ws_bytes : (size_t)0);
+    if (!aligned256(workspace)) return fail(CDD_EINVAL, "workspace must be 256-byte aligned");
+    char* ws = (char*)workspace;
+    const void* xt = voltages;
+    int e = 0;
+    if (p.nchan > 1) {
+      if ((e = launch_transposed(p, voltages, ws + lay.xt_off, stream)))
+        return device_fail("transpose launch", e);
+      xt = ws + lay.xt_off;
+    }
+    float* P = chan_intensity ? chan_intensity : (float*)(ws + lay.p_off);
+    int32_t* d = (int32_t*)(ws + lay.d_off);
+    DmTile tile;
+    tile.ndm = 1;
+    tile.dm[0] = dm;
+    void* tok = nullptr;
+    if ((e = stage_begin(stream, &tok)) || (e = launch_delays(p, tile, d, stream)) ||
+        (e = stage_end(kStageDelays, stream, tok)))
+      return device_fail("delay launch", e);
+    if ((e = stage_begin(stream, &tok)) || (e = launch_detect(p, xt, P, stream)) ||
+        (e = stage_end(kStageBlock, stream, tok)))
+      return device_fail("detect launch", e);
+    if ((e = stage_begin(stream, &tok)) ||
+        (e = launch_dsum(p, 1, P, d, intensity, coverage, p.t_int, stream)) ||
+        (e = stage_end(kStageDsum, stream, tok)))
+      return device_fail("aligned-sum launch", e);
+    clear_error();
+    return CDD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(CDD_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(CDD_EINTERNAL, "unexpected exception");
+  }
+}
+
 cdd_status cdd_plan_create(const cdd_beam* beams, int32_t nbeam, const cdd_opts* opts,
                            cdd_plan** out) {
   try {

@@ -150,6 +150,50 @@ int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream
 }
 
 // ---------------------------------------------------------------------------
+// Detection and integration without the coherent step (incoherent
+// dedispersion): P[c][u] = sum over r < n_int of |x_c[u n_int + r]|^2, in
+// order; consecutive threads take consecutive u of one channel.
+// ---------------------------------------------------------------------------
+template <int DT>
+__global__ __launch_bounds__(256) void detect_kernel(const void* __restrict__ xt,
+                                                     float* __restrict__ P, int64_t nsamp,
+                                                     int64_t t_int, int32_t n_int) {
+  const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (u >= t_int) return;
+  float s = 0.f;
+  const int64_t base = (int64_t)c * nsamp + u * n_int;
+  for (int r = 0; r < n_int; ++r) {
+    float re, im;
+    if constexpr (DT == CDD_CI8) {
+      const unsigned short w = ((const unsigned short*)xt)[base + r];
+      re = (float)(signed char)(w & 0xff);
+      im = (float)(signed char)(w >> 8);
+    } else {
+      const float2 z = ((const float2*)xt)[base + r];
+      re = z.x;
+      im = z.y;
+    }
+    s += re * re + im * im;
+  }
+  P[(int64_t)c * t_int + u] = s;
+}
+
+int launch_detect(const BeamPlan& p, const void* xt, float* P, void* stream) {
+  const int64_t nb = (p.t_int + 255) / 256;
+  if (nb <= 0) return 0;
+  if (nb > 0x7fffffffLL || p.nchan > 65535) return (int)hipErrorInvalidValue;
+  dim3 grid((unsigned)nb, (unsigned)p.nchan);
+  if (p.dtype == CDD_CI8)
+    hipLaunchKernelGGL(detect_kernel<CDD_CI8>, grid, dim3(256), 0, (hipStream_t)stream, xt, P,
+                       p.nsamp, p.t_int, p.n_int);
+  else
+    hipLaunchKernelGGL(detect_kernel<CDD_CF32>, grid, dim3(256), 0, (hipStream_t)stream, xt, P,
+                       p.nsamp, p.t_int, p.n_int);
+  return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // I[u] = sum over channels c with u + d_c < T_int of P_c[u + d_c], cov[u] =
 // number of terms.  A workgroup covers 64 consecutive u; its G waves each sum
 // a contiguous channel range in ascending order, and the G partial sums are

@@ -111,6 +111,8 @@ size_t batch_table_bytes(int nbeams);
 int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_tab,
                  unsigned int* counter, void* stream);
 int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream);
+// P[c][u] = sum of |x[c][u n_int + r]|^2, r < n_int (channel-major x).
+int launch_detect(const BeamPlan& p, const void* xt, float* P, void* stream);
 int launch_dsum(const BeamPlan& p, int ndm, const float* P, const int32_t* d,
                 float* I, int32_t* cov, int64_t out_stride, void* stream);
 // General form: for u in [u_begin, u_begin + u_count),

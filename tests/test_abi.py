@@ -95,6 +95,23 @@ def test_invalid_arguments_are_rejected(args, frag):
     assert ei.value.status == -1 and frag in str(ei.value), str(ei.value)
 
 
+def test_incoherent_validation_without_device():
+    cdd = _lib()
+    assert cdd.lib.cdd_incoherent_ws_bytes(0, 10_000, 64, 4) >= 64 * 10_000 * 2
+    assert cdd.lib.cdd_incoherent_ws_bytes(0, 10_000, 64, 0) == 0
+    assert cdd.lib.cdd_incoherent_ws_bytes(5, 10_000, 64, 4) == 0
+    o = cdd._binding.make_opts()
+    ws = cdd.lib.cdd_incoherent_ws_bytes(0, 10_000, 64, 4)
+    st = cdd.lib.cdd_incoherent(ctypes.c_void_p(0x1000), 0, 10_000, 64, 325.0, 4.0, 3000.0, 4,
+                                ctypes.c_void_p(0x2000), None, None, ctypes.byref(o), None, 0,
+                                None)
+    assert st == -1 and b"workspace" in cdd.lib.cdd_last_error()
+    st = cdd.lib.cdd_incoherent(ctypes.c_void_p(0x1000), 0, 10_000, 64, 10.0, 32.0, 30.0, 4,
+                                ctypes.c_void_p(0x2000), None, None, ctypes.byref(o),
+                                ctypes.c_void_p(0x3000), ws, None)
+    assert st == -1 and b"above 0" in cdd.lib.cdd_last_error()
+
+
 def test_explicit_plan_validation():
     cdd = _lib()
     ok = cdd.query(0, 10_000, 64, 325.0, 4.0, 30.0, 1024, 4, overlap=128, nfront=64)

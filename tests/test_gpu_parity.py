@@ -177,6 +177,27 @@ def test_taper_long_transform_against_oracle():
     _check(got, o)
 
 
+def test_incoherent_against_oracle():
+    """Incoherent dedispersion (no coherent step): per-channel intensities
+    exactly (int8 squares sum exactly in FP32), the aligned sum and coverage."""
+    import torch
+    cdd = _cdd()
+    v = _beam_int8(150, 21_001, 40, 325.0, 40 * 0.0625, 67.9)
+    g = cdd.incoherent(to_dev(v), 325.0, 40 * 0.0625, 67.9, 4, want_chan=True)
+    torch.cuda.synchronize()
+    o = O.incoherent(v, 325.0, 40 * 0.0625, 67.9, 4)
+    assert np.array_equal(g["P"].cpu().numpy().astype(np.float64), o["P"])
+    assert rel_l2(g["I"].cpu().numpy(), o["I"]) <= 1e-6
+    assert np.array_equal(g["cov"].cpu().numpy(), o["cov"])
+    # complex-float, one channel: the input is read in place
+    rng = np.random.default_rng(151)
+    x = (rng.standard_normal(5003) + 1j * rng.standard_normal(5003)).astype(np.complex64)
+    g = cdd.incoherent(to_dev(x), 610.0, 16.0, 10.0, 7)
+    torch.cuda.synchronize()
+    o = O.incoherent(x, 610.0, 16.0, 10.0, 7)
+    assert rel_l2(g["I"].cpu().numpy(), o["I"]) <= 1e-6
+
+
 def test_config2_full_size():
     """512 channels x 4 s at 32 MHz, N = 8192, n_int = 4, DM 67.9, in the
     launch shape the benchmark times: per-channel intensities of 64 sampled
