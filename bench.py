@@ -317,6 +317,19 @@ def main():
                      "alg_hbm_frac": round(alg_bytes / (blk_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
         "gflops_paper_eq5": round(flops / (blk_avg * 1e-3) / 1e9, 1),
     }
+    # the incoherent baseline (no coherent step) on the same resident beam
+    oi = cdd.incoherent(vd, b.f_centre, b.bw, b.dm, b.n_int)
+    for _ in range(args.warmup):
+        cdd.incoherent(vd, b.f_centre, b.bw, b.dm, b.n_int, out=oi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cdd.incoherent(vd, b.f_centre, b.bw, b.dm, b.n_int, out=oi)
+    torch.cuda.synchronize()
+    mi = (time.perf_counter() - t0) / args.steps * 1e3
+    res["incoherent_baseline"] = {"ms_per_step": round(mi, 4),
+                                  "msamples_per_s": round(samples / (mi * 1e-3) / 1e6, 1),
+                                  "coherent_cost_ratio": round(ms / mi, 2)}
     if args.config == 2 and not args.no_dm_trials:
         res["dm_trials"] = dm_trials(cdd, torch, vd, b, info, taper=args.taper)
     if not args.no_cpu_baseline:
