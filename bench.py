@@ -36,6 +36,7 @@ K_DM_US = 4.148808e9       # cold-plasma constant, only to synthesise the pulses
 WORKLOADS = {
     2: "filterbank_32MHz_512ch_4s_int8_N8192_nint4_dm67.9",
     3: "filterbank_200MHz_4096ch_2s_int8_N8192_nint4_dm120",
+    4: "multibeam_16-32-32-200MHz_512-512-1024-4096ch_1-4s_int8_nint4_autotuned",
     5: "serving_8streams_16-32-200MHz_int8_dm5-300",
 }
 
@@ -99,6 +100,52 @@ def cpu_baseline(v, b, seconds: float):
             "kind": "oracle",
             "sample": "%d of %d channels, full %d-sample duration, FP64 numpy, %.1f s"
                       % (len(chans), b.nchan, b.nsamp, dt)}
+
+
+def multibeam(cdd, torch, reps: int = 3):
+    """Four beams of uneven bandwidth and length (16/32/32/200 MHz, 512/512/
+    1024/4096 channels, 1-4 s, DM 10/67.9/67.9/120), seeded int8 noise: one
+    plan (autotuned transform length per beam, one persistent launch per
+    length) against a loop of one-shot calls at the same plans."""
+    import synth
+    beams = synth.extra_beams()
+    vs = [torch.from_numpy(synth.noise_int8(synth.rng_for(4, salt=i + 1), b.nsamp, b.nchan,
+                                            b.sigma)).cuda() for i, b in enumerate(beams)]
+    t0 = time.perf_counter()
+    plan = cdd.Plan([dict(voltages=v, f_centre=b.f_centre, bw=b.bw, dms=[b.dm], n_int=b.n_int)
+                     for v, b in zip(vs, beams)], autotune=True)
+    t_tune = time.perf_counter() - t0
+    infos = [plan.info(i) for i in range(len(beams))]
+    plan.execute()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.execute()
+    torch.cuda.synchronize()
+    t_plan = (time.perf_counter() - t0) / reps
+    outs = [cdd.dedisperse(v, b.f_centre, b.bw, b.dm, q["fft_len"], b.n_int,
+                           overlap=q["overlap"], nfront=q["nfront"])
+            for v, b, q in zip(vs, beams, infos)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for v, b, q, o in zip(vs, beams, infos, outs):
+            cdd.dedisperse(v, b.f_centre, b.bw, b.dm, q["fft_len"], b.n_int,
+                           overlap=q["overlap"], nfront=q["nfront"], out=o)
+    torch.cuda.synchronize()
+    t_loop = (time.perf_counter() - t0) / reps
+    diff = max(float(torch.linalg.norm(plan.I[i][0] - outs[i]["I"]) /
+                     torch.linalg.norm(outs[i]["I"])) for i in range(len(beams)))
+    plan.close()
+    samples = sum(b.nchan * b.nsamp for b in beams)
+    duration = max(b.nsamp / (b.bw / b.nchan * 1e6) for b in beams)
+    return {"beams": [{"bw_mhz": b.bw, "nchan": b.nchan, "nsamp": b.nsamp, "dm": b.dm,
+                       "fft_len": q["fft_len"]} for b, q in zip(beams, infos)],
+            "plan_ms": round(t_plan * 1e3, 3), "loop_ms": round(t_loop * 1e3, 3),
+            "plan_msamples_per_s": round(samples / t_plan / 1e6, 1),
+            "loop_msamples_per_s": round(samples / t_loop / 1e6, 1),
+            "speedup": round(t_loop / t_plan, 3), "x_realtime": round(duration / t_plan, 1),
+            "autotune_s": round(t_tune, 2), "rel_l2_plan_vs_loop": diff}
 
 
 def dm_trials(cdd, torch, vd, b, info, reps: int = 3, taper: str = "none"):
@@ -240,6 +287,16 @@ def main():
         return
     import paper_1509_00186_amd as cdd
 
+    if args.config == 4:
+        mb = multibeam(cdd, torch)
+        res = {"metric": "Msamples/s dedispersed (four uneven beams, one plan)",
+               "value": mb["plan_msamples_per_s"], "unit": "Msamples/s", "n_gpus": 1,
+               "steps": 3, "warmup": 1, "ms_per_step": mb["plan_ms"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+               "data": "synthetic (seeded int8 noise)", "config": {"workload": WORKLOADS[4]},
+               "multibeam": mb}
+        print(json.dumps(res), flush=True)
+        return
     if args.config == 5:
         paced = serving(cdd, args.seconds, paced=True)
         burst = serving(cdd, max(2.0, args.seconds / 5), paced=False)

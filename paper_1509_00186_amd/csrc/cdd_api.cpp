@@ -93,6 +93,8 @@ constexpr size_t kPlanPBudget = (size_t)8 << 30;  // per-channel intensities hel
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+bool one_dm(const BeamPlan& p) { return block_supported(p.N) && p.dms.size() == 1; }
+
 // DM tiles and workspace layout of a plan: each beam gets its own channel-major
 // copy, intensity and delay regions; then one launch table per round and the
 // work counter.
@@ -114,7 +116,8 @@ void layout_plan(cdd_plan* pl) {
                                 std::max<size_t>(1, budget / std::max<size_t>(per_dm, 1)));
     }
     pl->tile[b] = t;
-    pl->lay[b] = ws_layout(p, t, true);
+    // a one-DM beam takes the chirp from a table, like the one-shot call
+    pl->lay[b] = ws_layout(p, t, true, one_dm(p));
     pl->ws_base[b] = off;
     off = align256(off + pl->lay[b].total);
     pl->rounds = std::max(pl->rounds, (ndm + t - 1) / t);
@@ -379,16 +382,27 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
         tiles[b].ndm = std::max(0, std::min(plan->tile[b], (int)p.dms.size() - i0));
         for (int i = 0; i < tiles[b].ndm; ++i) tiles[b].dm[i] = p.dms[i0 + i];
       }
-      // one persistent launch per transform length among the block-kernel beams
+      // per transform length: one launch over the one-DM beams (chirp tables)
+      // and one persistent launch over the beams with DM tiles
       std::vector<bool> done(nb, false);
       void* tab_dev = ws + plan->tab_off + batch_table_bytes((int)nb) * (size_t)r;
       size_t tab_used = 0;
       for (size_t b0 = 0; b0 < nb; ++b0) {
         if (done[b0] || tiles[b0].ndm == 0 || !block_supported(plan->beams[b0].N)) continue;
+        const bool single = one_dm(plan->beams[b0]);
         group.clear();
+        std::vector<const void*> H;
         for (size_t b = b0; b < nb; ++b) {
-          if (done[b] || tiles[b].ndm == 0 || plan->beams[b].N != plan->beams[b0].N) continue;
+          if (done[b] || tiles[b].ndm == 0 || plan->beams[b].N != plan->beams[b0].N ||
+              one_dm(plan->beams[b]) != single)
+            continue;
           done[b] = true;
+          if (single) {
+            char* h = ws + plan->ws_base[b] + plan->lay[b].h_off;
+            if ((e = launch_chirp_table(plan->beams[b], tiles[b].dm[0], h, stream)))
+              return device_fail("chirp table launch", e);
+            H.push_back(h);
+          }
           BatchBeam bb;
           bb.p = &plan->beams[b];
           bb.xt = xt[b];
@@ -397,17 +411,25 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
           bb.co = offline_coords(plan->beams[b]);
           group.push_back(bb);
         }
-        // longest work first
-        std::stable_sort(group.begin(), group.end(), [](const BatchBeam& x, const BatchBeam& y) {
-          return x.dms.ndm > y.dms.ndm;
-        });
         host_tabs.emplace_back(batch_table_bytes((int)group.size()), 0);
         void* tok = nullptr;
         if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
-        if ((e = launch_batch(group.data(), (int)group.size(), host_tabs.back().data(),
-                              (char*)tab_dev + tab_used,
-                              (unsigned int*)(ws + plan->cnt_off), stream)))
-          return device_fail("batched launch", e);
+        if (single) {
+          if ((e = launch_multi_single(group.data(), H.data(), (int)group.size(),
+                                       host_tabs.back().data(), (char*)tab_dev + tab_used,
+                                       stream)))
+            return device_fail("multi-beam launch", e);
+        } else {
+          // longest work first
+          std::stable_sort(group.begin(), group.end(),
+                           [](const BatchBeam& x, const BatchBeam& y) {
+                             return x.dms.ndm > y.dms.ndm;
+                           });
+          if ((e = launch_batch(group.data(), (int)group.size(), host_tabs.back().data(),
+                                (char*)tab_dev + tab_used,
+                                (unsigned int*)(ws + plan->cnt_off), stream)))
+            return device_fail("batched launch", e);
+        }
         if ((e = stage_end(kStageBlock, stream, tok))) return device_fail("event record", e);
         tab_used += batch_table_bytes((int)group.size());
       }

@@ -386,6 +386,27 @@ __global__ __launch_bounds__(S::T, (S::MINB + 1) / 2) void batch_kernel(
   }
 }
 
+// Several one-DM beams of one transform length in one launch: one workgroup
+// per (beam, channel, block) over the concatenated items (beams listed with
+// their first item), XCD-aware as block_kernel; each beam's chirp comes from
+// its own table.
+template <class S>
+__global__ __launch_bounds__(S::T, S::MINB) void multi_single_kernel(
+    const BlockArgs* __restrict__ beams, int32_t nbeams, int64_t total) {
+  __shared__ __align__(16) float lds[S::lds_floats()];
+  const int64_t item = xcd_item(blockIdx.x, total);
+  int b = 0;
+  while (b + 1 < nbeams && item >= beams[b + 1].item0) ++b;
+  const BlockArgs& a = beams[b];
+  const int64_t local = item - a.item0;
+  const int c = (int)(local / a.nblocks);
+  const int64_t k = local - (int64_t)c * a.nblocks;
+  if (a.dtype == CDD_CI8)
+    process_item<S, CDD_CI8, false>(a, c, k, lds, threadIdx.x);
+  else
+    process_item<S, CDD_CF32, false>(a, c, k, lds, threadIdx.x);
+}
+
 __global__ void zero_counter_kernel(unsigned int* c) { *c = 0u; }
 
 // Chirp table of one DM: H[c*N + i] = exp(-2 pi i q)/N for bin i of channel c
@@ -579,6 +600,24 @@ static int launch_batch_t(BlockArgs* host_tab, int nbeams, int64_t total, BlockA
   return (int)hipGetLastError();
 }
 
+template <int N>
+static int launch_multi_single_t(BlockArgs* host_tab, int nbeams, int64_t total,
+                                 BlockArgs* dev_tab, void* stream) {
+  using S = typename SchedFor<N, 0>::type;
+  const float2* tw = nullptr;
+  int err = twiddles_of<S>(&tw);
+  if (err) return err;
+  for (int b = 0; b < nbeams; ++b) host_tab[b].tw = tw;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(dev_tab, host_tab, sizeof(BlockArgs) * nbeams,
+                                hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return (int)e;
+  if (total <= 0) return 0;
+  hipLaunchKernelGGL(multi_single_kernel<S>, dim3((unsigned)total), dim3(S::T), 0, st, dev_tab,
+                     nbeams, total);
+  return (int)hipGetLastError();
+}
+
 static int log2i(int n) {
   int l = 0;
   while ((1 << l) < n) ++l;
@@ -639,6 +678,34 @@ int launch_block_co(const BeamPlan& p, const Coords& co, const void* xt, const D
 }
 
 size_t batch_table_bytes(int nbeams) { return sizeof(BlockArgs) * (size_t)nbeams; }
+
+int launch_multi_single(const BatchBeam* beams, const void* const* H, int nbeams,
+                        void* host_tab, void* dev_tab, void* stream) {
+  if (nbeams < 1) return 0;
+  const int N = beams[0].p->N;
+  BlockArgs* ht = (BlockArgs*)host_tab;
+  int64_t total = 0;
+  for (int b = 0; b < nbeams; ++b) {
+    const BeamPlan& p = *beams[b].p;
+    if (p.N != N || beams[b].dms.ndm != 1 || H[b] == nullptr) return (int)hipErrorInvalidValue;
+    ht[b] = make_args(p, beams[b].co, beams[b].xt, beams[b].dms, beams[b].P, nullptr,
+                      (const float2*)H[b]);
+    ht[b].item0 = total;
+    total += (int64_t)p.nchan * beams[b].co.nblocks;
+  }
+  if (total > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+  BlockArgs* dt = (BlockArgs*)dev_tab;
+  switch (N) {
+    case 256: return launch_multi_single_t<256>(ht, nbeams, total, dt, stream);
+    case 512: return launch_multi_single_t<512>(ht, nbeams, total, dt, stream);
+    case 1024: return launch_multi_single_t<1024>(ht, nbeams, total, dt, stream);
+    case 2048: return launch_multi_single_t<2048>(ht, nbeams, total, dt, stream);
+    case 4096: return launch_multi_single_t<4096>(ht, nbeams, total, dt, stream);
+    case 8192: return launch_multi_single_t<8192>(ht, nbeams, total, dt, stream);
+    case 16384: return launch_multi_single_t<16384>(ht, nbeams, total, dt, stream);
+  }
+  return (int)hipErrorInvalidValue;
+}
 
 size_t chirp_table_bytes(const BeamPlan& p) {
   return block_supported(p.N) ? (size_t)p.nchan * p.N * sizeof(float2) : 0;

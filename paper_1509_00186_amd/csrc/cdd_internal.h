@@ -108,6 +108,11 @@ struct BatchBeam {
   Coords co;
 };
 size_t batch_table_bytes(int nbeams);
+// One-DM beams sharing a transform length: one launch over all their
+// (channel, block) items, beam b's chirp from its table H[b]; tables as for
+// launch_batch (host_tab pinned or kept alive until the copy completes).
+int launch_multi_single(const BatchBeam* beams, const void* const* H, int nbeams,
+                        void* host_tab, void* dev_tab, void* stream);
 int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_tab,
                  unsigned int* counter, void* stream);
 int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream);

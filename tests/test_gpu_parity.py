@@ -438,6 +438,34 @@ def test_persistent_launch_mixed_sample_types():
     plan.close()
 
 
+def test_plan_of_one_dm_beams_uses_tables_and_matches_oracle():
+    """One-DM beams of one transform length (int8 and complex float, uneven
+    channel counts) in one launch over their chirp tables; a one-DM beam of
+    another length and a multi-DM beam in the same plan."""
+    import torch
+    cdd = _cdd()
+    v0 = _beam_int8(160, 9_000, 24, 325.0, 1.5, 67.9)
+    v1 = _beam_int8(161, 7_000, 8, 610.0, 0.25, 10.0)
+    x1 = (v1[..., 0].astype(np.float32) + 1j * v1[..., 1]).astype(np.complex64)
+    v2 = _beam_int8(162, 6_000, 16, 400.0, 0.78125, 30.0)
+    v3 = _beam_int8(163, 8_000, 12, 325.0, 0.75, 40.0)
+    raw = [(v0, 325.0, 1.5, [67.9], 2048), (x1, 610.0, 0.25, [10.0], 2048),
+           (v2, 400.0, 0.78125, [30.0], 1024), (v3, 325.0, 0.75, [40.0, 41.0], 2048)]
+    plan = cdd.Plan([dict(voltages=to_dev(v), f_centre=f, bw=bw, dms=dms, n_int=4, fft_len=N)
+                     for (v, f, bw, dms, N) in raw])
+    for rep in range(2):
+        plan.execute()
+        torch.cuda.synchronize()
+        for bi, (v, fcen, bw, dms, N) in enumerate(raw):
+            info = plan.info(bi)
+            for i, dm in enumerate(dms):
+                o = O.dedisperse(v, fcen, bw, dm, 4, fft_len=N, overlap=info["overlap"],
+                                 nfront=info["nfront"])
+                assert rel_l2(plan.I[bi][i].cpu().numpy(), o["I"]) <= TOL_I, (bi, i)
+                assert np.array_equal(plan.cov[bi][i].cpu().numpy(), o["cov"])
+    plan.close()
+
+
 def test_dm_tiles_beyond_one_launch():
     """More DM trials than one launch holds (70 > 64): two rounds."""
     import torch
