@@ -121,7 +121,14 @@ typedef struct {
                               1 = no split                                 */
   int32_t taper;           /* cdd_taper; the plan (N, L, nfront) is the same
                               with or without a taper                      */
-  int32_t reserved[3];
+  int32_t npol;            /* cdd_dedisperse: polarisations in the record
+                              (0 or 1 = one; 2 = two records of the same
+                              shape back to back, [2][nsamp][nchan]...):
+                              their detected intensities are summed before
+                              the delay-aligned sum (Sec. 4.1, one
+                              polarisation per host, summed); N <= 16384,
+                              nchan > 1, one time chunk, no voltages out   */
+  int32_t reserved[2];
 } cdd_opts;
 
 /* Plan figures for one beam (filled by cdd_query / cdd_plan_info). */
@@ -183,6 +190,22 @@ cdd_status cdd_incoherent(const void* voltages, int32_t dtype, int64_t nsamp,
                           int32_t* coverage, float* chan_intensity,
                           const cdd_opts* opts, void* workspace,
                           size_t ws_bytes, void* stream);
+
+/*
+ * cdd_fold -- fold an intensity series at a known period into phase bins
+ * (the folded profiles the paper compares in Sec. 5).  Sample u goes to bin
+ * floor(frac(u / period + phase0) * nbins) (clamped to nbins - 1),
+ * frac(x) = x - floor(x), all in FP64; profile[b] is the sum of its samples
+ * in ascending u (accumulated in FP64, stored as FP32) and counts[b] their
+ * number.
+ *   intensity  device float [t_int] (e.g. the output of cdd_dedisperse)
+ *   period     in samples of the series, > 1; phase0 in turns, finite
+ *   profile    device float [nbins]; counts device int32 [nbins] or NULL
+ * Errors: EINVAL for NULL intensity or profile, t_int < 1, nbins < 1,
+ * period <= 1 or non-finite period/phase0; EDEVICE if the launch fails.
+ */
+cdd_status cdd_fold(const float* intensity, int64_t t_int, double period, double phase0,
+                    int32_t nbins, float* profile, int32_t* counts, void* stream);
 
 /* ---------------------------------------------------------------------
  * Batched form: many DM trials on several beams in one launch.  The

@@ -320,6 +320,21 @@ def incoherent(voltages, f_centre: float, bw: float, dm: float, n_int: int,
     return {"P": P, "I": I, "cov": cov, "d": d}
 
 
+def fold(I: np.ndarray, period: float, phase0: float, nbins: int):
+    """Fold a series at a known period (the folded profiles compared in
+    Sec. 5): sample u goes to bin floor(frac(u / period + phase0) * nbins),
+    frac(x) = x - floor(x), clamped to nbins - 1.  Returns the per-bin sums
+    (float64, ascending u) and counts."""
+    prof = np.zeros(nbins)
+    cnt = np.zeros(nbins, dtype=np.int64)
+    for u in range(len(I)):
+        x = u / period + phase0
+        b = min(int(math.floor((x - math.floor(x)) * nbins)), nbins - 1)
+        prof[b] += I[u]
+        cnt[b] += 1
+    return prof, cnt
+
+
 def dft_direct(x: np.ndarray, sign: int = -1) -> np.ndarray:
     """O(N^2) discrete Fourier transform by explicit sums (small N only)."""
     x = np.asarray(x, dtype=np.complex128)

@@ -31,7 +31,7 @@ class Opts(ctypes.Structure):
                 ("dm_const", ctypes.c_double), ("phase_mode", ctypes.c_int32),
                 ("kernel_variant", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("time_chunks", ctypes.c_int32), ("taper", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("npol", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -143,6 +143,8 @@ def _load():
     lib.cdd_incoherent.argtypes = [vp, i32, i64, i32, f64, f64, f64, i32, vp, vp, vp,
                                    ctypes.POINTER(Opts), vp, sz, vp]
     lib.cdd_incoherent.restype = ctypes.c_int
+    lib.cdd_fold.argtypes = [vp, i64, f64, f64, i32, vp, vp, vp]
+    lib.cdd_fold.restype = ctypes.c_int
     return lib
 
 
@@ -229,8 +231,11 @@ def _stream_handle(stream):
 
 def dedisperse(voltages, f_centre, bw, dm, fft_len=0, n_int=1, *, want_chan=False,
                want_voltages=False, overlap=None, nfront=None, dm_const=0.0, phase_mode=0,
-               variant=0, time_chunks=0, taper="none", stream=None, out=None):
+               variant=0, time_chunks=0, taper="none", npol=1, stream=None, out=None):
     """Run cdd_dedisperse on a resident device tensor.
+
+    With npol=2 the tensor holds two polarisation records, [2][nsamp][...],
+    whose detected intensities are summed.
 
     Returns a dict: I [t_int] float32, cov [t_int] int32, P [nchan][t_int]
     (if want_chan), y [nchan][nsamp] complex64 (if want_voltages), info.
@@ -239,9 +244,15 @@ def dedisperse(voltages, f_centre, bw, dm, fft_len=0, n_int=1, *, want_chan=Fals
     import torch
     if not voltages.is_cuda or not voltages.is_contiguous():
         raise ValueError("voltages must be a contiguous device tensor")
-    dt, nsamp, nchan = _layout(voltages)
+    if npol == 2:
+        if voltages.shape[0] != 2:
+            raise ValueError("npol=2 needs voltages shaped [2][nsamp][...]")
+        dt, nsamp, nchan = _layout(voltages[0])
+    else:
+        dt, nsamp, nchan = _layout(voltages)
     o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode, variant,
                   time_chunks=time_chunks, taper=taper)
+    o.npol = int(npol)
     info = PlanInfo()
     _check(lib.cdd_query(dt, nsamp, nchan, float(f_centre), float(bw), float(dm), int(fft_len),
                          int(n_int), int(want_voltages), ctypes.byref(o), ctypes.byref(info)))
@@ -298,6 +309,21 @@ def incoherent(voltages, f_centre, bw, dm, n_int=1, *, want_chan=False, dm_const
                               ptr("cov"), ptr("P") if want_chan else None, ctypes.byref(o),
                               ptr("ws"), out["ws"].numel(), _stream_handle(stream)))
     return out
+
+
+def fold(intensity, period, phase0=0.0, nbins=128, stream=None):
+    """cdd_fold of a device float series: (profile [nbins] float32, counts
+    [nbins] int32) device tensors."""
+    import torch
+    if not intensity.is_cuda or intensity.dtype != torch.float32 or intensity.dim() != 1:
+        raise ValueError("intensity must be a 1-D float32 device tensor")
+    x = intensity.contiguous()
+    prof = torch.empty(int(nbins), dtype=torch.float32, device=x.device)
+    cnt = torch.empty(int(nbins), dtype=torch.int32, device=x.device)
+    _check(lib.cdd_fold(ctypes.c_void_p(x.data_ptr()), x.numel(), float(period), float(phase0),
+                        int(nbins), ctypes.c_void_p(prof.data_ptr()),
+                        ctypes.c_void_p(cnt.data_ptr()), _stream_handle(stream)))
+    return prof, cnt
 
 
 class Plan:

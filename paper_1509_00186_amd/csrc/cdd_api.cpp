@@ -156,12 +156,19 @@ cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp, in
     int chunks = 1;
     if (opts && opts->time_chunks > 0)
       chunks = (int)std::min<int64_t>({(int64_t)opts->time_chunks, p.nblocks, kMaxChunks});
+    const int npol = (opts && opts->npol > 1) ? opts->npol : 1;
+    if (opts && (opts->npol < 0 || opts->npol > 2))
+      return fail(CDD_EINVAL, "npol must be 0, 1 or 2 (got %d)", opts->npol);
+    if (npol == 2 && !(block_supported(p.N) && p.nchan > 1 && chunks == 1 && !volt_out))
+      return fail(CDD_ENOTSUP,
+                  "two polarisations need fft_len <= 16384, nchan > 1, one time chunk and no "
+                  "voltage output");
     if (block_supported(p.N) && p.nchan > 1) {
       char* ws = (char*)workspace;
       int e = run_pipelined(p, voltages, dm, ws + lay.xt_off,
                             chan_intensity ? chan_intensity : (float*)(ws + lay.p_off),
                             (int32_t*)(ws + lay.d_off), ws + lay.h_off, volt_out, intensity,
-                            coverage, chunks, stream);
+                            coverage, chunks, npol, stream);
       if (e) return device_fail("pipelined launch", e);
       clear_error();
       return CDD_OK;
@@ -274,6 +281,20 @@ extern "C" cdd_status cdd_incoherent(const void* voltages, int32_t dtype, int64_
   } catch (...) {
     return fail(CDD_EINTERNAL, "unexpected exception");
   }
+}
+
+extern "C" cdd_status cdd_fold(const float* intensity, int64_t t_int, double period,
+                               double phase0, int32_t nbins, float* profile, int32_t* counts,
+                               void* stream) {
+  if (!intensity || !profile) return fail(CDD_EINVAL, "intensity or profile is NULL");
+  if (t_int < 1) return fail(CDD_EINVAL, "t_int must be >= 1");
+  if (nbins < 1) return fail(CDD_EINVAL, "nbins must be >= 1");
+  if (!std::isfinite(period) || !std::isfinite(phase0) || !(period > 1.0))
+    return fail(CDD_EINVAL, "period must be finite and > 1 sample, phase0 finite");
+  const int e = launch_fold(intensity, t_int, period, phase0, nbins, profile, counts, stream);
+  if (e) return device_fail("fold launch", e);
+  clear_error();
+  return CDD_OK;
 }
 
 cdd_status cdd_plan_create(const cdd_beam* beams, int32_t nbeam, const cdd_opts* opts,

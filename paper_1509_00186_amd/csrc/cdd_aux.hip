@@ -194,6 +194,59 @@ int launch_detect(const BeamPlan& p, const void* xt, float* P, void* stream) {
 }
 
 // ---------------------------------------------------------------------------
+// Folding at a known period: one thread per phase bin b.  Sample u belongs to
+// bin floor(frac(u/period + phase0) * nbins) (FP64, contraction off, clamped
+// to nbins - 1); the thread visits, for each period k, the samples around
+// [(k + b/nbins - phase0) period, (k + (b+1)/nbins - phase0) period), keeps
+// those whose bin is b, and adds them in ascending u (a fixed order) in FP64,
+// rounding the sum to FP32 once (a bin may hold the whole series).
+// ---------------------------------------------------------------------------
+#pragma clang fp contract(off)
+__device__ __forceinline__ int fold_bin(int64_t u, double period, double phase0, int nbins) {
+  const double x = (double)u / period + phase0;
+  const int b = (int)floor((x - floor(x)) * (double)nbins);
+  return b < nbins ? b : nbins - 1;
+}
+
+__global__ __launch_bounds__(256) void fold_kernel(const float* __restrict__ I, int64_t t_int,
+                                                   double period, double phase0, int32_t nbins,
+                                                   float* __restrict__ prof,
+                                                   int32_t* __restrict__ cnt) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= nbins) return;
+  const int64_t k0 = (int64_t)floor(phase0) - 1;
+  const int64_t k1 = (int64_t)floor((double)(t_int - 1) / period + phase0) + 1;
+  double s = 0.0;
+  int32_t n = 0;
+  int64_t next = 0;  // samples below have been visited
+  for (int64_t k = k0; k <= k1; ++k) {
+    const double lo = ((double)k + (double)b / nbins - phase0) * period;
+    const double hi = ((double)k + (double)(b + 1) / nbins - phase0) * period;
+    int64_t u0 = (int64_t)floor(lo) - 2, u1 = (int64_t)ceil(hi) + 2;
+    if (u0 < next) u0 = next;
+    if (u1 > t_int) u1 = t_int;
+    for (int64_t u = u0; u < u1; ++u)
+      if (fold_bin(u, period, phase0, nbins) == b) {
+        s += (double)I[u];
+        ++n;
+      }
+    if (u1 > next) next = u1;
+  }
+  prof[b] = (float)s;
+  if (cnt) cnt[b] = n;
+}
+#pragma clang fp contract(on)
+
+int launch_fold(const float* I, int64_t t_int, double period, double phase0, int32_t nbins,
+                float* profile, int32_t* counts, void* stream) {
+  const int64_t nb = ((int64_t)nbins + 255) / 256;
+  if (nb <= 0 || nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(fold_kernel, dim3((unsigned)nb), dim3(256), 0, (hipStream_t)stream, I,
+                     t_int, period, phase0, nbins, profile, counts);
+  return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // I[u] = sum over channels c with u + d_c < T_int of P_c[u + d_c], cov[u] =
 // number of terms.  A workgroup covers 64 consecutive u; its G waves each sum
 // a contiguous channel range in ascending order, and the G partial sums are

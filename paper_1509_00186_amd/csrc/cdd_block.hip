@@ -81,6 +81,7 @@ struct BlockArgs {
   int64_t v_stride, o_lim;
   int64_t nblocks, item0;   // blocks per channel; first work item of this beam
   int32_t nchan, M, nfront, n_int, dtype, phase_mode, exact_div, taper;
+  int32_t accum, pad;   // accum: add to P instead of storing (second polarisation)
   double f_lo, df, dconst;
   DmTile dms;
 };
@@ -284,7 +285,8 @@ __device__ __forceinline__ void epilogue(const float2* v, float* lds, const Bloc
       const int64_t u = u0 + ul;
       if (u >= a.u_lim) break;
       const float4 q = *(const float4*)&lds[a.nfront + 4 * ul];
-      P[u] = ((q.x + q.y) + q.z) + q.w;
+      const float s = ((q.x + q.y) + q.z) + q.w;
+      P[u] = a.accum ? P[u] + s : s;
     }
   } else {
     for (int ul = t; ul < nu; ul += S::T) {
@@ -293,7 +295,7 @@ __device__ __forceinline__ void epilogue(const float2* v, float* lds, const Bloc
       const int base = a.nfront + ul * a.n_int;
       float s = 0.f;
       for (int r = 0; r < a.n_int; ++r) s += lds[base + r];
-      P[u] = s;
+      P[u] = a.accum ? P[u] + s : s;
     }
   }
 }
@@ -528,6 +530,7 @@ static BlockArgs make_args(const BeamPlan& p, const Coords& co, const void* xt, 
   a.v_stride = co.v_stride;
   a.o_lim = co.o_lim;
   a.nblocks = co.nblocks;
+  a.accum = co.accum;
   a.item0 = 0;
   a.nchan = p.nchan;
   a.M = p.M;

@@ -78,6 +78,7 @@ struct Coords {
   int64_t p_stride = 0, p_dm_stride = 0, u_lim = 0;
   int64_t v_stride = 0, o_lim = 0;
   int64_t nblocks = 0;
+  int32_t accum = 0;  // 1: add the integrated samples to P (second polarisation)
 };
 Coords offline_coords(const BeamPlan& p);
 
@@ -97,7 +98,7 @@ int launch_chirp_table(const BeamPlan& p, double dm, void* H, void* stream);
 // and the aligned sums on an auxiliary stream (cdd_pipeline.hip).
 int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, float* P,
                   int32_t* d, void* H, void* volt_out, float* I, int32_t* cov, int chunks,
-                  void* stream);
+                  int npol, void* stream);
 // Batched form: beams that share one transform length, each with its DM
 // tile, in one persistent launch.
 struct BatchBeam {
@@ -118,6 +119,8 @@ int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_t
 int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream);
 // P[c][u] = sum of |x[c][u n_int + r]|^2, r < n_int (channel-major x).
 int launch_detect(const BeamPlan& p, const void* xt, float* P, void* stream);
+int launch_fold(const float* I, int64_t t_int, double period, double phase0, int32_t nbins,
+                float* profile, int32_t* counts, void* stream);
 int launch_dsum(const BeamPlan& p, int ndm, const float* P, const int32_t* d,
                 float* I, int32_t* cov, int64_t out_stride, void* stream);
 // General form: for u in [u_begin, u_begin + u_count),

@@ -71,7 +71,7 @@ static int aux_of(Aux** out) {
 // stream, which the caller's stream waits for before the block kernel.
 static int run_single(Aux& ax, const BeamPlan& p, const void* voltages, double dm, char* xt,
                       float* P, int32_t* d, void* H, void* volt_out, float* I, int32_t* cov,
-                      hipStream_t S) {
+                      int npol, hipStream_t S) {
   hipStream_t A = ax.s;
   hipError_t e;
   int err = 0;
@@ -89,13 +89,21 @@ static int run_single(Aux& ax, const BeamPlan& p, const void* voltages, double d
   if ((err = stage_end(kStageDelays, A, tok))) return err;
   hipEvent_t eA = take(ax);
   if ((e = hipEventRecord(eA, A)) != hipSuccess) return (int)e;
-  if ((err = stage_begin(S, &tok))) return err;
-  if ((err = launch_transpose(voltages, xt, p.dtype, p.nsamp, p.nchan, p.nsamp, S))) return err;
-  if ((err = stage_end(kStageTranspose, S, tok))) return err;
-  if ((e = hipStreamWaitEvent(S, eA, 0)) != hipSuccess) return (int)e;
-  if ((err = stage_begin(S, &tok))) return err;
-  if ((err = launch_block(p, xt, tile, P, volt_out, H, S))) return err;
-  if ((err = stage_end(kStageBlock, S, tok))) return err;
+  // polarisation records back to back; the second adds its intensities
+  const size_t rec = (size_t)p.nsamp * p.nchan * (p.dtype == CDD_CI8 ? 2 : 8);
+  Coords co = offline_coords(p);
+  for (int pol = 0; pol < npol; ++pol) {
+    if ((err = stage_begin(S, &tok))) return err;
+    if ((err = launch_transpose((const char*)voltages + pol * rec, xt, p.dtype, p.nsamp,
+                                p.nchan, p.nsamp, S)))
+      return err;
+    if ((err = stage_end(kStageTranspose, S, tok))) return err;
+    if (pol == 0 && (e = hipStreamWaitEvent(S, eA, 0)) != hipSuccess) return (int)e;
+    co.accum = pol > 0;
+    if ((err = stage_begin(S, &tok))) return err;
+    if ((err = launch_block_co(p, co, xt, tile, P, volt_out, H, S))) return err;
+    if ((err = stage_end(kStageBlock, S, tok))) return err;
+  }
   if ((err = stage_begin(S, &tok))) return err;
   if ((err = launch_dsum(p, 1, P, d, I, cov, p.t_int, S))) return err;
   return stage_end(kStageDsum, S, tok);
@@ -103,7 +111,7 @@ static int run_single(Aux& ax, const BeamPlan& p, const void* voltages, double d
 
 int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, float* P,
                   int32_t* d, void* H, void* volt_out, float* I, int32_t* cov, int chunks,
-                  void* stream) {
+                  int npol, void* stream) {
   std::lock_guard<std::mutex> lk(g_aux_mu);
   Aux* axp = nullptr;
   int aerr = aux_of(&axp);
@@ -111,7 +119,9 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
   Aux& ax = *axp;
   hipError_t e = hipSuccess;
   if (chunks <= 1)
-    return run_single(ax, p, voltages, dm, xt, P, d, H, volt_out, I, cov, (hipStream_t)stream);
+    return run_single(ax, p, voltages, dm, xt, P, d, H, volt_out, I, cov, npol,
+                      (hipStream_t)stream);
+  if (npol != 1) return (int)hipErrorInvalidValue;
   hipStream_t S = (hipStream_t)stream, A = ax.s, S2 = ax.s2;
   const size_t elem = p.dtype == CDD_CI8 ? 2 : 8;
   const int C = chunks;

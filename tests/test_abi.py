@@ -112,6 +112,18 @@ def test_incoherent_validation_without_device():
     assert st == -1 and b"above 0" in cdd.lib.cdd_last_error()
 
 
+def test_fold_validation_without_device():
+    cdd = _lib()
+    st = cdd.lib.cdd_fold(None, 100, 10.0, 0.0, 8, ctypes.c_void_p(0x100), None, None)
+    assert st == -1 and b"NULL" in cdd.lib.cdd_last_error()
+    st = cdd.lib.cdd_fold(ctypes.c_void_p(0x100), 100, 0.5, 0.0, 8, ctypes.c_void_p(0x200),
+                          None, None)
+    assert st == -1 and b"period" in cdd.lib.cdd_last_error()
+    st = cdd.lib.cdd_fold(ctypes.c_void_p(0x100), 100, 10.0, 0.0, 0, ctypes.c_void_p(0x200),
+                          None, None)
+    assert st == -1 and b"nbins" in cdd.lib.cdd_last_error()
+
+
 def test_explicit_plan_validation():
     cdd = _lib()
     ok = cdd.query(0, 10_000, 64, 325.0, 4.0, 30.0, 1024, 4, overlap=128, nfront=64)

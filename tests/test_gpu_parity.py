@@ -198,6 +198,45 @@ def test_incoherent_against_oracle():
     assert rel_l2(g["I"].cpu().numpy(), o["I"]) <= 1e-6
 
 
+def test_fold_against_oracle():
+    """Folding on the GPU: counts exact, per-bin sums (ascending u, FP64
+    accumulation) against the FP64 oracle, at integer and fractional periods
+    and with a single bin holding the whole series."""
+    import torch
+    cdd = _cdd()
+    rng = np.random.default_rng(170)
+    I = rng.random(62_500).astype(np.float32) * 1000
+    for period, phase0, nbins in ((1390.625, 0.3, 128), (37.0, -2.25, 37), (5000.5, 0.0, 1)):
+        prof, cnt = cdd.fold(to_dev(I), period, phase0, nbins)
+        torch.cuda.synchronize()
+        op, oc = O.fold(I.astype(np.float64), period, phase0, nbins)
+        assert np.array_equal(cnt.cpu().numpy(), oc), (period, nbins)
+        assert rel_l2(prof.cpu().numpy(), op) <= 1e-6, (period, nbins)
+
+
+def test_two_polarisations_sum_their_intensities():
+    """npol = 2: two records back to back; per-channel and aligned
+    intensities equal the oracle's sums over the two polarisations."""
+    import torch
+    cdd = _cdd()
+    fcen, nchan, df, nsamp, dm, N = 325.0, 32, 0.0625, 30_000, 67.9, 2048
+    p0 = _beam_int8(180, nsamp, nchan, fcen, nchan * df, dm)
+    p1 = _beam_int8(181, nsamp, nchan, fcen, nchan * df, dm)
+    both = np.ascontiguousarray(np.stack([p0, p1]))
+    g = cdd.dedisperse(to_dev(both), fcen, nchan * df, dm, N, 4, want_chan=True, npol=2)
+    torch.cuda.synchronize()
+    info = g["info"]
+    o0 = O.dedisperse(p0, fcen, nchan * df, dm, 4, fft_len=N, overlap=info["overlap"],
+                      nfront=info["nfront"])
+    o1 = O.dedisperse(p1, fcen, nchan * df, dm, 4, fft_len=N, overlap=info["overlap"],
+                      nfront=info["nfront"])
+    assert rel_l2(g["P"].cpu().numpy(), o0["P"] + o1["P"]) <= TOL_I
+    assert rel_l2(g["I"].cpu().numpy(), o0["I"] + o1["I"]) <= TOL_I
+    assert np.array_equal(g["cov"].cpu().numpy(), o0["cov"])
+    with pytest.raises(cdd.CddError):
+        cdd.dedisperse(to_dev(both), fcen, nchan * df, dm, N, 4, npol=2, time_chunks=2)
+
+
 def test_config2_full_size():
     """512 channels x 4 s at 32 MHz, N = 8192, n_int = 4, DM 67.9, in the
     launch shape the benchmark times: per-channel intensities of 64 sampled
