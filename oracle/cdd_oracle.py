@@ -9,7 +9,8 @@ It is written from De & Gupta, "A Real-time Coherent Dedispersion Pipeline
 for the Giant Metrewave Radio Telescope" (Experimental Astronomy), as plainly
 as possible: every quantity is computed in float64 with no reduction, no
 blocking beyond what overlap-save itself prescribes, and no fusion.  Library
-primitives used as steps: ``numpy.fft.fft`` / ``numpy.fft.ifft``.
+primitives used as steps: ``numpy.fft.fft`` / ``numpy.fft.ifft`` and, for
+real series, ``numpy.fft.rfft`` / ``numpy.fft.irfft``.
 
 Readings of the paper that it follows (each is listed with its reason in the
 design notes of the repository):
@@ -32,6 +33,10 @@ design notes of the repository):
   channel): none (rectangular), Hanning 1/2 (1 + cos 2 pi x) or Welch
   1 - (2 x)^2, with x = f / df the bin's offset from the channel centre as a
   fraction of the channel width, x in [-1/2, 1/2).
+* Full-band mode (Sec. 2.1, 2.3, 3.1): the recorded spectra are real-FFT
+  outputs; their inverse transforms give back the real series (sampled at
+  twice the band), which is dedispersed as one band with the filter of
+  Eq. 3 about the lower band edge, by overlap-save with real transforms.
 * Incoherent alignment of channels (Sec. 1.2; the linear term of Eq. 2):
   per-channel delay d_c = floor(D*DM*(f_c^-2 - f_ref^-2)*df/n_int + 0.5)
   integrated samples, f_ref the highest channel centre (lowest for DM < 0);
@@ -333,6 +338,130 @@ def fold(I: np.ndarray, period: float, phase0: float, nbins: int):
         prof[b] += I[u]
         cnt[b] += 1
     return prof, cnt
+
+
+# --------------------------------------------------------------------------
+# Full-band mode: the recorded spectra back to one real series, then one
+# long real transform over the whole band (Sec. 2.1, 2.3, 3.1)
+# --------------------------------------------------------------------------
+def gsb_inverse(spectra) -> np.ndarray:
+    """Inverse transform of voltage-beam records (Sec. 2.3; the inverse
+    transform routine of Sec. 3.1).  Record t holds bins 0 .. nchan-1 (DC
+    first) of a 2*nchan-point real FFT of the real sampled voltage; its
+    Nyquist bin is not recorded (taken as zero) and the imaginary part of
+    its DC bin is dropped (a real series has a real DC term).  Each record
+    is inverse transformed with 1/(2 nchan), so a record made by a forward
+    real FFT gives its samples back, and the records are laid end to end.
+
+    spectra: [T][nchan][2] int8 or [T][nchan] complex -> float64 [T*2*nchan].
+    """
+    X = as_complex(spectra)
+    T, nchan = X.shape
+    full = np.zeros((T, nchan + 1), dtype=np.complex128)
+    full[:, :nchan] = X
+    full[:, 0] = full[:, 0].real
+    return np.fft.irfft(full, n=2 * nchan, axis=1).reshape(-1)
+
+
+def band_window(x: np.ndarray, kind: str = "none") -> np.ndarray:
+    """The taper of Sec. 2.2 at x = position in the band, in [-1/2, 1/2]."""
+    x = np.asarray(x, dtype=np.float64)
+    if kind == "none":
+        return np.ones_like(x)
+    if kind == "hann":
+        return 0.5 * (1.0 + np.cos(2.0 * np.pi * x))
+    if kind == "welch":
+        return 1.0 - (2.0 * x) ** 2
+    raise ValueError("unknown taper %r" % kind)
+
+
+def fullband_transfer(n: int, f_lo: float, bw: float, dm: float, dconst: float = D_PAPER,
+                      sign: int = -1, window: str = "none") -> np.ndarray:
+    """Filter on the n/2 + 1 bins of an n-point real FFT of the band
+    [f_lo, f_lo + bw] sampled at 2 bw (Sec. 2.1: real-sampled band, offsets
+    f_l from its lower edge f_o): bin j lies f = j*bw/(n/2) above f_lo and
+    takes exp(sign 2 pi i q(f)) with q of Eq. 3 about f_lo; the taper spans
+    the band, x = f/bw - 1/2."""
+    j = np.arange(n // 2 + 1, dtype=np.float64)
+    f = j * (bw / (n // 2))
+    q = chirp_turns(f, f_lo, dm, dconst)
+    return np.exp(sign * 2j * np.pi * q) * band_window(f / bw - 0.5, window)
+
+
+def fullband_plan(f_lo: float, bw: float, dm: float, n_int: int,
+                  fft_len: int | None = None, dconst: float = D_PAPER):
+    """(N, L, nfront) in real samples at rate 2 bw for the full-band filter
+    about the lower band edge.  The filter delays every frequency above f_lo
+    to f_lo's arrival, so for DM >= 0 its impulse response reaches forward
+    only, by the dispersion time across the band (Sec. 2.2): front = ceil of
+    it, back = 0 (the other way round for DM < 0).  L = the power of two at or
+    above front + back (at least 2), raised until n_int divides N - L; nfront
+    = front + floor((L - front - back)/2), moved to an even value inside
+    [front, L - back].  N defaults to the Sec. 2.3 rule, raised to 2L and 512.
+    n_int must be even (integration over pairs of real samples)."""
+    if n_int < 2 or n_int % 2:
+        raise ValueError("n_int must be even")
+    reach = dispersion_samples(f_lo, f_lo + bw, 2.0 * bw, dm, dconst)
+    front, back = (math.ceil(reach), 0) if dm >= 0 else (0, math.ceil(reach))
+    L = next_pow2(max(2, front + back))
+    if fft_len is None:
+        fft_len = max(fft_len_rule(reach), 2 * L, 512)
+    N = int(fft_len)
+    while L < N and (N - L) % n_int != 0:
+        L += 1
+    if L >= N:
+        raise ValueError("fft_len too short for this DM: need N > %d" % L)
+    nf = front + (L - front - back) // 2
+    if nf % 2:
+        nf = nf + 1 if nf + 1 <= L - back else nf - 1
+    return N, L, nf
+
+
+def overlap_save_real(x: np.ndarray, H: np.ndarray, N: int, L: int, nfront: int) -> np.ndarray:
+    """overlap_save for a real series: each block's real FFT (N/2 + 1 bins)
+    is multiplied by H and inverse real transformed (the imaginary parts a
+    real series cannot carry at DC and Nyquist are dropped)."""
+    x = np.asarray(x, dtype=np.float64)
+    M = N - L
+    T = x.shape[0]
+    y = np.zeros(T)
+    for k in range(-(-T // M)):
+        start = k * M - nfront
+        s = np.zeros(N)
+        lo, hi = max(0, start), min(T, start + N)
+        if hi > lo:
+            s[lo - start:hi - start] = x[lo:hi]
+        z = np.fft.irfft(np.fft.rfft(s) * H, n=N)
+        take = min(M, T - k * M)
+        y[k * M:k * M + take] = z[nfront:nfront + take]
+    return y
+
+
+def fullband_dedisperse(spectra, f_centre: float, bw: float, dm: float, n_int: int,
+                        fft_len: int | None = None, overlap: int | None = None,
+                        nfront: int | None = None, dconst: float = D_PAPER,
+                        window: str = "none", sign: int = -1, want_voltages: bool = False):
+    """The paper's unchannelised mode: recorded spectra -> real series
+    (gsb_inverse) -> overlap-save with the full-band chirp about the lower
+    band edge (real samples at 2 bw) -> y^2 integrated over n_int samples.
+    ``spectra`` may also be a real float series (then taken as is).
+    Returns N, L, nfront, P [T/n_int], and x, y if asked."""
+    a = np.asarray(spectra)
+    x = a.astype(np.float64) if a.ndim == 1 and not np.iscomplexobj(a) else gsb_inverse(a)
+    f_lo = f_centre - bw / 2.0
+    if fft_len is None or overlap is None or nfront is None:
+        N, L, nf = fullband_plan(f_lo, bw, dm, n_int, fft_len, dconst)
+        fft_len = fft_len or N
+        overlap = L if overlap is None else overlap
+        nfront = nf if nfront is None else nfront
+    H = fullband_transfer(fft_len, f_lo, bw, dm, dconst, sign, window)
+    y = overlap_save_real(x, H, fft_len, overlap, nfront)
+    t_int = y.shape[0] // n_int
+    P = (y[:t_int * n_int] ** 2).reshape(t_int, n_int).sum(-1)
+    out = {"N": fft_len, "L": overlap, "nfront": nfront, "P": P}
+    if want_voltages:
+        out["x"], out["y"] = x, y
+    return out
 
 
 def dft_direct(x: np.ndarray, sign: int = -1) -> np.ndarray:

@@ -453,3 +453,172 @@ def test_coherent_folded_profile_is_sharper_than_incoherent():
     share = lambda p: p.max() / p.sum()     # noqa: E731
     assert share(pc) > 4 * share(pi), (share(pc), share(pi))
     assert abs(int(np.argmax(pc)) - 0) <= 2 or abs(int(np.argmax(pc)) - 128) <= 2
+
+
+# ---------------------------------------------------------------------------
+# Full-band mode: recorded spectra -> real series -> one long real transform
+# (Sec. 2.1 real-sampled band from its lower edge, Sec. 2.3, Sec. 3.1)
+# ---------------------------------------------------------------------------
+def _real_idft_direct(X, n):
+    """x[m] = (1/n) (Re X_0 + Re X_{n/2} (-1)^m + 2 sum_{0<j<n/2} Re(X_j
+    exp(2 pi i j m / n))) by explicit loops: the inverse DFT of a Hermitian
+    spectrum given by its first n/2 + 1 bins."""
+    out = np.zeros(n)
+    for m in range(n):
+        acc = X[0].real + (X[n // 2].real * (-1) ** m if len(X) > n // 2 else 0.0)
+        for j in range(1, n // 2):
+            ang = 2.0 * math.pi * ((j * m) % n) / n
+            acc += 2.0 * (X[j] * complex(math.cos(ang), math.sin(ang))).real
+        out[m] = acc / n
+    return out
+
+
+def test_gsb_inverse_is_the_explicit_real_inverse_sum():
+    """Each record's bins 0..nchan-1 (Nyquist absent, DC imaginary part
+    dropped) inverse transformed by the explicit real inverse DFT sum, and
+    records laid end to end in time order."""
+    rng = np.random.default_rng(31)
+    nchan, T = 8, 3
+    sp = rng.integers(-100, 100, size=(T, nchan, 2)).astype(np.int8)
+    x = O.gsb_inverse(sp)
+    assert x.shape == (T * 2 * nchan,)
+    for t in range(T):
+        X = sp[t, :, 0].astype(float) + 1j * sp[t, :, 1].astype(float)
+        want = _real_idft_direct(np.append(X, 0.0), 2 * nchan)
+        assert np.allclose(x[t * 2 * nchan:(t + 1) * 2 * nchan], want, atol=1e-12)
+
+
+def test_gsb_inverse_returns_the_recorded_series_but_its_nyquist_term():
+    """Records made by a forward real FFT of consecutive 2*nchan-sample
+    segments come back as those segments, less the unrecorded Nyquist term
+    X_nchan (-1)^m / (2 nchan) of each; a tone at bin c comes back as a
+    cosine of c cycles per record."""
+    rng = np.random.default_rng(32)
+    nchan, T = 16, 5
+    x = rng.standard_normal(T * 2 * nchan)
+    seg = x.reshape(T, 2 * nchan)
+    spec = np.fft.rfft(seg, axis=1)
+    back = O.gsb_inverse(spec[:, :nchan])
+    m = np.arange(2 * nchan)
+    nyq = spec[:, nchan].real[:, None] * ((-1.0) ** m)[None, :] / (2 * nchan)
+    assert np.allclose(back, (seg - nyq).reshape(-1), atol=1e-12)
+    tone = np.zeros((1, nchan), dtype=complex)
+    tone[0, 3] = nchan  # amplitude 1 after the 1/(2 nchan) and the mirror bin
+    assert np.allclose(O.gsb_inverse(tone), np.cos(2 * np.pi * 3 * m / (2 * nchan)), atol=1e-12)
+
+
+@pytest.mark.parametrize("N,L,nfront,T", [(64, 16, 6, 300), (32, 8, 0, 70), (16, 4, 4, 16)])
+def test_fullband_overlap_save_equals_brute_force_real_convolution(N, L, nfront, T):
+    """Every block of the real overlap-save equals the circular convolution
+    of the block with the real impulse response (explicit real inverse DFT
+    of the filter), kept from nfront for N - L samples."""
+    rng = np.random.default_rng(N + T)
+    x = rng.standard_normal(T)
+    H = O.fullband_transfer(N, 300.0, 4.0, 0.02)
+    h = _real_idft_direct(H, N)
+    M = N - L
+    want = np.zeros(T)
+    for k in range(-(-T // M)):
+        s = np.zeros(N)
+        for n in range(N):
+            t = k * M - nfront + n
+            if 0 <= t < T:
+                s[n] = x[t]
+        for m in range(M):
+            if k * M + m < T:
+                n = nfront + m
+                want[k * M + m] = sum(s[i] * h[(n - i) % N] for i in range(N))
+    got = O.overlap_save_real(x, H, N, L, nfront)
+    assert np.allclose(got, want, atol=1e-11)
+
+
+def test_fullband_dm_zero_is_identity():
+    rng = np.random.default_rng(33)
+    x = rng.standard_normal(5000)
+    r = O.fullband_dedisperse(x, 610.0, 16.0, 0.0, 4, fft_len=1024, overlap=64,
+                              nfront=20, want_voltages=True)
+    assert np.allclose(r["y"], x, atol=1e-12)
+    assert np.allclose(r["P"], (x[:5000 // 4 * 4] ** 2).reshape(-1, 4).sum(1))
+
+
+def test_fullband_filter_delays_each_frequency_to_the_lower_edge_arrival():
+    """A real-sampled pulse built from wave packets that arrive at t0 + the
+    cold-plasma delay of their frequency relative to the lower band edge
+    (earlier for higher frequencies) collapses at t0 after the full-band
+    filter, and smears with the opposite sign.  Baseband frequency fb of the
+    real series is the sky frequency f_lo + fb (upper sideband)."""
+    f_lo, bw, dm = 300.0, 4.0, 5.0
+    fs = 2.0 * bw
+    nsamp = 1 << 17
+    t0 = 14000.0  # us: arrival at f_lo
+    law = arrival_law(dm, f_lo)
+    sweep_us = -law(f_lo + bw)
+    assert sweep_us > 5000
+    rng = np.random.default_rng(34)
+    t = np.arange(nsamp) / fs
+    x = np.zeros(nsamp)
+    nsub, sig = 128, 40.0 / 2.3548
+    for k in range(nsub):
+        fb = (k + 0.5) * bw / nsub
+        tau = t0 + law(f_lo + fb)
+        env = np.exp(-0.5 * ((t - tau) / sig) ** 2)
+        x += env * np.cos(2 * np.pi * fb * (t - tau) + rng.uniform(0, 2 * np.pi))
+    N, L, nf = O.fullband_plan(f_lo, bw, dm, 2)
+    assert L >= sweep_us * fs
+    y = O.overlap_save_real(x, O.fullband_transfer(N, f_lo, bw, dm), N, L, nf)
+    p = _smooth(y * y, 64)
+    c = int(t0 * fs)
+    assert abs(int(np.argmax(p)) - c) < 80
+    assert np.sum(y[c - 600:c + 600] ** 2) > 0.5 * np.sum(y * y)
+    yw = O.overlap_save_real(x, O.fullband_transfer(N, f_lo, bw, dm, sign=+1), N, L, nf)
+    assert _smooth(yw * yw, 64).max() < 0.1 * p.max()
+
+
+def test_fullband_impulse_response_reaches_forward_by_the_sweep():
+    """About the lower edge the dedispersing filter is causal: a delta comes
+    out spread over [0, sweep] samples after it (ripple aside), nothing
+    before; the plan's front covers the sweep and nfront lies inside it."""
+    f_lo, bw, dm = 600.0, 2.0, 30.0
+    N, L, nf = O.fullband_plan(f_lo, bw, dm, 2)
+    sweep = O.dispersion_samples(f_lo, f_lo + bw, 2 * bw, dm)
+    assert math.ceil(sweep) <= nf <= L and nf % 2 == 0
+    h = np.fft.irfft(O.fullband_transfer(N, f_lo, bw, dm), n=N)
+    e = h * h
+    fwd = e[:int(sweep) + 8].sum()
+    assert fwd > 0.99 * e.sum()
+    assert e[N - 64:].sum() < 1e-3 * e.sum()
+
+
+def test_fullband_plan_reproduces_the_papers_lengths():
+    """The Sec. 2.3 rule on the whole band: 2^19 real points (= the 2^18
+    complex of the channel form) and a 2^18 overlap for 16 MHz at 610 MHz,
+    DM 10; 2^27 real points for each of Sec. 4.5's memory-bound DM limits."""
+    N, L, nf = O.fullband_plan(602.0, 16.0, 10.0, 16)
+    assert (N, L) == (1 << 19, 1 << 18)
+    g = json.load(open(os.path.join(GOLDEN, "max_dm_sec4_5.json")))
+    for case in g["cases"]:
+        f, bw, dm = case["f_mhz"], case["bw_mhz"], case["dm"]
+        assert O.fullband_plan(f - bw / 2, bw, dm, 2)[0] == 1 << 27, case
+
+
+def test_fullband_and_gsb_inverse_take_int8_records():
+    """The int8 [T][nchan][2] records and the same values as complex give
+    the same full-band result."""
+    rng = np.random.default_rng(35)
+    sp = rng.integers(-60, 60, size=(40, 32, 2)).astype(np.int8)
+    cx = sp[..., 0].astype(float) + 1j * sp[..., 1]
+    a = O.fullband_dedisperse(sp, 610.0, 16.0, 0.01, 4, fft_len=1024)
+    b = O.fullband_dedisperse(cx, 610.0, 16.0, 0.01, 4, fft_len=1024)
+    assert np.array_equal(a["P"], b["P"])
+
+
+def test_fullband_hanning_at_dm_zero_is_the_band_pass_three_tap_filter():
+    """Over the band [f_lo, f_lo + bw] the Hanning window is sin^2(pi f/bw)
+    = 1/2 - cos(2 pi f/bw)/2; at DM 0 on a real series sampled at 2 bw that
+    is y[n] = x[n]/2 - (x[n-2] + x[n+2])/4 (zero at DC and Nyquist)."""
+    rng = np.random.default_rng(36)
+    x = rng.standard_normal(3000)
+    r = O.fullband_dedisperse(x, 610.0, 16.0, 0.0, 2, fft_len=512, overlap=8, nfront=4,
+                              window="hann", want_voltages=True)
+    want = 0.5 * x[2:-2] - 0.25 * (x[:-4] + x[4:])
+    assert np.allclose(r["y"][2:-2], want, atol=1e-12)
