@@ -208,6 +208,87 @@ cdd_status cdd_fold(const float* intensity, int64_t t_int, double period, double
                     int32_t nbins, float* profile, int32_t* counts, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Full-band mode: the paper's own pipeline without sub-banding (Sec. 2.1,
+ * 2.3, 3.1).  The recorded voltage beam is a sequence of records, each the
+ * first nchan bins (DC upward) of a 2 nchan-point real FFT of the real
+ * sampled voltage, as int8 (re, im): [nspec][nchan][2].  The records are
+ * inverse transformed back into one real series of nsamp = nspec * 2 nchan
+ * samples at 2 bw samples per microsecond (upper sideband: baseband
+ * frequency f is sky frequency f_lo + f, f_lo = f_centre - bw/2), which is
+ * dedispersed as one band by overlap-save with real transforms of N points:
+ * bin j (0 .. N/2) lies f = j bw / (N/2) above f_lo and takes exp(-2 pi i q),
+ * q = D*DM*f^2 / (f_lo^2 (f_lo + f)) turns (Eq. 3 about the lower band edge,
+ * so the output is referenced to the arrival time at f_lo), times the taper
+ * over the band at x = f/bw - 1/2 and 1/N; the imaginary parts at DC and
+ * Nyquist are dropped (the series is real).  Block k transforms samples
+ * [k M - nfront, k M - nfront + N) and keeps [nfront, nfront + M), M = N - L.
+ * Output: y^2 summed over n_int samples, I[u], u < t_int = nsamp / n_int.
+ * ------------------------------------------------------------------- */
+typedef struct {
+  int32_t fft_len;     /* N, real points                                    */
+  int32_t overlap;     /* L                                                 */
+  int32_t nfront;      /* front discard                                     */
+  int32_t step;        /* M = N - L                                         */
+  int64_t nsamp;       /* real samples, nspec * 2 nchan                     */
+  int64_t nblocks;     /* ceil(nsamp / M)                                   */
+  int64_t t_int;       /* nsamp / n_int                                     */
+  int32_t front;       /* ceil of the impulse response's forward reach      */
+  int32_t back;        /* the same backward (DM < 0)                        */
+  size_t ws_bytes;     /* workspace cdd_fullband_dedisperse needs           */
+} cdd_fullband_info;
+
+/*
+ * cdd_gsb_inverse -- the inverse transform alone (Sec. 3.1, the inverse
+ * transform routine; Eq. 4 counts its cost).
+ *   spectra  device int8 [nspec][nchan][2], 4-byte aligned
+ *   series   device float [nspec * 2 nchan], 8-byte aligned: record t gives
+ *            samples [2 nchan t, 2 nchan (t + 1)) = its real inverse DFT with
+ *            1/(2 nchan); the Nyquist bin is taken as zero and the imaginary
+ *            part of the DC bin is dropped
+ * Errors: EINVAL for NULL or misaligned pointers, nspec < 1, nchan not a
+ * power of two in [128, 2048]; EDEVICE if the launch fails.
+ */
+cdd_status cdd_gsb_inverse(const void* spectra, int64_t nspec, int32_t nchan, float* series,
+                           void* stream);
+
+/*
+ * cdd_fullband_query -- plan figures and workspace size (host only).  Rules
+ * in real samples (Sec. 2.2, 2.3): front = ceil of the dispersion samples
+ * across the band, D*|DM|*(f_lo^-2 - f_hi^-2) * 2 bw, for DM >= 0 (back = 0;
+ * swapped for DM < 0); L = the power of two >= front + back (>= 2), raised
+ * until n_int divides N - L; nfront = front + (L - front - back)/2, moved to
+ * the even neighbour inside [front, L - back]; N (if 0) = max(smallest power
+ * of two > 2 x the dispersion samples, 2L, 2^16).  opts: dm_const, taper and
+ * explicit_plan (fft_len, overlap, nfront even) apply.
+ * Errors: EINVAL for nspec < 1, nchan not a power of two in [128, 2048],
+ * n_int odd or < 2 or above nsamp, bw <= 0, f_centre - bw/2 <= 0, non-finite
+ * values, fft_len not a power of two in [2^16, 2^23], an overlap shorter
+ * than the impulse response; ENOTSUP when the rule asks for more than 2^23
+ * points, for CDD_PHASE_FP32, npol, kernel_variant or time_chunks.
+ */
+cdd_status cdd_fullband_query(int64_t nspec, int32_t nchan, double f_centre_mhz, double bw_mhz,
+                              double dm, int32_t fft_len, int32_t n_int, const cdd_opts* opts,
+                              cdd_fullband_info* info);
+
+/*
+ * cdd_fullband_dedisperse -- inverse transform, full-band dedispersion,
+ * detection and integration of one recorded beam.
+ *   spectra    device int8 [nspec][nchan][2], 4-byte aligned
+ *   intensity  out, device float [t_int]
+ *   volt_out   out, device float [nsamp], the dedispersed real series, or
+ *              NULL (8-byte aligned)
+ *   workspace  device scratch of info.ws_bytes, 256-byte aligned (the real
+ *              series, one chunk of block spectra and the per-pair y^2)
+ * Errors: as cdd_fullband_query, plus NULL or misaligned pointers and a short
+ * workspace (EINVAL); EDEVICE if a launch fails.
+ */
+cdd_status cdd_fullband_dedisperse(const void* spectra, int64_t nspec, int32_t nchan,
+                                   double f_centre_mhz, double bw_mhz, double dm,
+                                   int32_t fft_len, int32_t n_int, float* intensity,
+                                   float* volt_out, const cdd_opts* opts, void* workspace,
+                                   size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
  * Batched form: many DM trials on several beams in one launch.  The
  * forward transform of each (beam, channel, block) is computed once and
  * every DM trial reuses it; the chirp is generated on the fly per trial.

@@ -397,15 +397,16 @@ def fullband_plan(f_lo: float, bw: float, dm: float, n_int: int,
     it, back = 0 (the other way round for DM < 0).  L = the power of two at or
     above front + back (at least 2), raised until n_int divides N - L; nfront
     = front + floor((L - front - back)/2), moved to an even value inside
-    [front, L - back].  N defaults to the Sec. 2.3 rule, raised to 2L and 512.
-    n_int must be even (integration over pairs of real samples)."""
+    [front, L - back].  N defaults to the Sec. 2.3 rule, raised to 2L and to
+    2^16 (the mode is for long transforms; shorter ones are the channel
+    form's).  n_int must be even (integration over pairs of real samples)."""
     if n_int < 2 or n_int % 2:
         raise ValueError("n_int must be even")
     reach = dispersion_samples(f_lo, f_lo + bw, 2.0 * bw, dm, dconst)
     front, back = (math.ceil(reach), 0) if dm >= 0 else (0, math.ceil(reach))
     L = next_pow2(max(2, front + back))
     if fft_len is None:
-        fft_len = max(fft_len_rule(reach), 2 * L, 512)
+        fft_len = max(fft_len_rule(reach), 2 * L, 1 << 16)
     N = int(fft_len)
     while L < N and (N - L) % n_int != 0:
         L += 1

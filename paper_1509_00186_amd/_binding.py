@@ -45,6 +45,17 @@ class PlanInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class FullbandInfo(ctypes.Structure):
+    _fields_ = [("fft_len", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("nfront", ctypes.c_int32), ("step", ctypes.c_int32),
+                ("nsamp", ctypes.c_int64), ("nblocks", ctypes.c_int64),
+                ("t_int", ctypes.c_int64), ("front", ctypes.c_int32),
+                ("back", ctypes.c_int32), ("ws_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class BeamDesc(ctypes.Structure):
     _fields_ = [("voltages", ctypes.c_void_p), ("dtype", ctypes.c_int32),
                 ("nchan", ctypes.c_int32), ("nsamp", ctypes.c_int64),
@@ -145,6 +156,14 @@ def _load():
     lib.cdd_incoherent.restype = ctypes.c_int
     lib.cdd_fold.argtypes = [vp, i64, f64, f64, i32, vp, vp, vp]
     lib.cdd_fold.restype = ctypes.c_int
+    lib.cdd_gsb_inverse.argtypes = [vp, i64, i32, vp, vp]
+    lib.cdd_gsb_inverse.restype = ctypes.c_int
+    lib.cdd_fullband_query.argtypes = [i64, i32, f64, f64, f64, i32, i32, ctypes.POINTER(Opts),
+                                       ctypes.POINTER(FullbandInfo)]
+    lib.cdd_fullband_query.restype = ctypes.c_int
+    lib.cdd_fullband_dedisperse.argtypes = [vp, i64, i32, f64, f64, f64, i32, i32, vp, vp,
+                                            ctypes.POINTER(Opts), vp, sz, vp]
+    lib.cdd_fullband_dedisperse.restype = ctypes.c_int
     return lib
 
 
@@ -324,6 +343,64 @@ def fold(intensity, period, phase0=0.0, nbins=128, stream=None):
                         int(nbins), ctypes.c_void_p(prof.data_ptr()),
                         ctypes.c_void_p(cnt.data_ptr()), _stream_handle(stream)))
     return prof, cnt
+
+
+def _records(spectra):
+    """(nspec, nchan) of a device int8 [nspec][nchan][2] record tensor."""
+    import torch
+    if (not spectra.is_cuda or spectra.dtype != torch.int8 or spectra.dim() != 3
+            or spectra.shape[2] != 2 or not spectra.is_contiguous()):
+        raise ValueError("spectra must be a contiguous int8 device tensor [nspec][nchan][2]")
+    return spectra.shape[0], spectra.shape[1]
+
+
+def gsb_inverse(spectra, stream=None, out=None):
+    """cdd_gsb_inverse: recorded real-FFT spectra [nspec][nchan][2] int8 ->
+    the real series [nspec * 2 nchan] float32 (device tensors)."""
+    import torch
+    nspec, nchan = _records(spectra)
+    if out is None:
+        out = torch.empty(nspec * 2 * nchan, dtype=torch.float32, device=spectra.device)
+    _check(lib.cdd_gsb_inverse(ctypes.c_void_p(spectra.data_ptr()), nspec, nchan,
+                               ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def fullband_query(nspec, nchan, f_centre, bw, dm, n_int=2, fft_len=0, **opt):
+    """Plan figures of cdd_fullband_query (host only)."""
+    info = FullbandInfo()
+    o = make_opts(fft_len, **opt)
+    _check(lib.cdd_fullband_query(int(nspec), int(nchan), float(f_centre), float(bw), float(dm),
+                                  int(fft_len), int(n_int), ctypes.byref(o), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def fullband(spectra, f_centre, bw, dm, n_int=2, fft_len=0, *, overlap=None, nfront=None,
+             dm_const=0.0, taper="none", want_voltages=False, stream=None, out=None):
+    """cdd_fullband_dedisperse on resident records: returns a dict with I
+    [t_int] float32, y [nsamp] float32 (the dedispersed real series, if
+    want_voltages) and info.  ``out`` may pass preallocated I, y, ws."""
+    import torch
+    nspec, nchan = _records(spectra)
+    o = make_opts(fft_len, overlap, nfront, dm_const, taper=taper)
+    info = FullbandInfo()
+    _check(lib.cdd_fullband_query(nspec, nchan, float(f_centre), float(bw), float(dm),
+                                  int(fft_len), int(n_int), ctypes.byref(o), ctypes.byref(info)))
+    dev = spectra.device
+    out = dict(out or {})
+    if "I" not in out:
+        out["I"] = torch.empty(info.t_int, dtype=torch.float32, device=dev)
+    if want_voltages and "y" not in out:
+        out["y"] = torch.empty(info.nsamp, dtype=torch.float32, device=dev)
+    if "ws" not in out or out["ws"].numel() < info.ws_bytes:
+        out["ws"] = torch.empty(max(info.ws_bytes, 256), dtype=torch.uint8, device=dev)
+    _check(lib.cdd_fullband_dedisperse(
+        ctypes.c_void_p(spectra.data_ptr()), nspec, nchan, float(f_centre), float(bw), float(dm),
+        int(fft_len), int(n_int), ctypes.c_void_p(out["I"].data_ptr()),
+        ctypes.c_void_p(out["y"].data_ptr()) if want_voltages else None, ctypes.byref(o),
+        ctypes.c_void_p(out["ws"].data_ptr()), out["ws"].numel(), _stream_handle(stream)))
+    out["info"] = info.as_dict()
+    return out
 
 
 class Plan:

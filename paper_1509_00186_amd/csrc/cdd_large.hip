@@ -17,11 +17,13 @@
 // that global accesses along n1 are contiguous.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
 
 #include "cdd_fft.h"
+#include "cdd_fullband.h"
 #include "cdd_internal.h"
 
 namespace cdd {
@@ -46,6 +48,10 @@ struct LargeArgs {
   int64_t nsamp, nblocks, item0;
   int32_t nchan, N1, N2, M, nfront, sl, phase_mode, exact_div, taper;
   double f_lo, df, dconst, dm;
+  // full-band mode: W_{2N}^m = tw2[m & (2^sl2-1)] * tw2[2^sl2 + (m >> sl2)], band width
+  const float2* tw2;
+  int32_t sl2;
+  double bw;
 };
 
 __device__ __forceinline__ float2 tw4_fwd(const LargeArgs& a, int64_t m) {
@@ -225,6 +231,200 @@ __global__ __launch_bounds__(256) void integrate_kernel(const float* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Full-band mode: one real series over the whole band (Sec. 2.1, 2.3, 3.1)
+// ---------------------------------------------------------------------------
+// A real block of 2N samples is transformed as N complex points z[n] =
+// x[2n] + i x[2n+1].  With Z = DFT_N(z), the spectra of the even and odd
+// samples are E_i = (Z_i + conj Z_(N-i)) / 2 and O_i = (Z_i - conj Z_(N-i)) /
+// (2i), and the real spectrum is X_i = E_i + w^i O_i, X_(N-i) = conj(E_i -
+// w^i O_i), w = exp(-i pi / N).  After the filter, Y = H X, the same relations
+// taken backwards give Z', whose inverse DFT holds the filtered samples in
+// pairs.  In the four-step layout bin i = k2 + N2 k1 sits in row k2 and its
+// mirror N - i in row N2 - k2 at k1' = N1 - 1 - k1 (row 0: k1' = -k1 mod N1),
+// so one workgroup transforms rows k2 and N2 - k2 together and hands each
+// row to the other through LDS.
+__device__ __forceinline__ float2 tw2_fwd(const LargeArgs& a, int64_t m) {
+  const float2 lo = a.tw2[m & ((1 << a.sl2) - 1)];
+  const float2 hi = a.tw2[(1 << a.sl2) + (m >> a.sl2)];
+  return cmul(lo, hi);
+}
+
+// Chirp of Eq. 3 about the lower band edge at real-spectrum bin j (0 .. N):
+// f = j bw / N above f_lo, q = D DM f^2 / (f_lo^2 (f_lo + f)) = B j^2 /
+// (1 + beta j) turns in FP64, reduced before the FP32 rotation; times the
+// band taper at x = j/N - 1/2 and the 1/N of the inverse transform.
+__device__ __forceinline__ float2 band_chirp(const LargeArgs& a, double B, double beta,
+                                             int64_t j, float inv_n) {
+  const double s = (double)j;
+  const double q = (B * (s * s)) / fma(beta, s, 1.0);
+  const float2 h = expi_neg_turns(q);
+  const float g = inv_n * taper_gain<false>(a.taper, (float)j * inv_n - 0.5f);
+  return make_float2(h.x * g, h.y * g);
+}
+
+template <int L, int LDSF>
+constexpr int pair_stride() {
+  return 2 * L > LDSF + 1 ? 2 * L : ((LDSF + 1 + 3) & ~3);
+}
+
+// One mirror pair of the packed spectrum: from Z_i and Z_(N-i) (z, zm) to
+// the filtered Z'_i and Z'_(N-i).  With E' = (Y_i + conj Y_(N-i)) / 2 and
+// O' = (Y_i - conj Y_(N-i)) conj(w^i) / 2, Z'_i = E' + i O' and
+// Z'_(N-i) = conj(E') + i conj(O').
+__device__ __forceinline__ void real_pair(const LargeArgs& a, double B, double beta,
+                                          float inv_n, int64_t N, int64_t i, float2 z,
+                                          float2 zm, float2* zi, float2* zmi) {
+  const float2 e = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+  const float2 o = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+  const float2 w = tw2_fwd(a, i);
+  const float2 wo = cmul(w, o);
+  float2 yp = cmul(cadd(e, wo), band_chirp(a, B, beta, i, inv_n));
+  float2 ym = cmul(make_float2(e.x - wo.x, wo.y - e.y), band_chirp(a, B, beta, N - i, inv_n));
+  if (i == 0) {  // DC and Nyquist of a real series are real
+    yp.y = 0.f;
+    ym.y = 0.f;
+  }
+  const float2 e2 = make_float2(0.5f * (yp.x + ym.x), 0.5f * (yp.y - ym.y));
+  const float2 o2 = cmul(make_float2(0.5f * (yp.x - ym.x), 0.5f * (yp.y + ym.y)),
+                         make_float2(w.x, -w.y));
+  *zi = make_float2(e2.x - o2.y, e2.y + o2.x);
+  *zmi = make_float2(e2.x + o2.y, o2.x - e2.y);
+}
+
+template <class SR, int G>
+__global__ __launch_bounds__(SR::T * G) void rows_real_kernel(const LargeArgs a) {
+  constexpr int L = SR::N, STRIDE = pair_stride<SR::N, SR::lds_floats()>();
+  __shared__ __align__(16) float lds[G * STRIDE];
+  constexpr int R0 = SR::rad_f(0), B0 = L / (R0 * SR::T);
+  constexpr int RL = SR::rad_f(SR::NP - 1), BL = L / (RL * SR::T);
+  const int t = threadIdx.x, g = t / SR::T, tl = t % SR::T;
+  // N2/2 row pairs per item, G/2 per workgroup: (0, N2/2), then (k, N2 - k)
+  const int ngrp = a.N2 / G;
+  const int64_t item = a.item0 + blockIdx.x / ngrp;
+  const int pair = (blockIdx.x % ngrp) * (G / 2) + (g >> 1);
+  const int side = g & 1;
+  const int k2 = pair == 0 ? side * (a.N2 / 2) : (side ? a.N2 - pair : pair);
+  const int64_t N = (int64_t)a.N1 * a.N2;
+  float2* row = a.S + (item - a.item0) * N + (int64_t)k2 * a.N1;
+  float2 v[SR::E];
+#pragma unroll
+  for (int b = 0; b < B0; ++b)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) v[b * R0 + r] = row[tl + SR::T * b + r * (L / R0)];
+  float* my = lds + g * STRIDE;
+  fft_forward<SR>(v, my, a.twr, tl);
+  __syncthreads();  // every read of the last exchange is done
+  float2* mine = (float2*)my;
+#pragma unroll
+  for (int b = 0; b < BL; ++b)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) mine[tl + SR::T * b + r * (L / RL)] = v[b * RL + r];
+  __syncthreads();
+  // Each mirror pair is filtered once, in place.  A row pair (k, N2 - k):
+  // bin k1 of row k pairs with N1 - 1 - k1 of row N2 - k; side s takes
+  // k1 in [s N1/2, (s+1) N1/2).  Row 0 pairs k1 with -k1 mod N1 (k1 = 0 and
+  // N1/2 with themselves); row N2/2 pairs k1 with N1 - 1 - k1.
+  float2* rowA = (float2*)(lds + (pair == 0 ? g : (g & ~1)) * STRIDE);
+  float2* rowB = (float2*)(lds + (pair == 0 ? g : (g | 1)) * STRIDE);
+  const int kA = pair == 0 ? k2 : pair;
+  const double dfn = a.bw / (double)N;
+  const double B = a.dconst * a.dm * dfn * dfn / (a.f_lo * a.f_lo * a.f_lo);
+  const double beta = dfn / a.f_lo;
+  const float inv_n = 1.0f / (float)N;
+  constexpr int half = L / 2;
+#pragma unroll 2
+  for (int p = tl; p < half; p += SR::T) {
+    int k1, k1m;
+    if (pair != 0) {
+      k1 = p + side * half;
+      k1m = L - 1 - k1;
+    } else if (side == 0) {
+      k1 = p;
+      k1m = (L - p) & (L - 1);
+    } else {
+      k1 = p;
+      k1m = L - 1 - p;
+    }
+    float2 zi, zmi;
+    real_pair(a, B, beta, inv_n, N, kA + (int64_t)a.N2 * k1, rowA[k1], rowB[k1m], &zi, &zmi);
+    rowA[k1] = zi;
+    rowB[k1m] = zmi;
+    if (pair == 0 && side == 0 && p == 0) {
+      real_pair(a, B, beta, inv_n, N, (int64_t)a.N2 * half, rowA[half], rowA[half], &zi, &zmi);
+      rowA[half] = zi;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < BL; ++b)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) v[b * RL + r] = mine[tl + SR::T * b + r * (L / RL)];
+  fft_inverse<SR>(v, my, a.twr, tl);  // its first exchange waits for the reads above
+#pragma unroll
+  for (int b = 0; b < B0; ++b)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int n1 = tl + SR::T * b + r * (L / R0);
+      const float2 w = tw4_fwd(a, (int64_t)n1 * k2);
+      row[n1] = cmul(v[b * R0 + r], make_float2(w.x, -w.y));
+    }
+}
+
+// Inverse transform of recorded spectra (Sec. 2.3, 3.1).  Record s holds
+// bins 0 .. L-1 of a 2L-point real FFT as int8 (re, im); the Nyquist bin is
+// not recorded and the DC bin's imaginary part is dropped.  Packed as above
+// (with w = exp(-i pi / L) and X_L = 0), the record becomes L complex values
+// Z_c = (E_c + i O_c), whose inverse DFT (times 1/L) is the record's 2L real
+// samples in pairs.  A group of SC::T lanes handles one record; G records
+// per workgroup.
+template <class SC, int G>
+__global__ __launch_bounds__(SC::T * G) void gsb_inverse_kernel(
+    const uint32_t* __restrict__ spec, float2* __restrict__ out,
+    const float2* __restrict__ pre, const float2* __restrict__ tw, int64_t nspec) {
+  constexpr int L = SC::N, STRIDE = pair_stride<SC::N, SC::lds_floats()>();
+  static_assert(STRIDE % 4 == 0, "records are staged as float4");
+  __shared__ __align__(16) float lds[G * STRIDE];
+  constexpr int RI = SC::rad_i(0), BI = L / (RI * SC::T);
+  constexpr int R0 = SC::rad_f(0), B0 = L / (R0 * SC::T);
+  const int t = threadIdx.x, g = t / SC::T, tl = t % SC::T;
+  const int64_t s = (int64_t)blockIdx.x * G + g;
+  const bool live = s < nspec;
+  float* my = lds + g * STRIDE;
+  float4* X4 = (float4*)my;
+  for (int c2 = tl; c2 < L / 2; c2 += SC::T) {
+    const uint32_t w = live ? spec[s * (L / 2) + c2] : 0u;
+    X4[c2] = make_float4((float)(int8_t)(w & 0xffu), (float)(int8_t)((w >> 8) & 0xffu),
+                         (float)(int8_t)((w >> 16) & 0xffu), (float)(int8_t)(w >> 24));
+  }
+  __syncthreads();
+  const float2* X = (const float2*)my;
+  const float sc = 0.5f / (float)L;
+  float2 v[SC::E];
+#pragma unroll
+  for (int b = 0; b < BI; ++b)
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      const int c = tl + SC::T * b + r * (L / RI);
+      float2 x = X[c];
+      float2 m = make_float2(0.f, 0.f);
+      if (c == 0)
+        x.y = 0.f;
+      else
+        m = X[L - c];
+      const float2 e = make_float2(x.x + m.x, x.y - m.y);                    // 2 E_c
+      const float2 o = cmul(make_float2(x.x - m.x, x.y + m.y), pre[c]);      // 2 O_c
+      v[b * RI + r] = make_float2(sc * (e.x - o.y), sc * (e.y + o.x));
+    }
+  fft_inverse<SC>(v, my, tw, tl);  // its first exchange waits for the reads above
+  if (live) {
+#pragma unroll
+    for (int b = 0; b < B0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) out[s * L + tl + SC::T * b + r * (L / R0)] = v[b * R0 + r];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 template <int LGN>
@@ -313,6 +513,133 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
   hipLaunchKernelGGL(integrate_kernel, dim3((unsigned)nb, (unsigned)p.nchan), dim3(256), 0, st,
                      pbuf, P, p.nsamp, p.t_int, p.n_int);
   return (int)hipGetLastError();
+}
+
+// exp(+i pi c / L), c < L: the post-twiddle of the packed real inverse.
+template <int LG>
+static std::vector<float2> make_gsb_pre() {
+  const int L = 1 << LG;
+  std::vector<float2> t(L);
+  for (int c = 0; c < L; ++c) {
+    const double ang = M_PI * (double)c / (double)L;
+    t[c] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  return t;
+}
+
+bool gsb_supported(int nchan) { return nchan >= 128 && nchan <= 2048 && (nchan & (nchan - 1)) == 0; }
+
+template <int LG>
+static int launch_gsb_t(const void* spec, int64_t nspec, float* series, void* stream) {
+  using SC = typename SubSched<(1 << LG)>::type;
+  constexpr int G = SC::T >= 256 ? 1 : 256 / SC::T;
+  const float2* tw = nullptr;
+  const float2* pre = nullptr;
+  int e = twiddles_of<SC>(&tw);
+  if (!e) e = cached_table((std::string("gsbpre") + std::to_string(LG)).c_str(),
+                           &make_gsb_pre<LG>, &pre);
+  if (e) return e;
+  const int64_t nb = (nspec + G - 1) / G;
+  if (nb < 1 || nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL((gsb_inverse_kernel<SC, G>), dim3((unsigned)nb), dim3(SC::T * G), 0,
+                     (hipStream_t)stream, (const uint32_t*)spec, (float2*)series, pre, tw, nspec);
+  return (int)hipGetLastError();
+}
+
+int launch_gsb_inverse(const void* spec, int64_t nspec, int32_t nchan, float* series,
+                       void* stream) {
+  switch (nchan) {
+    case 128: return launch_gsb_t<7>(spec, nspec, series, stream);
+    case 256: return launch_gsb_t<8>(spec, nspec, series, stream);
+    case 512: return launch_gsb_t<9>(spec, nspec, series, stream);
+    case 1024: return launch_gsb_t<10>(spec, nspec, series, stream);
+    case 2048: return launch_gsb_t<11>(spec, nspec, series, stream);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+int64_t fullband_chunk_blocks(const FullbandPlan& f) {
+  const int64_t per = std::max<int64_t>(1, kChunkBytes / ((int64_t)(f.N / 2) * 8));
+  return std::min(f.nblocks, per);
+}
+
+template <int LGN>
+static int launch_fullband_t(const FullbandPlan& f, const float* series, float2* S, float* pbuf,
+                             float* I, float* vout, void* stream) {
+  constexpr int N2 = 1 << (LGN / 2), N1 = 1 << (LGN - LGN / 2);
+  using SC = typename SubSched<N2>::type;
+  using SR = typename SubSched<N1>::type;
+  constexpr int GC = SC::T * 16 <= 1024 ? 16 : 8;
+  constexpr int GR = (SR::T * 8 <= 1024 && 8 * 2 * N1 * 4 <= 65536) ? 8 : 4;
+  static_assert(N1 % GC == 0 && N2 % GR == 0 && GR % 2 == 0,
+                "group sizes must tile the transform in row pairs");
+  LargeArgs a{};
+  int e = twiddles_of<SC>(&a.twc);
+  if (!e) e = twiddles_of<SR>(&a.twr);
+  if (!e) e = cached_table((std::string("fourstep") + std::to_string(LGN)).c_str(),
+                           &make_fourstep<LGN>, &a.tw4);
+  if (!e) e = cached_table((std::string("fourstep") + std::to_string(LGN + 1)).c_str(),
+                           &make_fourstep<LGN + 1>, &a.tw2);
+  if (e) return e;
+  a.x = series;
+  a.S = S;
+  a.p = pbuf;
+  a.vout = (float2*)vout;
+  a.nsamp = f.nsamp / 2;
+  a.nblocks = f.nblocks;
+  a.nchan = 1;
+  a.N1 = N1;
+  a.N2 = N2;
+  a.M = f.M / 2;
+  a.nfront = f.nfront / 2;
+  a.sl = (LGN + 1) / 2;
+  a.sl2 = (LGN + 2) / 2;
+  a.phase_mode = CDD_PHASE_FP64_REDUCED;
+  a.taper = f.taper;
+  a.exact_div = 1;
+  a.f_lo = f.f_lo;
+  a.bw = f.bw;
+  a.df = f.bw;
+  a.dconst = f.dconst;
+  a.dm = f.dm;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t chunk = fullband_chunk_blocks(f);
+  for (int64_t i0 = 0; i0 < f.nblocks; i0 += chunk) {
+    const int64_t q = std::min(chunk, f.nblocks - i0);
+    a.item0 = i0;
+    const int64_t gc = q * (N1 / GC), gr = q * (N2 / GR);
+    if (gc > 0x7fffffffLL || gr > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL((cols_fwd_kernel<SC, GC, CDD_CF32>), dim3((unsigned)gc), dim3(SC::T * GC),
+                       0, st, a);
+    hipLaunchKernelGGL((rows_real_kernel<SR, GR>), dim3((unsigned)gr), dim3(SR::T * GR), 0, st,
+                       a);
+    hipLaunchKernelGGL((cols_inv_kernel<SC, GC>), dim3((unsigned)gc), dim3(SC::T * GC), 0, st,
+                       a);
+    e = (int)hipGetLastError();
+    if (e) return e;
+  }
+  const int64_t nb = (f.t_int + 255) / 256;
+  if (nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+  if (nb > 0)
+    hipLaunchKernelGGL(integrate_kernel, dim3((unsigned)nb, 1u), dim3(256), 0, st, pbuf, I,
+                       f.nsamp / 2, f.t_int, f.n_int / 2);
+  return (int)hipGetLastError();
+}
+
+int launch_fullband(const FullbandPlan& f, const float* series, void* Sv, float* pbuf,
+                    float* I, float* vout, void* stream) {
+  float2* S = (float2*)Sv;
+  switch (f.N) {
+    case 1 << 16: return launch_fullband_t<15>(f, series, S, pbuf, I, vout, stream);
+    case 1 << 17: return launch_fullband_t<16>(f, series, S, pbuf, I, vout, stream);
+    case 1 << 18: return launch_fullband_t<17>(f, series, S, pbuf, I, vout, stream);
+    case 1 << 19: return launch_fullband_t<18>(f, series, S, pbuf, I, vout, stream);
+    case 1 << 20: return launch_fullband_t<19>(f, series, S, pbuf, I, vout, stream);
+    case 1 << 21: return launch_fullband_t<20>(f, series, S, pbuf, I, vout, stream);
+    case 1 << 22: return launch_fullband_t<21>(f, series, S, pbuf, I, vout, stream);
+    case 1 << 23: return launch_fullband_t<22>(f, series, S, pbuf, I, vout, stream);
+  }
+  return (int)hipErrorInvalidValue;
 }
 
 int exact_division_needed(const BeamPlan& p, double dm_abs_max);

@@ -207,3 +207,33 @@ def test_plan_create_validates_beams():
     assert (info.fft_len, info.overlap, info.nfront) == (N, L, nfront)
     assert cdd.lib.cdd_plan_info_get(h, 1, ctypes.byref(info)) == -1
     cdd.lib.cdd_plan_destroy(h)
+
+
+@pytest.mark.parametrize("args", [
+    (300, 512, 610.0, 16.0, 0.3, 2), (16384, 512, 610.0, 16.0, 10.0, 16),
+    (1000, 1024, 325.0, 32.0, -2.0, 8), (500, 256, 610.0, 16.0, 0.0, 2),
+    (300, 512, 610.0, 16.0, 0.3, 6), (4000, 2048, 325.0, 32.0, 3.0, 4),
+])
+def test_fullband_planner_matches_oracle_rules(args):
+    nspec, nchan, fcen, bw, dm, n_int = args
+    q = _lib().fullband_query(nspec, nchan, fcen, bw, dm, n_int)
+    N, L, nf = O.fullband_plan(fcen - bw / 2, bw, dm, n_int)
+    assert (q["fft_len"], q["overlap"], q["nfront"]) == (N, L, nf)
+    assert q["nsamp"] == nspec * 2 * nchan and q["step"] == N - L
+    assert q["nblocks"] == -(-q["nsamp"] // (N - L)) and q["t_int"] == q["nsamp"] // n_int
+
+
+@pytest.mark.parametrize("args,kw,frag", [
+    ((300, 500, 610.0, 16.0, 0.3, 2), {}, "nchan"),
+    ((300, 512, 610.0, 16.0, 0.3, 3), {}, "n_int"),
+    ((0, 512, 610.0, 16.0, 0.3, 2), {}, "nspec"),
+    ((300, 512, 610.0, 16.0, 0.3, 2), {"fft_len": 1 << 15}, "fft_len"),
+    ((300, 512, 610.0, 16.0, 3000.0, 2), {}, "DM too large"),
+    ((300, 512, 610.0, 16.0, 0.3, 2), {"phase_mode": 1}, "FP64"),
+    ((300, 512, 10.0, 30.0, 0.3, 2), {}, "band"),
+])
+def test_fullband_invalid_arguments_are_rejected(args, kw, frag):
+    cdd = _lib()
+    with pytest.raises(cdd.CddError) as e:
+        cdd.fullband_query(*args, **kw)
+    assert frag in str(e.value)
