@@ -38,6 +38,7 @@ WORKLOADS = {
     3: "filterbank_200MHz_4096ch_2s_int8_N8192_nint4_dm120",
     4: "multibeam_16-32-32-200MHz_512-512-1024-4096ch_1-4s_int8_nint4_autotuned",
     5: "serving_8streams_16-32-200MHz_int8_dm5-300",
+    6: "fullband_16MHz_610MHz_512bin_records_2^24_real_N2^19_nint16_dm10",
 }
 
 # Serving mix: (bandwidth MHz, channels, centre MHz) per stream.
@@ -142,6 +143,50 @@ def cpu_baseline_all_cores(v, b, seconds: float, per_core_rate: float):
     return {"value": done / dt / 1e6, "unit": "Msamples/s", "cores": cores, "kind": "oracle",
             "sample": "%d channel passes over the %d channels, one per task over %d "
                       "processes, %.1f s" % (n, b.nchan, cores, dt)}
+
+
+def fullband(cdd, torch, steps: int, warmup: int):
+    """The unchannelised mode on a 16 MHz band at 610 MHz (GSB-style records
+    of 512 bins from 1024-point real FFTs, 16384 records = 2^24 real samples,
+    0.52 s at 32 Msamples/s), DM 10: inverse transform of the records, then
+    2^19-point real overlap-save transforms over the band, y^2 and 16-sample
+    integration.  Seeded int8 noise records, resident in HBM."""
+    import synth
+    nspec, nchan, fcen, bw, dm, n_int = 16384, 512, 610.0, 16.0, 10.0, 16
+    sp = torch.from_numpy(synth.noise_int8(synth.rng_for(6), nspec, nchan, 20.0)).cuda()
+    out = cdd.fullband(sp, fcen, bw, dm, n_int)
+    info = out["info"]
+    for _ in range(warmup):
+        cdd.fullband(sp, fcen, bw, dm, n_int, out=out)
+    torch.cuda.synchronize()
+    cdd.profile_read()
+    cdd.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cdd.fullband(sp, fcen, bw, dm, n_int, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    cdd.profile_enable(False)
+    st = cdd.profile_read()
+    T = info["nsamp"]
+    r = info["fft_len"] / info["step"]
+    # bytes the passes must move per real sample: records in (1) and series out
+    # (4); column, row and column passes each read and write the 8-byte packed
+    # spectra of 2 samples, times the N/M re-transform of the overlap; |y|^2 of
+    # each pair (2) written and read back; I written
+    design = 5.0 + 20.0 * r + 4.0 + 4.0 / n_int
+    inv_ms = st["transpose"][0] / max(st["transpose"][1], 1)
+    long_ms = st["block"][0] / max(st["block"][1], 1)
+    return {"workload": WORKLOADS[6], "plan": {k: info[k] for k in ("fft_len", "overlap",
+                                                                   "nfront", "nblocks")},
+            "ms_per_call": round(dt * 1e3, 4),
+            "msamples_per_s": round(T / dt / 1e6, 1),
+            "x_realtime": round(T / (2 * bw) / 1e6 / dt, 1),
+            "stages_ms": {"inverse_transform": round(inv_ms, 4),
+                          "long_transforms": round(long_ms, 4)},
+            "design_bytes_per_sample": round(design, 2),
+            "design_hbm_frac": round(design * T / dt / 1e9 / PEAK_HBM_GBS, 4),
+            "inverse_transform_gbs": round(5.0 * T / (inv_ms * 1e-3) / 1e9, 1)}
 
 
 def multibeam(cdd, torch, reps: int = 3):
@@ -304,6 +349,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dm-trials", action="store_true")
+    ap.add_argument("--no-fullband", action="store_true")
     ap.add_argument("--taper", default="none", choices=["none", "hann", "welch"],
                     help="taper of the chirp function over each channel")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving run length (config 5)")
@@ -346,6 +392,16 @@ def main():
                "scaling": "weak", "vs_baseline": None, "dtype": "f32",
                "data": "synthetic (seeded int8 noise)", "config": {"workload": WORKLOADS[4]},
                "multibeam": mb}
+        print(json.dumps(res), flush=True)
+        return
+    if args.config == 6:
+        fb = fullband(cdd, torch, args.steps, args.warmup)
+        res = {"metric": "Msamples/s dedispersed (full band, real samples)",
+               "value": fb["msamples_per_s"], "unit": "Msamples/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": fb["ms_per_call"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f32", "data": "synthetic (seeded int8 noise records)",
+               "config": {"workload": WORKLOADS[6]}, "fullband": fb}
         print(json.dumps(res), flush=True)
         return
     if args.config == 5:
@@ -440,6 +496,8 @@ def main():
                                   "coherent_cost_ratio": round(ms / mi, 2)}
     if args.config == 2 and not args.no_dm_trials:
         res["dm_trials"] = dm_trials(cdd, torch, vd, b, info, taper=args.taper)
+    if args.config == 2 and not args.no_fullband:
+        res["fullband"] = fullband(cdd, torch, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(v, b, args.cpu_seconds)
         res["cpu_baseline_all_cores"] = all_cores

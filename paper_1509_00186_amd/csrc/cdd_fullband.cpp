@@ -133,7 +133,7 @@ static cdd_status make_fullband_plan(int64_t nspec, int32_t nchan, double f_cent
 }
 
 struct FullbandWs {
-  size_t x_off = 0, s_off = 0, pb_off = 0, total = 0;
+  size_t x_off = 0, s_off = 0, pb_off = 0, h_off = 0, total = 0;
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -147,6 +147,8 @@ static FullbandWs fullband_ws(const FullbandPlan& f) {
   off = align256(off + (size_t)fullband_chunk_blocks(f) * (size_t)(f.N / 2) * 8);
   w.pb_off = off;
   off = align256(off + (size_t)(f.nsamp / 2) * sizeof(float));
+  w.h_off = off;
+  off = align256(off + (size_t)(f.N / 2 + 1) * 8);
   w.total = off;
   return w;
 }
@@ -228,8 +230,8 @@ extern "C" cdd_status cdd_fullband_dedisperse(const void* spectra, int64_t nspec
     if (!e) e = stage_end(kStageTranspose, stream, tok);
     if (e) return device_error("inverse-transform launch", e);
     e = stage_begin(stream, &tok);
-    if (!e) e = launch_fullband(f, x, ws + lay.s_off, (float*)(ws + lay.pb_off), intensity,
-                                volt_out, stream);
+    if (!e) e = launch_fullband(f, x, ws + lay.s_off, (float*)(ws + lay.pb_off), ws + lay.h_off,
+                                intensity, volt_out, stream);
     if (!e) e = stage_end(kStageBlock, stream, tok);
     if (e) return device_error("full-band transform launch", e);
     clear_error();

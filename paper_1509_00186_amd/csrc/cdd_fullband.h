@@ -33,8 +33,9 @@ int launch_gsb_inverse(const void* spec, int64_t nspec, int32_t nchan, float* se
 int64_t fullband_chunk_blocks(const FullbandPlan& f);  // blocks per chunk of spectra
 // Overlap-save of the real series with the band chirp, y^2 integrated into
 // intensity [t_int]; vout (nullable) receives the dedispersed series [nsamp].
-// S holds fullband_chunk_blocks * N/2 complex values, pbuf nsamp/2 floats.
-int launch_fullband(const FullbandPlan& f, const float* series, void* S, float* pbuf,
+// S holds fullband_chunk_blocks * N/2 complex values, pbuf nsamp/2 floats,
+// H the call's chirp function, N/2 + 1 complex values.
+int launch_fullband(const FullbandPlan& f, const float* series, void* S, float* pbuf, void* H,
                     float* intensity, float* vout, void* stream);
 
 }  // namespace cdd

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "cdd_fft.h"
@@ -48,10 +49,12 @@ struct LargeArgs {
   int64_t nsamp, nblocks, item0;
   int32_t nchan, N1, N2, M, nfront, sl, phase_mode, exact_div, taper;
   double f_lo, df, dconst, dm;
-  // full-band mode: W_{2N}^m = tw2[m & (2^sl2-1)] * tw2[2^sl2 + (m >> sl2)], band width
+  // full-band mode: W_{2N}^m = tw2[m & (2^sl2-1)] * tw2[2^sl2 + (m >> sl2)], band width,
+  // chirp function per real-spectrum bin (N + 1 entries)
   const float2* tw2;
   int32_t sl2;
   double bw;
+  const float2* hb;
 };
 
 __device__ __forceinline__ float2 tw4_fwd(const LargeArgs& a, int64_t m) {
@@ -217,17 +220,50 @@ __global__ __launch_bounds__(SC::T * G) void cols_inv_kernel(const LargeArgs a) 
     }
 }
 
-// P[c][u] = sum_{r < n_int} p[c][u n_int + r], grid (u blocks, channels)
+// P[c][u] = sum_{r < n_int} p[c][u n_int + r] in ascending r, grid (u
+// blocks, channels).  V consecutive samples per load (V divides n_int and
+// the channel stride, so every vector load is aligned).
+template <int V>
 __global__ __launch_bounds__(256) void integrate_kernel(const float* __restrict__ p,
                                                         float* __restrict__ P, int64_t nsamp,
                                                         int64_t t_int, int32_t n_int) {
+  using VT = typename std::conditional<V == 4, float4, typename std::conditional<
+                                                         V == 2, float2, float>::type>::type;
   const int c = blockIdx.y;
   const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (u >= t_int) return;
-  const float* pc = p + (int64_t)c * nsamp + u * n_int;
+  const VT* pc = (const VT*)(p + (int64_t)c * nsamp + u * n_int);
   float s = 0.f;
-  for (int r = 0; r < n_int; ++r) s += pc[r];
+  for (int r = 0; r < n_int / V; ++r) {
+    const VT x = pc[r];
+    if constexpr (V == 4) {
+      s += x.x;
+      s += x.y;
+      s += x.z;
+      s += x.w;
+    } else if constexpr (V == 2) {
+      s += x.x;
+      s += x.y;
+    } else {
+      s += x;
+    }
+  }
   P[(int64_t)c * t_int + u] = s;
+}
+
+static int launch_integrate(const float* p, float* P, int64_t nsamp, int64_t t_int,
+                            int32_t n_int, int32_t nchan, hipStream_t st) {
+  const int64_t nb = (t_int + 255) / 256;
+  if (nb > 0x7fffffffLL || nchan > 65535) return (int)hipErrorInvalidValue;
+  if (nb == 0) return 0;
+  const dim3 grid((unsigned)nb, (unsigned)nchan);
+  if (n_int % 4 == 0 && (nchan == 1 || nsamp % 4 == 0))
+    hipLaunchKernelGGL(integrate_kernel<4>, grid, dim3(256), 0, st, p, P, nsamp, t_int, n_int);
+  else if (n_int % 2 == 0 && (nchan == 1 || nsamp % 2 == 0))
+    hipLaunchKernelGGL(integrate_kernel<2>, grid, dim3(256), 0, st, p, P, nsamp, t_int, n_int);
+  else
+    hipLaunchKernelGGL(integrate_kernel<1>, grid, dim3(256), 0, st, p, P, nsamp, t_int, n_int);
+  return (int)hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -262,6 +298,20 @@ __device__ __forceinline__ float2 band_chirp(const LargeArgs& a, double B, doubl
   return make_float2(h.x * g, h.y * g);
 }
 
+// The chirp function of one call for every real-spectrum bin, shared by all
+// blocks of the record, in the order the row pass reads it: entry
+// k2 N1 + k1 holds bin j = k2 + N2 k1 (j < N), entry N the Nyquist bin.
+__global__ __launch_bounds__(256) void band_chirp_table_kernel(LargeArgs a, int64_t N,
+                                                               float2* __restrict__ hb) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx > N) return;
+  const int64_t j = idx == N ? N : idx / a.N1 + (int64_t)a.N2 * (idx % a.N1);
+  const double dfn = a.bw / (double)N;
+  const double B = a.dconst * a.dm * dfn * dfn / (a.f_lo * a.f_lo * a.f_lo);
+  const double beta = dfn / a.f_lo;
+  hb[idx] = band_chirp(a, B, beta, j, 1.0f / (float)N);
+}
+
 template <int L, int LDSF>
 constexpr int pair_stride() {
   return 2 * L > LDSF + 1 ? 2 * L : ((LDSF + 1 + 3) & ~3);
@@ -271,15 +321,14 @@ constexpr int pair_stride() {
 // the filtered Z'_i and Z'_(N-i).  With E' = (Y_i + conj Y_(N-i)) / 2 and
 // O' = (Y_i - conj Y_(N-i)) conj(w^i) / 2, Z'_i = E' + i O' and
 // Z'_(N-i) = conj(E') + i conj(O').
-__device__ __forceinline__ void real_pair(const LargeArgs& a, double B, double beta,
-                                          float inv_n, int64_t N, int64_t i, float2 z,
-                                          float2 zm, float2* zi, float2* zmi) {
+__device__ __forceinline__ void real_pair(const LargeArgs& a, int64_t i, float2 hp, float2 hm,
+                                          float2 z, float2 zm, float2* zi, float2* zmi) {
   const float2 e = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
   const float2 o = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
   const float2 w = tw2_fwd(a, i);
   const float2 wo = cmul(w, o);
-  float2 yp = cmul(cadd(e, wo), band_chirp(a, B, beta, i, inv_n));
-  float2 ym = cmul(make_float2(e.x - wo.x, wo.y - e.y), band_chirp(a, B, beta, N - i, inv_n));
+  float2 yp = cmul(cadd(e, wo), hp);
+  float2 ym = cmul(make_float2(e.x - wo.x, wo.y - e.y), hm);
   if (i == 0) {  // DC and Nyquist of a real series are real
     yp.y = 0.f;
     ym.y = 0.f;
@@ -327,10 +376,10 @@ __global__ __launch_bounds__(SR::T * G) void rows_real_kernel(const LargeArgs a)
   float2* rowA = (float2*)(lds + (pair == 0 ? g : (g & ~1)) * STRIDE);
   float2* rowB = (float2*)(lds + (pair == 0 ? g : (g | 1)) * STRIDE);
   const int kA = pair == 0 ? k2 : pair;
-  const double dfn = a.bw / (double)N;
-  const double B = a.dconst * a.dm * dfn * dfn / (a.f_lo * a.f_lo * a.f_lo);
-  const double beta = dfn / a.f_lo;
-  const float inv_n = 1.0f / (float)N;
+  const int kB = pair == 0 ? k2 : a.N2 - pair;
+  const float2* hA = a.hb + (int64_t)kA * L;  // chirp of row kA's bins, then row kB's
+  const float2* hB = a.hb + (int64_t)kB * L;
+  const float2 hnyq = a.hb[N];
   constexpr int half = L / 2;
 #pragma unroll 2
   for (int p = tl; p < half; p += SR::T) {
@@ -346,11 +395,12 @@ __global__ __launch_bounds__(SR::T * G) void rows_real_kernel(const LargeArgs a)
       k1m = L - 1 - p;
     }
     float2 zi, zmi;
-    real_pair(a, B, beta, inv_n, N, kA + (int64_t)a.N2 * k1, rowA[k1], rowB[k1m], &zi, &zmi);
+    const int64_t i = kA + (int64_t)a.N2 * k1;
+    real_pair(a, i, hA[k1], i == 0 ? hnyq : hB[k1m], rowA[k1], rowB[k1m], &zi, &zmi);
     rowA[k1] = zi;
     rowB[k1m] = zmi;
     if (pair == 0 && side == 0 && p == 0) {
-      real_pair(a, B, beta, inv_n, N, (int64_t)a.N2 * half, rowA[half], rowA[half], &zi, &zmi);
+      real_pair(a, (int64_t)a.N2 * half, hA[half], hA[half], rowA[half], rowA[half], &zi, &zmi);
       rowA[half] = zi;
     }
   }
@@ -508,11 +558,7 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
     e = (int)hipGetLastError();
     if (e) return e;
   }
-  const int64_t nb = (p.t_int + 255) / 256;
-  if (nb > 0x7fffffffLL || p.nchan > 65535) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(integrate_kernel, dim3((unsigned)nb, (unsigned)p.nchan), dim3(256), 0, st,
-                     pbuf, P, p.nsamp, p.t_int, p.n_int);
-  return (int)hipGetLastError();
+  return launch_integrate(pbuf, P, p.nsamp, p.t_int, p.n_int, p.nchan, st);
 }
 
 // exp(+i pi c / L), c < L: the post-twiddle of the packed real inverse.
@@ -565,7 +611,7 @@ int64_t fullband_chunk_blocks(const FullbandPlan& f) {
 
 template <int LGN>
 static int launch_fullband_t(const FullbandPlan& f, const float* series, float2* S, float* pbuf,
-                             float* I, float* vout, void* stream) {
+                             float2* hb, float* I, float* vout, void* stream) {
   constexpr int N2 = 1 << (LGN / 2), N1 = 1 << (LGN - LGN / 2);
   using SC = typename SubSched<N2>::type;
   using SR = typename SubSched<N1>::type;
@@ -602,7 +648,11 @@ static int launch_fullband_t(const FullbandPlan& f, const float* series, float2*
   a.df = f.bw;
   a.dconst = f.dconst;
   a.dm = f.dm;
+  a.hb = hb;
   hipStream_t st = (hipStream_t)stream;
+  constexpr int64_t NP = (int64_t)1 << LGN;
+  hipLaunchKernelGGL(band_chirp_table_kernel, dim3((unsigned)((NP + 256) / 256)), dim3(256), 0,
+                     st, a, NP, hb);
   const int64_t chunk = fullband_chunk_blocks(f);
   for (int64_t i0 = 0; i0 < f.nblocks; i0 += chunk) {
     const int64_t q = std::min(chunk, f.nblocks - i0);
@@ -618,26 +668,22 @@ static int launch_fullband_t(const FullbandPlan& f, const float* series, float2*
     e = (int)hipGetLastError();
     if (e) return e;
   }
-  const int64_t nb = (f.t_int + 255) / 256;
-  if (nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
-  if (nb > 0)
-    hipLaunchKernelGGL(integrate_kernel, dim3((unsigned)nb, 1u), dim3(256), 0, st, pbuf, I,
-                       f.nsamp / 2, f.t_int, f.n_int / 2);
-  return (int)hipGetLastError();
+  return launch_integrate(pbuf, I, f.nsamp / 2, f.t_int, f.n_int / 2, 1, st);
 }
 
 int launch_fullband(const FullbandPlan& f, const float* series, void* Sv, float* pbuf,
-                    float* I, float* vout, void* stream) {
+                    void* Hv, float* I, float* vout, void* stream) {
   float2* S = (float2*)Sv;
+  float2* H = (float2*)Hv;
   switch (f.N) {
-    case 1 << 16: return launch_fullband_t<15>(f, series, S, pbuf, I, vout, stream);
-    case 1 << 17: return launch_fullband_t<16>(f, series, S, pbuf, I, vout, stream);
-    case 1 << 18: return launch_fullband_t<17>(f, series, S, pbuf, I, vout, stream);
-    case 1 << 19: return launch_fullband_t<18>(f, series, S, pbuf, I, vout, stream);
-    case 1 << 20: return launch_fullband_t<19>(f, series, S, pbuf, I, vout, stream);
-    case 1 << 21: return launch_fullband_t<20>(f, series, S, pbuf, I, vout, stream);
-    case 1 << 22: return launch_fullband_t<21>(f, series, S, pbuf, I, vout, stream);
-    case 1 << 23: return launch_fullband_t<22>(f, series, S, pbuf, I, vout, stream);
+    case 1 << 16: return launch_fullband_t<15>(f, series, S, pbuf, H, I, vout, stream);
+    case 1 << 17: return launch_fullband_t<16>(f, series, S, pbuf, H, I, vout, stream);
+    case 1 << 18: return launch_fullband_t<17>(f, series, S, pbuf, H, I, vout, stream);
+    case 1 << 19: return launch_fullband_t<18>(f, series, S, pbuf, H, I, vout, stream);
+    case 1 << 20: return launch_fullband_t<19>(f, series, S, pbuf, H, I, vout, stream);
+    case 1 << 21: return launch_fullband_t<20>(f, series, S, pbuf, H, I, vout, stream);
+    case 1 << 22: return launch_fullband_t<21>(f, series, S, pbuf, H, I, vout, stream);
+    case 1 << 23: return launch_fullband_t<22>(f, series, S, pbuf, H, I, vout, stream);
   }
   return (int)hipErrorInvalidValue;
 }
