@@ -177,6 +177,17 @@ def fullband(cdd, torch, steps: int, warmup: int):
     design = 5.0 + 20.0 * r + 4.0 + 4.0 / n_int
     inv_ms = st["transpose"][0] / max(st["transpose"][1], 1)
     long_ms = st["block"][0] / max(st["block"][1], 1)
+    # longer transforms than the rule's minimum re-transform less overlap
+    by_len = {}
+    for lg in range(20, 24):
+        o2 = cdd.fullband(sp, fcen, bw, dm, n_int, fft_len=1 << lg)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            cdd.fullband(sp, fcen, bw, dm, n_int, fft_len=1 << lg, out=o2)
+        torch.cuda.synchronize()
+        by_len[str(1 << lg)] = round((time.perf_counter() - t1) / steps * 1e3, 4)
+        del o2
     return {"workload": WORKLOADS[6], "plan": {k: info[k] for k in ("fft_len", "overlap",
                                                                    "nfront", "nblocks")},
             "ms_per_call": round(dt * 1e3, 4),
@@ -186,7 +197,8 @@ def fullband(cdd, torch, steps: int, warmup: int):
                           "long_transforms": round(long_ms, 4)},
             "design_bytes_per_sample": round(design, 2),
             "design_hbm_frac": round(design * T / dt / 1e9 / PEAK_HBM_GBS, 4),
-            "inverse_transform_gbs": round(5.0 * T / (inv_ms * 1e-3) / 1e9, 1)}
+            "inverse_transform_gbs": round(5.0 * T / (inv_ms * 1e-3) / 1e9, 1),
+            "ms_per_call_by_fft_len": by_len}
 
 
 def multibeam(cdd, torch, reps: int = 3):
@@ -233,6 +245,38 @@ def multibeam(cdd, torch, reps: int = 3):
             "loop_msamples_per_s": round(samples / t_loop / 1e6, 1),
             "speedup": round(t_loop / t_plan, 3), "x_realtime": round(duration / t_plan, 1),
             "autotune_s": round(t_tune, 2), "rel_l2_plan_vs_loop": diff}
+
+
+def polarisations_and_fold(cdd, torch, vd, b, steps: int, ms_one: float):
+    """Two polarisation records of the workload (the second a seeded
+    permutation of the first in time) dedispersed in one call with their
+    intensities summed, then the aligned sum folded at the pulse period into
+    256 bins."""
+    g = torch.Generator(device="cpu").manual_seed(1509)
+    perm = torch.randperm(b.nsamp, generator=g).to(vd.device)
+    two = torch.stack([vd, vd[perm]]).contiguous()
+    o = cdd.dedisperse(two, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, npol=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cdd.dedisperse(two, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, npol=2, out=o)
+    torch.cuda.synchronize()
+    ms2 = (time.perf_counter() - t0) / steps * 1e3
+    period = b.period_s * 1e6 / (b.n_int / (b.bw / b.nchan))  # integrated samples
+    cdd.fold(o["I"], period, 0.0, 256)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prof, cnt = cdd.fold(o["I"], period, 0.0, 256)
+    torch.cuda.synchronize()
+    msf = (time.perf_counter() - t0) / steps * 1e3
+    del two
+    return {"npol2_ms_per_step": round(ms2, 4),
+            "npol2_msamples_per_s": round(2 * b.nchan * b.nsamp / (ms2 * 1e-3) / 1e6, 1),
+            "npol2_cost_vs_one": round(ms2 / ms_one, 3),
+            "fold_ms": round(msf, 4), "fold_bins": 256,
+            "fold_period_samples": round(period, 3),
+            "fold_counts_total": int(cnt.sum().item())}
 
 
 def dm_trials(cdd, torch, vd, b, info, reps: int = 3, taper: str = "none"):
@@ -496,6 +540,8 @@ def main():
                                   "coherent_cost_ratio": round(ms / mi, 2)}
     if args.config == 2 and not args.no_dm_trials:
         res["dm_trials"] = dm_trials(cdd, torch, vd, b, info, taper=args.taper)
+    if args.config == 2:
+        res["polarisations_and_fold"] = polarisations_and_fold(cdd, torch, vd, b, args.steps, ms)
     if args.config == 2 and not args.no_fullband:
         res["fullband"] = fullband(cdd, torch, args.steps, args.warmup)
     if not args.no_cpu_baseline:
