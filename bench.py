@@ -34,6 +34,7 @@ PEAK_HBM_GBS = 8000.0      # MI355X HBM3E (published)
 K_DM_US = 4.148808e9       # cold-plasma constant, only to synthesise the pulses
 
 WORKLOADS = {
+    1: "single_channel_16MHz_610MHz_cf32_2^23_N2^18_nint16_dm10_voltages_out",
     2: "filterbank_32MHz_512ch_4s_int8_N8192_nint4_dm67.9",
     3: "filterbank_200MHz_4096ch_2s_int8_N8192_nint4_dm120",
     4: "multibeam_16-32-32-200MHz_512-512-1024-4096ch_1-4s_int8_nint4_autotuned",
@@ -99,7 +100,7 @@ def cpu_baseline(v, b, seconds: float):
     after the last one)."""
     done, t0 = 0, time.perf_counter()
     n = 0
-    while time.perf_counter() - t0 < seconds and n < 8 * b.nchan:
+    while time.perf_counter() - t0 < seconds and n < max(8 * b.nchan, 64):
         done += _oracle_channel(_channel_task(v, b, n % b.nchan))
         n += 1
     dt = time.perf_counter() - t0
@@ -411,11 +412,12 @@ def main():
     # The host-side oracle on all cores runs first, in spawned worker
     # processes, before this process touches the GPU.
     pre, all_cores = None, None
-    if args.config in (2, 3) and not args.no_cpu_baseline and not args.calibrate_copy_mb:
+    if args.config in (1, 2, 3) and not args.no_cpu_baseline and not args.calibrate_copy_mb:
         pre = make_input(args.config)
         b0, v0 = pre
-        one = cpu_baseline(v0, b0, 2.0)
-        all_cores = cpu_baseline_all_cores(v0, b0, min(args.cpu_seconds, 8.0), one["value"])
+        if b0.nchan >= 16:
+            one = cpu_baseline(v0, b0, 2.0)
+            all_cores = cpu_baseline_all_cores(v0, b0, min(args.cpu_seconds, 8.0), one["value"])
 
     import torch
     if args.calibrate_copy_mb:
@@ -464,7 +466,7 @@ def main():
     b, v = pre if pre is not None else make_input(args.config)
     dev = torch.device("cuda:0")
     vd = torch.from_numpy(v).to(dev)
-    tk = dict(taper=args.taper)
+    tk = dict(taper=args.taper, want_voltages=args.config == 1)
     out = cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, **tk)   # allocate
     info = out["info"]
     torch.cuda.synchronize()
@@ -495,7 +497,8 @@ def main():
     flops = b.nchan * info["nblocks"] * block_flops(info["fft_len"], info["step"]) / per_step
     achieved = flops / (blk_avg * 1e-3) / 1e12
     traffic = measured_traffic("block_kernel", WORKLOADS[args.config])
-    alg_bytes = (b.nchan * b.nsamp * 2 + b.nchan * info["t_int"] * 4) / per_step
+    in_bytes = 2 if b.int8 else 8
+    alg_bytes = (b.nchan * b.nsamp * in_bytes + b.nchan * info["t_int"] * 4) / per_step
     res = {
         "metric": "Msamples/s dedispersed",
         "value": round(value, 1),
@@ -512,7 +515,8 @@ def main():
         "config": {"workload": WORKLOADS[args.config], "nchan": b.nchan, "nsamp": b.nsamp,
                    "fft_len": info["fft_len"], "overlap": info["overlap"],
                    "nfront": info["nfront"], "n_int": b.n_int, "dm": b.dm,
-                   "input": "int8 time-major, resident in HBM", "taper": args.taper},
+                   "input": ("int8" if b.int8 else "complex64") + " time-major, resident in HBM",
+                   "taper": args.taper},
         "x_realtime": round(duration_s / (ms * 1e-3), 1),
         "stages_ms_per_step": {k: round(t / args.steps, 4) for k, (t, n) in stages.items()},
         "roofline": {"kernel": "block_kernel (FFT+chirp+IFFT+detect+integrate)",
@@ -527,6 +531,23 @@ def main():
                      "alg_hbm_frac": round(alg_bytes / (blk_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
         "gflops_paper_eq5": round(flops / (blk_avg * 1e-3) / 1e9, 1),
     }
+    if info["fft_len"] > 16384:
+        # long transforms: four passes over HBM (columns, rows, inverse columns
+        # with voltages out, integration), bound by HBM; design bytes per sample
+        # at R = N/M: input R + 8R spectra, 8R + 8R, 8R + 4 (|y|^2) + 8 (voltages),
+        # 4 + 4/n_int
+        R = info["fft_len"] / info["step"]
+        design = ((in_bytes + 32.0) * R + 8.0 + 4.0 / b.n_int +
+                  (8.0 if args.config == 1 else 0.0))
+        dbytes = design * b.nchan * b.nsamp
+        gbs = dbytes / (blk_avg * 1e-3) / 1e9
+        res["roofline"] = {"kernel": "four-step passes (cols_fwd, rows, cols_inv, integrate)",
+                           "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                           "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                           "traffic": None, "avg_ms": round(blk_avg, 4),
+                           "launches_per_step": per_step,
+                           "design_bytes_per_sample": round(design, 2),
+                           "alg_flops_per_launch": round(flops)}
     # the incoherent baseline (no coherent step) on the same resident beam
     oi = cdd.incoherent(vd, b.f_centre, b.bw, b.dm, b.n_int)
     for _ in range(args.warmup):

@@ -228,7 +228,7 @@ struct Sched {
     for (int i = 0; i < q; ++i) s *= rad_i(i);
     return s;
   }
-  // twiddle rows of R entries for every pass after the first
+  // twiddle tables (R x NS entries) for every pass after the first
   static constexpr int tw_f(int p) {
     int o = 0;
     for (int i = 1; i < p; ++i) o += ns_f(i) * rad_f(i);
@@ -262,7 +262,9 @@ __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 // Stockham pass pieces
 // ---------------------------------------------------------------------------
 // Twiddles of one pass (radix R, span NS) for this thread's butterflies,
-// loaded ahead of the exchange that precedes the pass.
+// loaded ahead of the exchange that precedes the pass.  The table holds
+// W^(r k) at r * NS + k, so the lanes of a wave, whose k are consecutive,
+// read consecutive entries.
 template <class S, int R, int NS, int TWOFF>
 struct PassTw {
   static constexpr int BPT = S::N / (R * S::T);
@@ -273,9 +275,9 @@ struct PassTw {
 #pragma unroll
       for (int b = 0; b < BPT; ++b) {
         const int k = (t + S::T * b) & (NS - 1);
-        const float2* row = tw + TWOFF + k * R;
+        const float2* col = tw + TWOFF + k;
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[b * (R - 1) + r - 1] = row[r];
+        for (int r = 1; r < R; ++r) w[b * (R - 1) + r - 1] = col[r * NS];
       }
     }
   }
@@ -440,8 +442,9 @@ __device__ __forceinline__ float2 expi_neg_turns(double r) {
   return expi_neg_turns64(q * 64.0);
 }
 
-// Host: FP64 twiddle tables of a schedule, rows of R entries per pass after
-// the first; forward tables then inverse (conjugate) tables.
+// Host: FP64 twiddle tables of a schedule, R x NS entries per pass after the
+// first (entry r * NS + k = W^(r k)); forward tables then inverse
+// (conjugate) tables.
 template <class S>
 std::vector<float2> make_twiddles() {
   std::vector<float2> tw(S::tw_total() > 0 ? S::tw_total() : 1);
@@ -450,7 +453,7 @@ std::vector<float2> make_twiddles() {
     for (int k = 0; k < ns; ++k)
       for (int r = 0; r < R; ++r) {
         const double ang = -2.0 * M_PI * (double)(r * k) / (double)(ns * R);
-        tw[off + k * R + r] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+        tw[off + r * ns + k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
       }
   }
   for (int q = 1; q < S::NP; ++q) {
@@ -458,7 +461,7 @@ std::vector<float2> make_twiddles() {
     for (int k = 0; k < ns; ++k)
       for (int r = 0; r < R; ++r) {
         const double ang = 2.0 * M_PI * (double)(r * k) / (double)(ns * R);
-        tw[off + k * R + r] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+        tw[off + r * ns + k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
       }
   }
   return tw;

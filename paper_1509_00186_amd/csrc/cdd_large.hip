@@ -1,4 +1,4 @@
-// Long overlap-save transforms (N = 2^15 .. 2^22) as a four-step FFT.
+// Long overlap-save transforms (N = 2^15 .. 2^22 complex points) as a four-step FFT.
 //
 // The paper dedisperses the full band with transforms of millions of points
 // (Sec. 1.3, 2.3, 4.5); here N = N1 * N2 with n = n1 + N1 n2 and
@@ -14,7 +14,11 @@
 //   integrate: P[u] = sum of n_int consecutive |y|^2
 // Every sub-transform reuses the register/LDS Stockham passes of the block
 // kernel; a workgroup runs G sub-transforms side by side, lanes ordered so
-// that global accesses along n1 are contiguous.
+// that global accesses along n1 are contiguous.  The twiddles W_N^(n1 k2)
+// are computed (exact phase in turns, hardware sine and cosine), not read
+// from a table.  The same passes carry the full-band mode (further below):
+// a real series packed two samples per complex value, the row pass holding
+// the mirror rows of each bin pair.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,22 +49,28 @@ struct LargeArgs {
   float2* vout;         // [nchan][nsamp] or null
   const float2* twc;    // column sub-transform twiddles
   const float2* twr;    // row sub-transform twiddles
-  const float2* tw4;    // four-step twiddles: W_N^m = lo[m & (2^sl-1)] * hi[m >> sl]
   int64_t nsamp, nblocks, item0;
-  int32_t nchan, N1, N2, M, nfront, sl, phase_mode, exact_div, taper;
+  int32_t nchan, N1, N2, M, nfront, phase_mode, exact_div, taper;
   double f_lo, df, dconst, dm;
-  // full-band mode: W_{2N}^m = tw2[m & (2^sl2-1)] * tw2[2^sl2 + (m >> sl2)], band width,
-  // chirp function per real-spectrum bin (N + 1 entries)
-  const float2* tw2;
-  int32_t sl2;
+  // full-band mode: band width, chirp function per real-spectrum bin (N + 1 entries)
   double bw;
   const float2* hb;
+  int32_t lgn;  // log2(N1 N2)
 };
 
+// exp(-2 pi i m / M) for M = 2^lg <= 2^23: (m + M/2) mod M over M is exact in
+// FP32, so t = that - 1/2 is the phase in turns reduced to [-1/2, 1/2), and
+// the hardware sine and cosine take turns (absolute error about 1.2e-7).
+// Computing the four-step twiddles this way keeps the passes free of table
+// gathers, whose scattered indices (n1 k2) touch a cache line per lane.
+__device__ __forceinline__ float2 expi_pow2(int64_t m, int lg) {
+  const int64_t M = (int64_t)1 << lg;
+  const float t = ldexpf((float)((m + (M >> 1)) & (M - 1)), -lg) - 0.5f;
+  return make_float2(__builtin_amdgcn_cosf(t), -__builtin_amdgcn_sinf(t));
+}
+
 __device__ __forceinline__ float2 tw4_fwd(const LargeArgs& a, int64_t m) {
-  const float2 lo = a.tw4[m & ((1 << a.sl) - 1)];
-  const float2 hi = a.tw4[(1 << a.sl) + (m >> a.sl)];
-  return cmul(lo, hi);
+  return expi_pow2(m, a.lgn);
 }
 
 // ---------------------------------------------------------------------------
@@ -280,9 +290,7 @@ static int launch_integrate(const float* p, float* P, int64_t nsamp, int64_t t_i
 // so one workgroup transforms rows k2 and N2 - k2 together and hands each
 // row to the other through LDS.
 __device__ __forceinline__ float2 tw2_fwd(const LargeArgs& a, int64_t m) {
-  const float2 lo = a.tw2[m & ((1 << a.sl2) - 1)];
-  const float2 hi = a.tw2[(1 << a.sl2) + (m >> a.sl2)];
-  return cmul(lo, hi);
+  return expi_pow2(m, a.lgn + 1);
 }
 
 // Chirp of Eq. 3 about the lower band edge at real-spectrum bin j (0 .. N):
@@ -477,23 +485,6 @@ __global__ __launch_bounds__(SC::T * G) void gsb_inverse_kernel(
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-template <int LGN>
-static std::vector<float2> make_fourstep() {
-  const int sl = (LGN + 1) / 2;
-  const int64_t N = (int64_t)1 << LGN;
-  const int64_t nlo = (int64_t)1 << sl, nhi = N >> sl;
-  std::vector<float2> t(nlo + nhi);
-  for (int64_t m = 0; m < nlo; ++m) {
-    const double ang = -2.0 * M_PI * (double)m / (double)N;
-    t[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-  }
-  for (int64_t h = 0; h < nhi; ++h) {
-    const double ang = -2.0 * M_PI * (double)(h << sl) / (double)N;
-    t[nlo + h] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-  }
-  return t;
-}
-
 constexpr int64_t kChunkBytes = (int64_t)512 << 20;  // intermediate spectra per chunk
 
 bool large_supported(int N) { return N >= (1 << 15) && N <= (1 << 22) && (N & (N - 1)) == 0; }
@@ -516,8 +507,6 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
   LargeArgs a{};
   int e = twiddles_of<SC>(&a.twc);
   if (!e) e = twiddles_of<SR>(&a.twr);
-  if (!e) e = cached_table((std::string("fourstep") + std::to_string(LGN)).c_str(),
-                           &make_fourstep<LGN>, &a.tw4);
   if (e) return e;
   a.x = xt;
   a.S = S;
@@ -530,7 +519,7 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
   a.N2 = N2;
   a.M = p.M;
   a.nfront = p.nfront;
-  a.sl = (LGN + 1) / 2;
+  a.lgn = LGN;
   a.phase_mode = p.phase_mode;
   a.taper = p.taper;
   a.exact_div = exact_div;
@@ -622,10 +611,6 @@ static int launch_fullband_t(const FullbandPlan& f, const float* series, float2*
   LargeArgs a{};
   int e = twiddles_of<SC>(&a.twc);
   if (!e) e = twiddles_of<SR>(&a.twr);
-  if (!e) e = cached_table((std::string("fourstep") + std::to_string(LGN)).c_str(),
-                           &make_fourstep<LGN>, &a.tw4);
-  if (!e) e = cached_table((std::string("fourstep") + std::to_string(LGN + 1)).c_str(),
-                           &make_fourstep<LGN + 1>, &a.tw2);
   if (e) return e;
   a.x = series;
   a.S = S;
@@ -638,8 +623,7 @@ static int launch_fullband_t(const FullbandPlan& f, const float* series, float2*
   a.N2 = N2;
   a.M = f.M / 2;
   a.nfront = f.nfront / 2;
-  a.sl = (LGN + 1) / 2;
-  a.sl2 = (LGN + 2) / 2;
+  a.lgn = LGN;
   a.phase_mode = CDD_PHASE_FP64_REDUCED;
   a.taper = f.taper;
   a.exact_div = 1;
