@@ -434,6 +434,11 @@ typedef struct {
   int64_t count[CDD_NSTAGES]; /* number of launches timed per stage         */
 } cdd_profile;
 cdd_status cdd_profile_enable(int32_t on);  /* process-wide switch          */
+/* Which stages are timed while enabled: bit s = stage s (default all).  Each
+ * timed stage adds two event records to its stream, which cost the device a
+ * few microseconds each; timing only the stage of interest keeps a measured
+ * run close to an untimed one.  EINVAL for 0 or bits beyond CDD_NSTAGES. */
+cdd_status cdd_profile_select(uint32_t stage_mask);
 cdd_status cdd_profile_read(cdd_profile* out);
 
 /* ---------------------------------------------------------------------

@@ -125,6 +125,8 @@ def _load():
         getattr(lib, f).restype = ctypes.c_int
     lib.cdd_profile_enable.argtypes = [i32]
     lib.cdd_profile_enable.restype = ctypes.c_int
+    lib.cdd_profile_select.argtypes = [ctypes.c_uint32]
+    lib.cdd_profile_select.restype = ctypes.c_int
     lib.cdd_profile_read.argtypes = [ctypes.POINTER(Profile)]
     lib.cdd_profile_read.restype = ctypes.c_int
     lib.cdd_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
@@ -176,7 +178,11 @@ def _check(status: int):
         raise CddError(status, lib.cdd_last_error().decode())
 
 
-def profile_enable(on: bool = True):
+def profile_enable(on: bool = True, stages=None):
+    """Switch stage timing on or off; ``stages`` (names from STAGES) limits
+    it to those stages, None times every stage."""
+    mask = (1 << len(STAGES)) - 1 if stages is None else sum(1 << STAGES.index(s) for s in stages)
+    _check(lib.cdd_profile_select(ctypes.c_uint32(mask)))
     _check(lib.cdd_profile_enable(int(bool(on))))
 
 

@@ -20,7 +20,7 @@ cdd_status device_fail(const char* what, int err) {
 // Layout change with stage timing.
 int launch_transposed(const BeamPlan& p, const void* in, void* out, void* stream) {
   void* tok = nullptr;
-  int e = stage_begin(stream, &tok);
+  int e = stage_begin(kStageTranspose, stream, &tok);
   if (e) return e;
   if ((e = launch_transpose(in, out, p.dtype, p.nsamp, p.nchan, p.nsamp, stream))) return e;
   return stage_end(kStageTranspose, stream, tok);
@@ -44,7 +44,7 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
   }
   float* P = chan_P ? chan_P : (float*)(ws + lay.p_off);
   int32_t* d = (int32_t*)(ws + lay.d_off);
-  if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
+  if ((e = stage_begin(kStageDelays, stream, &tok))) return device_fail("event record", e);
   if ((e = launch_delays(p, tile, d, stream))) return device_fail("delay launch", e);
   void* H = nullptr;
   if (block_supported(p.N) && tile.ndm == 1) {
@@ -54,7 +54,7 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
       return device_fail("chirp table launch", e);
   }
   if ((e = stage_end(kStageDelays, stream, tok))) return device_fail("event record", e);
-  if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
+  if ((e = stage_begin(kStageBlock, stream, &tok))) return device_fail("event record", e);
   if (block_supported(p.N)) {
     if ((e = launch_block(p, xt, tile, P, volt_out, H, stream)))
       return device_fail("block kernel launch", e);
@@ -68,7 +68,7 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
     }
   }
   if ((e = stage_end(kStageBlock, stream, tok))) return device_fail("event record", e);
-  if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
+  if ((e = stage_begin(kStageDsum, stream, &tok))) return device_fail("event record", e);
   if ((e = launch_dsum(p, tile.ndm, P, d, intensity, coverage, out_stride, stream)))
     return device_fail("delay-sum launch", e);
   if ((e = stage_end(kStageDsum, stream, tok))) return device_fail("event record", e);
@@ -264,13 +264,13 @@ extern "C" cdd_status cdd_incoherent(const void* voltages, int32_t dtype, int64_
     tile.ndm = 1;
     tile.dm[0] = dm;
     void* tok = nullptr;
-    if ((e = stage_begin(stream, &tok)) || (e = launch_delays(p, tile, d, stream)) ||
+    if ((e = stage_begin(kStageDelays, stream, &tok)) || (e = launch_delays(p, tile, d, stream)) ||
         (e = stage_end(kStageDelays, stream, tok)))
       return device_fail("delay launch", e);
-    if ((e = stage_begin(stream, &tok)) || (e = launch_detect(p, xt, P, stream)) ||
+    if ((e = stage_begin(kStageBlock, stream, &tok)) || (e = launch_detect(p, xt, P, stream)) ||
         (e = stage_end(kStageBlock, stream, tok)))
       return device_fail("detect launch", e);
-    if ((e = stage_begin(stream, &tok)) ||
+    if ((e = stage_begin(kStageDsum, stream, &tok)) ||
         (e = launch_dsum(p, 1, P, d, intensity, coverage, p.t_int, stream)) ||
         (e = stage_end(kStageDsum, stream, tok)))
       return device_fail("aligned-sum launch", e);
@@ -434,7 +434,7 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
         }
         host_tabs.emplace_back(batch_table_bytes((int)group.size()), 0);
         void* tok = nullptr;
-        if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
+        if ((e = stage_begin(kStageBlock, stream, &tok))) return device_fail("event record", e);
         if (single) {
           if ((e = launch_multi_single(group.data(), H.data(), (int)group.size(),
                                        host_tabs.back().data(), (char*)tab_dev + tab_used,
@@ -464,7 +464,7 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
         float* P = (float*)(wb + lay.p_off);
         void* tok = nullptr;
         if (!block_supported(p.N)) {
-          if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
+          if ((e = stage_begin(kStageBlock, stream, &tok))) return device_fail("event record", e);
           for (int i = 0; i < tiles[b].ndm; ++i)
             if ((e = launch_large(p, xt[b], tiles[b].dm[i], wb + lay.s_off,
                                   (float*)(wb + lay.pb_off), P + (int64_t)i * p.nchan * p.t_int,
@@ -474,10 +474,10 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
         }
         int32_t* dl = (int32_t*)(wb + lay.d_off);
         const int64_t i0 = (int64_t)r * plan->tile[b];
-        if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
+        if ((e = stage_begin(kStageDelays, stream, &tok))) return device_fail("event record", e);
         if ((e = launch_delays(p, tiles[b], dl, stream))) return device_fail("delay launch", e);
         if ((e = stage_end(kStageDelays, stream, tok))) return device_fail("event record", e);
-        if ((e = stage_begin(stream, &tok))) return device_fail("event record", e);
+        if ((e = stage_begin(kStageDsum, stream, &tok))) return device_fail("event record", e);
         if ((e = launch_dsum(p, tiles[b].ndm, P, dl, d.intensity + i0 * p.t_int,
                              d.coverage ? d.coverage + i0 * p.t_int : nullptr, p.t_int, stream)))
           return device_fail("delay-sum launch", e);

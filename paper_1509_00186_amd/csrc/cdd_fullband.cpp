@@ -170,7 +170,7 @@ extern "C" cdd_status cdd_gsb_inverse(const void* spectra, int64_t nspec, int32_
   if (!gsb_supported(nchan))
     return fail(CDD_EINVAL, "nchan must be a power of two in [128, 2048] (got %d)", nchan);
   void* tok = nullptr;
-  int e = stage_begin(stream, &tok);
+  int e = stage_begin(kStageTranspose, stream, &tok);
   if (!e) e = launch_gsb_inverse(spectra, nspec, nchan, series, stream);
   if (!e) e = stage_end(kStageTranspose, stream, tok);
   if (e) return device_error("inverse-transform launch", e);
@@ -225,11 +225,11 @@ extern "C" cdd_status cdd_fullband_dedisperse(const void* spectra, int64_t nspec
     char* ws = (char*)workspace;
     float* x = (float*)(ws + lay.x_off);
     void* tok = nullptr;
-    int e = stage_begin(stream, &tok);
+    int e = stage_begin(kStageTranspose, stream, &tok);
     if (!e) e = launch_gsb_inverse(spectra, nspec, nchan, x, stream);
     if (!e) e = stage_end(kStageTranspose, stream, tok);
     if (e) return device_error("inverse-transform launch", e);
-    e = stage_begin(stream, &tok);
+    e = stage_begin(kStageBlock, stream, &tok);
     if (!e) e = launch_fullband(f, x, ws + lay.s_off, (float*)(ws + lay.pb_off), ws + lay.h_off,
                                 intensity, volt_out, stream);
     if (!e) e = stage_end(kStageBlock, stream, tok);

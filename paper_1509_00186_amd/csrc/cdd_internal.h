@@ -139,7 +139,7 @@ int block_variants(int N);  // number of schedules compiled for N
 
 // Stage timing (cdd_profile.hip): no-ops unless profiling is enabled.
 bool profiling();
-int stage_begin(void* stream, void** token);
+int stage_begin(int stage, void* stream, void** token);
 int stage_end(int stage, void* stream, void* token);
 enum { kStageTranspose = 0, kStageDelays = 1, kStageBlock = 2, kStageDsum = 3 };
 const char* hip_error_string(int err);

@@ -83,7 +83,7 @@ static int run_single(Aux& ax, const BeamPlan& p, const void* voltages, double d
   hipEvent_t e0 = take(ax);
   if ((e = hipEventRecord(e0, S)) != hipSuccess) return (int)e;
   if ((e = hipStreamWaitEvent(A, e0, 0)) != hipSuccess) return (int)e;
-  if ((err = stage_begin(A, &tok))) return err;
+  if ((err = stage_begin(kStageDelays, A, &tok))) return err;
   if ((err = launch_chirp_table(p, dm, H, A))) return err;
   if ((err = launch_delays(p, tile, d, A))) return err;
   if ((err = stage_end(kStageDelays, A, tok))) return err;
@@ -93,18 +93,18 @@ static int run_single(Aux& ax, const BeamPlan& p, const void* voltages, double d
   const size_t rec = (size_t)p.nsamp * p.nchan * (p.dtype == CDD_CI8 ? 2 : 8);
   Coords co = offline_coords(p);
   for (int pol = 0; pol < npol; ++pol) {
-    if ((err = stage_begin(S, &tok))) return err;
+    if ((err = stage_begin(kStageTranspose, S, &tok))) return err;
     if ((err = launch_transpose((const char*)voltages + pol * rec, xt, p.dtype, p.nsamp,
                                 p.nchan, p.nsamp, S)))
       return err;
     if ((err = stage_end(kStageTranspose, S, tok))) return err;
     if (pol == 0 && (e = hipStreamWaitEvent(S, eA, 0)) != hipSuccess) return (int)e;
     co.accum = pol > 0;
-    if ((err = stage_begin(S, &tok))) return err;
+    if ((err = stage_begin(kStageBlock, S, &tok))) return err;
     if ((err = launch_block_co(p, co, xt, tile, P, volt_out, H, S))) return err;
     if ((err = stage_end(kStageBlock, S, tok))) return err;
   }
-  if ((err = stage_begin(S, &tok))) return err;
+  if ((err = stage_begin(kStageDsum, S, &tok))) return err;
   if ((err = launch_dsum(p, 1, P, d, I, cov, p.t_int, S))) return err;
   return stage_end(kStageDsum, S, tok);
 }
@@ -148,7 +148,7 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
   if (two && (e = hipStreamWaitEvent(S2, e0, 0)) != hipSuccess) return (int)e;
   int err = 0;
   void* tok = nullptr;
-  if ((err = stage_begin(S, &tok))) return err;
+  if ((err = stage_begin(kStageDelays, S, &tok))) return err;
   if ((err = launch_delays(p, tile, d, S))) return err;
   if ((err = launch_chirp_table(p, dm, H, S))) return err;
   if ((err = stage_end(kStageDelays, S, tok))) return err;
@@ -156,7 +156,7 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
   for (int i = 0; i < C; ++i) {
     const int64_t rows = tr[i + 1] - tr[i];
     if (rows > 0) {
-      if ((err = stage_begin(A, &tok))) return err;
+      if ((err = stage_begin(kStageTranspose, A, &tok))) return err;
       if ((err = launch_transpose((const char*)voltages + tr[i] * p.nchan * elem,
                                   xt + tr[i] * elem, p.dtype, rows, p.nchan, p.nsamp, A)))
         return err;
@@ -185,7 +185,7 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
       co.u_lim = p.t_int - u0;
       co.o_lim = p.nsamp - k0 * p.M;
       co.nblocks = nb;
-      if ((err = stage_begin(Q, &tok))) return err;
+      if ((err = stage_begin(kStageBlock, Q, &tok))) return err;
       if ((err = launch_block_co(p, co, xt, tile, P + u0,
                                  volt_out ? (char*)volt_out + k0 * p.M * 8 : nullptr, H, Q)))
         return err;
@@ -208,7 +208,7 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
     int64_t upto = last ? p.t_int
                         : std::min<int64_t>(p.t_int, kb[i + 1] * (p.M / p.n_int) - p.d_max);
     if (upto > u_done) {
-      if ((err = stage_begin(Q, &tok))) return err;
+      if ((err = stage_begin(kStageDsum, Q, &tok))) return err;
       if ((err = launch_dsum_range(p.nchan, 1, P, p.t_int, (int64_t)p.nchan * p.t_int, p.t_int,
                                    u_done, upto - u_done, d, I + u_done,
                                    cov ? cov + u_done : nullptr, p.t_int, Q)))

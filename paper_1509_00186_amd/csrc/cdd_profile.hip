@@ -12,6 +12,7 @@ namespace cdd {
 
 namespace {
 std::atomic<int> g_on{0};
+std::atomic<unsigned> g_mask{(1u << CDD_NSTAGES) - 1u};  // stages timed while on
 std::mutex g_mu;
 struct Rec {
   int stage;
@@ -22,9 +23,9 @@ std::vector<Rec> g_recs;
 
 bool profiling() { return g_on.load(std::memory_order_relaxed) != 0; }
 
-int stage_begin(void* stream, void** token) {
+int stage_begin(int stage, void* stream, void** token) {
   *token = nullptr;
-  if (!profiling()) return 0;
+  if (!profiling() || !((g_mask.load(std::memory_order_relaxed) >> stage) & 1u)) return 0;
   hipEvent_t a;
   hipError_t e = hipEventCreate(&a);
   if (e != hipSuccess) return (int)e;
@@ -55,6 +56,14 @@ extern "C" {
 
 cdd_status cdd_profile_enable(int32_t on) {
   cdd::g_on.store(on ? 1 : 0);
+  return CDD_OK;
+}
+
+cdd_status cdd_profile_select(uint32_t stage_mask) {
+  if (stage_mask == 0 || (stage_mask >> CDD_NSTAGES) != 0)
+    return cdd::fail(CDD_EINVAL, "stage_mask 0x%x must select stages among the %d", stage_mask,
+                     CDD_NSTAGES);
+  cdd::g_mask.store(stage_mask);
   return CDD_OK;
 }
 

@@ -253,7 +253,7 @@ int issue_batch(cdd_server* sv, BatchRec& br) {
     });
     br.host_tabs.emplace_back(batch_table_bytes((int)group.size()), 0);
     void* tok = nullptr;
-    if ((e = stage_begin(cs, &tok))) return e;
+    if ((e = stage_begin(kStageBlock, cs, &tok))) return e;
     if ((e = launch_batch(group.data(), (int)group.size(), br.host_tabs.back().data(),
                           (char*)br.tab_dev + tab_used, br.counter + 64 * ngroup, cs)))
       return e;
@@ -276,7 +276,7 @@ int issue_batch(cdd_server* sv, BatchRec& br) {
     if (cnt > 0) {
       if (cnt > s->icap) return (int)hipErrorInvalidValue;
       void* tok = nullptr;
-      if ((e = stage_begin(cs, &tok))) return e;
+      if ((e = stage_begin(kStageDsum, cs, &tok))) return e;
       if ((e = launch_dsum_range(p.nchan, 1, s->Pb[s->pcur], s->pcap, (int64_t)p.nchan * s->pcap,
                                  s->U - s->ubase, s->Inext - s->ubase, cnt, s->d, s->Iout,
                                  nullptr, cnt, cs)))

@@ -237,3 +237,11 @@ def test_fullband_invalid_arguments_are_rejected(args, kw, frag):
     with pytest.raises(cdd.CddError) as e:
         cdd.fullband_query(*args, **kw)
     assert frag in str(e.value)
+
+
+def test_profile_select_validation():
+    cdd = _lib()
+    assert cdd.lib.cdd_profile_select(0) == -1
+    assert cdd.lib.cdd_profile_select(1 << 4) == -1
+    assert cdd.lib.cdd_profile_select(0b0100) == 0
+    assert cdd.lib.cdd_profile_select(0b1111) == 0
