@@ -397,6 +397,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dm-trials", action="store_true")
     ap.add_argument("--no-fullband", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed steps (no incoherent baseline, polarisations, fold)")
     ap.add_argument("--no-fullband-sweep", action="store_true",
                     help="full band at the rule's transform length only")
     ap.add_argument("--taper", default="none", choices=["none", "hann", "welch"],
@@ -561,6 +563,9 @@ def main():
                            "launches_per_step": per_step,
                            "design_bytes_per_sample": round(design, 2),
                            "alg_flops_per_launch": round(flops)}
+    if args.no_extras:
+        print(json.dumps(res), flush=True)
+        return
     # the incoherent baseline (no coherent step) on the same resident beam
     oi = cdd.incoherent(vd, b.f_centre, b.bw, b.dm, b.n_int)
     for _ in range(args.warmup):
