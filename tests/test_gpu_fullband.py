@@ -100,3 +100,16 @@ def test_fullband_repeated_calls_reuse_buffers():
     b = cdd.fullband(sp, 610.0, 16.0, 0.3, 2, out=a)
     torch.cuda.synchronize()
     assert torch.equal(first, b["I"])
+
+
+def test_fullband_several_chunks_of_spectra():
+    """2^23-point transforms keep at most 16 blocks of spectra in the
+    workspace: a record of 17 blocks runs in two chunks."""
+    nchan = 512
+    M = (1 << 23) - 1024
+    nspec = -(-16 * M // (2 * nchan)) + 5
+    sp = _records(14, nspec, nchan)
+    y, I, o, info = _fb_both(sp, 610.0, 16.0, 0.05, 2, fft_len=1 << 23)
+    assert info["nblocks"] == 17 and info["overlap"] == 1024
+    assert rel_l2(y, o["y"]) <= TOL_V
+    assert rel_l2(I, o["P"]) <= TOL_I

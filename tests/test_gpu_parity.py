@@ -544,3 +544,26 @@ def test_autotuner_picks_a_valid_plan_and_plan_uses_it():
                          overlap=info["overlap"], nfront=info["nfront"])
         assert rel_l2(plan.I[0][i].cpu().numpy(), o["I"]) <= TOL_I
     plan.close()
+
+
+def test_long_transforms_in_several_chunks():
+    """2^22-point channel transforms keep at most 16 (channel, block) items
+    of spectra in the workspace: 4 channels of 5 blocks run in two chunks."""
+    import torch
+    cdd = _cdd()
+    nchan, fcen, bw, dm, n_int = 4, 300.0, 4.0, 0.001, 4
+    N = 1 << 22
+    q = cdd.query(0, 1 << 20, nchan, fcen, bw, dm, N, n_int)
+    M = q["step"]
+    nsamp = 5 * M - 1000
+    rng = np.random.default_rng(41)
+    v = synth.noise_int8(rng, nsamp, nchan, 20.0)
+    flush("case: long transforms, %d channels x %d samples, N 2^22" % (nchan, nsamp))
+    g = cdd.dedisperse(to_dev(v), fcen, bw, dm, N, n_int, want_chan=True)
+    torch.cuda.synchronize()
+    info = g["info"]
+    assert info["nblocks"] == 5
+    o = O.dedisperse(v, fcen, bw, dm, n_int, fft_len=N, overlap=info["overlap"],
+                     nfront=info["nfront"])
+    assert rel_l2(g["P"].cpu().numpy(), o["P"]) <= TOL_I
+    assert rel_l2(g["I"].cpu().numpy(), o["I"]) <= TOL_I
