@@ -118,6 +118,50 @@ __global__ __launch_bounds__(SC::T * G) void cols_fwd_kernel(const LargeArgs a) 
 }
 
 // ---------------------------------------------------------------------------
+// Chirp function of channel c at bin i of the N-point transform (bin i < N/2
+// lies +i df/N from the channel centre, else (i - N) df/N): exp(-2 pi i q) of
+// Eq. 3 about the centre, times the taper and 1/N.  FP64 phase reduced before
+// the FP32 rotation, or all FP32 (precision study).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 chan_chirp(const LargeArgs& a, double fc, int64_t i,
+                                             int64_t N) {
+  const float inv_n = 1.0f / (float)N;
+  const int64_t si = i < N / 2 ? i : i - N;
+  const float g = inv_n * taper_gain<false>(a.taper, (float)si * inv_n);
+  if (a.phase_mode == CDD_PHASE_FP64_REDUCED) {
+    const double dfn = a.df / (double)N;
+    const double B = a.dconst * a.dm * dfn * dfn / (fc * fc * fc);
+    const double beta = dfn / fc;
+    const double sd = (double)si;
+    const double x = beta * sd;
+    const double q = a.exact_div ? (B * (sd * sd)) / fma(beta, sd, 1.0)
+                                 : (B * (sd * sd)) * fma(x, x, 1.0 - x);
+    const float2 h = expi_neg_turns(q - rint(q));
+    return make_float2(h.x * g, h.y * g);
+  }
+  const float fcf = (float)fc;
+  const float Af = (float)(a.dconst * a.dm) / (fcf * fcf);
+  const float f = (float)si * ((float)a.df / (float)N);
+  const float q = Af * (f * f) / (fcf + f);
+  float sn, cs;
+  sincospif(2.0f * q, &sn, &cs);
+  return make_float2(cs * g, -sn * g);
+}
+
+// The chirp functions of one call, per channel in the order the row pass
+// reads them: entry c N + k2 N1 + k1 holds bin i = k2 + N2 k1 of channel c.
+__global__ __launch_bounds__(256) void chan_chirp_table_kernel(LargeArgs a, int64_t N,
+                                                               float2* __restrict__ hb) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= N * a.nchan) return;
+  const int c = (int)(idx / N);
+  const int64_t e = idx - (int64_t)c * N;
+  const int64_t i = e / a.N1 + (int64_t)a.N2 * (e % a.N1);
+  const double fc = a.f_lo + ((double)c + 0.5) * a.df;
+  hb[idx] = chan_chirp(a, fc, i, N);
+}
+
+// ---------------------------------------------------------------------------
 // rows: forward row DFT, chirp, inverse row DFT, conjugate four-step twiddle
 // ---------------------------------------------------------------------------
 template <class SR, int G>
@@ -139,46 +183,13 @@ __global__ __launch_bounds__(SR::T * G) void rows_kernel(const LargeArgs a) {
     for (int r = 0; r < R0; ++r) v[b * R0 + r] = row[tl + SR::T * b + r * (L / R0)];
   float* my = lds + g * (SR::lds_floats() + 1);
   fft_forward<SR>(v, my, a.twr, tl);
-  // chirp on bins i = k2 + N2 k1
-  const double fc = a.f_lo + ((double)c + 0.5) * a.df;
-  const float inv_n = 1.0f / (float)N;
-  if (a.phase_mode == CDD_PHASE_FP64_REDUCED) {
-    const double dfn = a.df / (double)N;
-    const double B = a.dconst * a.dm * dfn * dfn / (fc * fc * fc);
-    const double beta = dfn / fc;
+  // chirp on bins i = k2 + N2 k1, from the call's table
+  const float2* h = a.hb + (int64_t)c * N + (int64_t)k2 * a.N1;
 #pragma unroll
-    for (int b = 0; b < BL; ++b)
+  for (int b = 0; b < BL; ++b)
 #pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const int64_t k1 = tl + SR::T * b + r * (L / RL);
-        const int64_t i = k2 + (int64_t)a.N2 * k1;
-        const double sd = (double)(i < N / 2 ? i : i - N);
-        const double x = beta * sd;
-        const double q = a.exact_div ? (B * (sd * sd)) / fma(beta, sd, 1.0)
-                                     : (B * (sd * sd)) * fma(x, x, 1.0 - x);
-        const float2 h = expi_neg_turns(q - rint(q));
-        const float g = inv_n * taper_gain<false>(a.taper, (float)sd * inv_n);
-        v[b * RL + r] = cmul(v[b * RL + r], make_float2(h.x * g, h.y * g));
-      }
-  } else {
-    const float fcf = (float)fc;
-    const float Af = (float)(a.dconst * a.dm) / (fcf * fcf);
-    const float dfn = (float)a.df / (float)N;
-#pragma unroll
-    for (int b = 0; b < BL; ++b)
-#pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const int64_t k1 = tl + SR::T * b + r * (L / RL);
-        const int64_t i = k2 + (int64_t)a.N2 * k1;
-        const float sf = (float)(i < N / 2 ? i : i - N);
-        const float f = sf * dfn;
-        const float q = Af * (f * f) / (fcf + f);
-        float sn, cs;
-        sincospif(2.0f * q, &sn, &cs);
-        const float g = inv_n * taper_gain<false>(a.taper, sf * inv_n);
-        v[b * RL + r] = cmul(v[b * RL + r], make_float2(cs * g, -sn * g));
-      }
-  }
+    for (int r = 0; r < RL; ++r)
+      v[b * RL + r] = cmul(v[b * RL + r], h[tl + SR::T * b + r * (L / RL)]);
   fft_inverse<SR>(v, my, a.twr, tl);
 #pragma unroll
   for (int b = 0; b < B0; ++b)
@@ -530,6 +541,13 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
   hipStream_t st = (hipStream_t)stream;
   const int64_t items = (int64_t)p.nchan * p.nblocks;
   const int64_t chunk = large_chunk_items(p);
+  // the call's chirp table follows the chunk of spectra in the workspace
+  constexpr int64_t NP = (int64_t)1 << LGN;
+  a.hb = S + chunk * NP;
+  const int64_t nt = (NP * p.nchan + 255) / 256;
+  if (nt > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(chan_chirp_table_kernel, dim3((unsigned)nt), dim3(256), 0, st, a, NP,
+                     (float2*)a.hb);
   for (int64_t i0 = 0; i0 < items; i0 += chunk) {
     const int64_t q = std::min(chunk, items - i0);
     a.item0 = i0;

@@ -199,8 +199,9 @@ WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p, bool chirp_tabl
   w.d_bytes = (size_t)ndm_tile * p.nchan * sizeof(int32_t);
   off = align256(off + w.d_bytes);
   if (!block_supported(p.N) && large_supported(p.N)) {
+    // one chunk of spectra, then the call's chirp table (nchan x N)
     w.s_off = off;
-    w.s_bytes = (size_t)large_chunk_items(p) * p.N * 8;
+    w.s_bytes = (size_t)(large_chunk_items(p) + p.nchan) * p.N * 8;
     off = align256(off + w.s_bytes);
     w.pb_off = off;
     w.pb_bytes = (size_t)p.nchan * p.nsamp * sizeof(float);
