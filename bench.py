@@ -280,14 +280,18 @@ def polarisations_and_fold(cdd, torch, vd, b, steps: int, ms_one: float):
             "fold_counts_total": int(cnt.sum().item())}
 
 
-def dm_trials(cdd, torch, vd, b, info, reps: int = 3, taper: str = "none"):
+def dm_trials(cdd, torch, vd, b, info, reps: int = 3, taper: str = "none",
+              autotune: bool = False):
     """64 DM trials (60.0 + 0.254 i) on the same resident beam: the batched
     plan (forward transform shared, one persistent launch per 64 trials)
-    against a plain loop of single-DM calls at the same (N, L, nfront)."""
+    against a plain loop of single-DM calls at the same (N, L, nfront).  With
+    ``autotune`` the plan's transform length and schedule come from the
+    autotuner (2^11 .. 2^14) instead of the beam's N."""
     import synth
     dms = synth.config(4).dms
     plan = cdd.Plan([dict(voltages=vd, f_centre=b.f_centre, bw=b.bw, dms=dms, n_int=b.n_int,
-                          fft_len=b.fft_len)], taper=taper)
+                          fft_len=0 if autotune else b.fft_len)], taper=taper,
+                    autotune=autotune)
     pi = plan.info(0)
     plan.execute()
     torch.cuda.synchronize()
@@ -297,7 +301,8 @@ def dm_trials(cdd, torch, vd, b, info, reps: int = 3, taper: str = "none"):
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
     outs = [cdd.dedisperse(vd, b.f_centre, b.bw, dm, pi["fft_len"], b.n_int,
-                           overlap=pi["overlap"], nfront=pi["nfront"], taper=taper) for dm in dms]
+                           overlap=pi["overlap"], nfront=pi["nfront"], taper=taper)
+            for dm in dms]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -587,6 +592,8 @@ def main():
                                   "coherent_cost_ratio": round(ms / mi, 2)}
     if args.config == 2 and not args.no_dm_trials:
         res["dm_trials"] = dm_trials(cdd, torch, vd, b, info, taper=args.taper)
+        res["dm_trials_autotuned"] = dm_trials(cdd, torch, vd, b, info, taper=args.taper,
+                                               autotune=True)
     if args.config == 2:
         res["polarisations_and_fold"] = polarisations_and_fold(cdd, torch, vd, b, args.steps, ms)
     if args.config == 2 and not args.no_fullband:

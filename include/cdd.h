@@ -445,9 +445,9 @@ cdd_status cdd_profile_read(cdd_profile* out);
  * Autotuner: transform length and block-kernel schedule for a beam shape.
  * Every N in [n_min, n_max] (powers of two; 0 = 2^11 and 2^14) for which the
  * overlap fits, and every schedule compiled for that N, is timed on the
- * current device on a random int8 record of the beam's shape (up to eight
- * DM trials per work item); the fastest in input samples x DM trials per
- * second wins.  Results are cached per device and shape in memory, and
+ * current device on a random int8 record of the beam's shape (up to sixteen
+ * DM trials per work item), in two sweeps whose best time per candidate
+ * counts; the fastest in input samples x DM trials per second wins.  Results are cached per device and shape in memory, and
  * appended to the text file named by the environment variable CDD_TUNE_CACHE
  * (read back on first use).  Allocates and frees its own device memory and
  * waits for the device.  ENOTSUP for complex-float records.
