@@ -448,7 +448,7 @@ def main():
                "steps": 3, "warmup": 1, "ms_per_step": mb["plan_ms"], "higher_is_better": True,
                "scaling": "weak", "vs_baseline": None, "dtype": "f32",
                "data": "synthetic (seeded int8 noise)", "config": {"workload": WORKLOADS[4]},
-               "multibeam": mb}
+               "x_realtime": mb["x_realtime"], "multibeam": mb}
         print(json.dumps(res), flush=True)
         return
     if args.config == 6:
@@ -458,7 +458,8 @@ def main():
                "steps": args.steps, "warmup": args.warmup, "ms_per_step": fb["ms_per_call"],
                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                "dtype": "f32", "data": "synthetic (seeded int8 noise records)",
-               "config": {"workload": WORKLOADS[6]}, "fullband": fb}
+               "config": {"workload": WORKLOADS[6]}, "x_realtime": fb["x_realtime"],
+               "fullband": fb}
         print(json.dumps(res), flush=True)
         return
     if args.config == 5:
