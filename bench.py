@@ -549,6 +549,8 @@ def main():
                      "bound": "alu", "achieved": round(achieved, 2),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "peak_without_packed_fp32": PEAK_FP32_TFLOPS / 2,
+                     "frac_without_packed_fp32": round(achieved / (PEAK_FP32_TFLOPS / 2), 4),
                      "traffic": traffic,
                      "avg_ms": round(blk_avg, 4),
                      "launches_per_step": per_step,
