@@ -63,7 +63,7 @@ typedef enum {
   CDD_EBUSY = -4,     /* object in use (e.g. a stream with work in flight)  */
   CDD_EAGAIN = -5,    /* admission refused now (over budget); retry later   */
   CDD_EINTERNAL = -6, /* invariant broken inside the library               */
-  CDD_ENOTSUP = -7    /* valid request this build does not support          */
+  CDD_ENOTSUP = -7    /* valid request the library does not support        */
 } cdd_status;
 
 /* Input sample formats (time-major, as a voltage-beam recorder writes

@@ -146,7 +146,7 @@ cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp, in
                              opts, &p);
     if (s != CDD_OK) return s;
     if (!block_supported(p.N) && !large_supported(p.N))
-      return fail(CDD_ENOTSUP, "fft_len %d is not supported by this build", p.N);
+      return fail(CDD_ENOTSUP, "fft_len %d is not supported by the library", p.N);
     WsLayout lay = ws_layout(p, 1, true, true);
     if (!workspace || ws_bytes < lay.total)
       return fail(CDD_EINVAL, "workspace too small: need %zu bytes, got %zu", lay.total,

@@ -111,7 +111,7 @@ static cdd_status make_fullband_plan(int64_t nspec, int32_t nchan, double f_cent
       N = std::max<int64_t>(std::max<int64_t>(r, 2 * L), kMinFullband);
       if (N > kMaxFullband)
         return fail(CDD_ENOTSUP, "DM too large: the length rule asks for %lld real points, "
-                    "this build transforms at most %d", (long long)N, kMaxFullband);
+                    "the library transforms at most %d", (long long)N, kMaxFullband);
     }
     while (L < N && (N - L) % n_int != 0) ++L;
     if (L >= N)
