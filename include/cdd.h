@@ -125,7 +125,7 @@ typedef struct {
                               (0 or 1 = one; 2 = two records of the same
                               shape back to back, [2][nsamp][nchan]...):
                               their detected intensities are summed before
-                              the delay-aligned sum (Sec. 4.1, one
+                              the delay-aligned sum (Sec. 4.3 and 4.5, one
                               polarisation per host, summed); N <= 16384,
                               nchan > 1, one time chunk, no voltages out   */
   int32_t reserved[2];
@@ -193,7 +193,7 @@ cdd_status cdd_incoherent(const void* voltages, int32_t dtype, int64_t nsamp,
 
 /*
  * cdd_fold -- fold an intensity series at a known period into phase bins
- * (the folded profiles the paper compares in Sec. 5).  Sample u goes to bin
+ * (the folded profiles the paper compares in Sec. 4.5).  Sample u goes to bin
  * floor(frac(u / period + phase0) * nbins) (clamped to nbins - 1),
  * frac(x) = x - floor(x), all in FP64; profile[b] is the sum of its samples
  * in ascending u (accumulated in FP64, stored as FP32) and counts[b] their

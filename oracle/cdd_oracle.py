@@ -327,7 +327,7 @@ def incoherent(voltages, f_centre: float, bw: float, dm: float, n_int: int,
 
 def fold(I: np.ndarray, period: float, phase0: float, nbins: int):
     """Fold a series at a known period (the folded profiles compared in
-    Sec. 5): sample u goes to bin floor(frac(u / period + phase0) * nbins),
+    Sec. 4.5): sample u goes to bin floor(frac(u / period + phase0) * nbins),
     frac(x) = x - floor(x), clamped to nbins - 1.  Returns the per-bin sums
     (float64, ascending u) and counts."""
     prof = np.zeros(nbins)

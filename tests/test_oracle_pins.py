@@ -406,7 +406,7 @@ def test_incoherent_keeps_the_intra_channel_smear_that_coherent_removes():
 
 
 # ---------------------------------------------------------------------------
-# Folding (Sec. 5 compares folded profiles)
+# Folding (Sec. 4.5 compares folded profiles)
 # ---------------------------------------------------------------------------
 def test_fold_of_an_impulse_train_lands_in_one_bin():
     """Impulses every 37 samples starting at 5, folded with 37 bins at the
@@ -435,7 +435,7 @@ def test_coherent_folded_profile_is_sharper_than_incoherent():
     """A pulse train (period 20 ms, 60 us pulses) through 16 channels of
     0.25 MHz at DM 60, folded at its period: the coherent profile's peak bin
     holds a larger share of the energy than the incoherent one (the comparison
-    of Sec. 1.2 / Fig. 1 and Sec. 5, on synthetic data)."""
+    of Sec. 1.2 / Fig. 1 and Sec. 4.5, on synthetic data)."""
     nchan, df, nsamp, dm, n_int = 16, 0.25, 60_000, 60.0, 4
     fcen = 325.0
     fc, _ = O.channel_centres(fcen, nchan * df, nchan)
