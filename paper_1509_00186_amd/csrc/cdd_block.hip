@@ -101,26 +101,27 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
   constexpr int N = S::N, R = S::rad_f(S::NP - 1), BPT = N / (R * S::T);
   // This thread holds bins i = (t + T b) + r N/R with t + T b < N/R, so
   // i >= N/2 exactly when r >= R/2: the signed bin is a per-b base plus a
-  // compile-time constant per r.
-  const float inv_n = 1.0f / (float)N;
+  // compile-time constant per r.  The spectrum arrives already scaled by
+  // 1/N (once per item, not once per trial).
   if (a.phase_mode == CDD_PHASE_FP64_REDUCED) {
     const double dfn = a.df / (double)N;
     const double B = a.dconst * dm * dfn * dfn / (fc * fc * fc);  // turns
     const double beta = dfn / fc;
+    const double Bb = B * beta, Bbb = Bb * beta;
     auto rot = [&](float2 z, double q) {
       const float r = (float)(q - rint(q));
-      const float c = __builtin_amdgcn_cosf(r) * inv_n, s = __builtin_amdgcn_sinf(r) * inv_n;
+      const float c = __builtin_amdgcn_cosf(r), s = __builtin_amdgcn_sinf(r);
       return make_float2(z.x * c + z.y * s, z.y * c - z.x * s);  // z (c - i s)
     };
     if (a.exact_div == 0) {
+      // B s^2 (1 - x + x^2), x = beta s, as s^2 (B + s (-B beta + s B beta^2))
 #pragma unroll
       for (int b = 0; b < BPT; ++b) {
         const double s0 = (double)(t + S::T * b);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const double sd = s0 + (double)(r * (N / R) - (2 * r >= R ? N : 0));
-          const double x = beta * sd;
-          v[b * R + r] = rot(v[b * R + r], (B * (sd * sd)) * fma(x, x, 1.0 - x));
+          v[b * R + r] = rot(v[b * R + r], (sd * sd) * fma(sd, fma(sd, Bbb, -Bb), B));
         }
       }
     } else {
@@ -149,7 +150,7 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
         const float q = Af * (f * f) / (fcf + f);
         float sn, cs;
         sincospif(2.0f * q, &sn, &cs);
-        v[b * R + r] = cmul(v[b * R + r], make_float2(cs * inv_n, -sn * inv_n));
+        v[b * R + r] = cmul(v[b * R + r], make_float2(cs, -sn));
       }
     }
   }
@@ -318,9 +319,11 @@ __device__ __forceinline__ void process_item(const BlockArgs& a, int c, int64_t 
     // The taper depends on the bin only: it scales the shared spectrum once,
     // and the per-trial chirp is a pure rotation.
     if (a.taper) apply_taper<S>(v, a.taper, t);
+    // the inverse transform's 1/N (a power of two, so exact) once per item
+    constexpr float inv_n = 1.0f / (float)S::N;
     float2 X[S::E];
 #pragma unroll
-    for (int e = 0; e < S::E; ++e) X[e] = v[e];
+    for (int e = 0; e < S::E; ++e) X[e] = make_float2(v[e].x * inv_n, v[e].y * inv_n);
     for (int i = 0; i < a.dms.ndm; ++i) {
       // Per-bin indices do not depend on the DM; an opaque copy of the
       // thread index keeps the compiler from hoisting them (and holding them
