@@ -245,3 +245,31 @@ def test_profile_select_validation():
     assert cdd.lib.cdd_profile_select(1 << 4) == -1
     assert cdd.lib.cdd_profile_select(0b0100) == 0
     assert cdd.lib.cdd_profile_select(0b1111) == 0
+
+
+def test_fullband_entry_points_validate_without_device():
+    """Argument errors of the full-band calls are reported before any launch."""
+    import ctypes
+    cdd = _lib()
+    L = cdd.lib
+    buf = ctypes.create_string_buffer(1 << 16)
+    base = ctypes.addressof(buf)
+    aligned = (base + 255) & ~255
+    # inverse transform: NULL, misaligned, bad shapes
+    assert L.cdd_gsb_inverse(None, 4, 512, ctypes.c_void_p(aligned), None) == -1
+    assert L.cdd_gsb_inverse(ctypes.c_void_p(aligned + 2), 4, 512, ctypes.c_void_p(aligned), None) == -1
+    assert L.cdd_gsb_inverse(ctypes.c_void_p(aligned), 4, 500, ctypes.c_void_p(aligned), None) == -1
+    assert L.cdd_gsb_inverse(ctypes.c_void_p(aligned), 0, 512, ctypes.c_void_p(aligned), None) == -1
+    # whole path: short workspace, misaligned workspace, odd n_int
+    from paper_1509_00186_amd._binding import make_opts
+    o = make_opts()
+    args = (ctypes.c_void_p(aligned), 300, 512, 610.0, 16.0, 0.3, 0, 2,
+            ctypes.c_void_p(aligned), None, ctypes.byref(o))
+    assert L.cdd_fullband_dedisperse(*args, ctypes.c_void_p(aligned), 256, None) == -1
+    assert "workspace" in L.cdd_last_error().decode()
+    assert L.cdd_fullband_dedisperse(*args, ctypes.c_void_p(aligned + 8), 1 << 40, None) == -1
+    assert "aligned" in L.cdd_last_error().decode()
+    bad = (ctypes.c_void_p(aligned), 300, 512, 610.0, 16.0, 0.3, 0, 3,
+           ctypes.c_void_p(aligned), None, ctypes.byref(o))
+    assert L.cdd_fullband_dedisperse(*bad, ctypes.c_void_p(aligned), 1 << 40, None) == -1
+    assert "n_int" in L.cdd_last_error().decode()
