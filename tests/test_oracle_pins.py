@@ -622,3 +622,19 @@ def test_fullband_hanning_at_dm_zero_is_the_band_pass_three_tap_filter():
                               window="hann", want_voltages=True)
     want = 0.5 * x[2:-2] - 0.25 * (x[:-4] + x[4:])
     assert np.allclose(r["y"][2:-2], want, atol=1e-12)
+
+
+@pytest.mark.parametrize("j,gain", [(0, 0.0), (64, 0.75), (128, 1.0), (192, 0.75), (256, 0.0)])
+def test_fullband_welch_at_dm_zero_scales_band_tones_by_the_parabola(j, gain):
+    """Welch over the band [f_lo, f_lo + bw] is 1 - (2 f/bw - 1)^2 = 4 u (1 - u)
+    at u = f/bw (Sec. 2.2's taper written out over the whole band): at DM 0 a
+    real tone at bin j of a 512-point transform (u = j/256; its period divides
+    every block that lies inside the data, so it is one bin pair in each) comes
+    out scaled by 3/4 at a quarter and three quarters of the band, by 1 at the
+    centre, and removed at DC and Nyquist.  The first and last blocks see the
+    zeros outside the series and are left out."""
+    n = np.arange(4000)
+    x = np.cos(2.0 * np.pi * j * n / 512.0 + (0.3 if 0 < j < 256 else 0.0))
+    r = O.fullband_dedisperse(x, 610.0, 16.0, 0.0, 2, fft_len=512, overlap=8, nfront=4,
+                              window="welch", want_voltages=True)
+    assert np.allclose(r["y"][512:-512], gain * x[512:-512], atol=1e-11)
