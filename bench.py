@@ -12,7 +12,12 @@ FFT/chirp/IFFT/detect/integrate kernel, delay-aligned sum).  Prints one JSON
 line with Msamples/s (complex samples summed over channels per second), the
 real-time factor, the dominant kernel's roofline figures (from HIP events
 recorded on the launch stream during the timed steps) and the FP64 oracle
-timed on the host on a bounded sample of the same workload.
+timed on the host on a bounded sample of the same workload.  The line also
+carries every other workload as a sub-object, each measured in the same run:
+64 DM trials batched against the loop, the single-channel long transforms
+(2^23 and 2^26 samples), the 4096-channel beam with the errors of both phase
+modes, four uneven beams in one plan against the loop, the serving loop
+(paced and unpaced) and the full-band mode.
 """
 from __future__ import annotations
 
@@ -47,11 +52,12 @@ SERVING_MIX = [(16.0, 512, 610.0), (32.0, 512, 325.0), (200.0, 4096, 400.0), (16
                (32.0, 512, 325.0), (200.0, 4096, 400.0), (32.0, 512, 325.0), (16.0, 512, 610.0)]
 
 
-def block_flops(N: int, M: int) -> float:
-    """Algorithmic flops of one overlap-save block: two complex FFTs at
-    5 N log2 N each (the paper's Eq. 5 convention), the chirp multiply
-    (6 flops per bin) and detection + integration (4 flops per kept sample)."""
-    return 10.0 * N * math.log2(N) + 6.0 * N + 4.0 * M
+def flops_per_output_sample(N: int, M: int) -> float:
+    """Algorithmic flops per output sample of the overlap-save path: two
+    complex FFTs at 5 N log2 N each (the paper's Eq. 5 convention) and the
+    chirp multiply (6 flops per bin), over the M samples a block keeps, plus
+    detection and integration (4 flops per output sample)."""
+    return (10.0 * math.log2(N) + 6.0) * N / M + 4.0
 
 
 def source_digest() -> str:
@@ -393,12 +399,229 @@ def serving(cdd, seconds: float, paced: bool):
             "hbm_used_gb": round(stats["hbm_used"] / 2**30, 2)}
 
 
+def time_beam(cdd, torch, b, v, steps: int, warmup: int, taper: str = "none",
+              want_voltages: bool = False, workload: str = "", every: int = 5):
+    """One beam through the one-shot call: W untimed steps, K timed steps
+    (HIP events around the transform kernel on every ``every``-th step, on
+    the launch stream), then a separate profiled run of every stage.  Returns
+    the figures of a bench line (value, ms per step, roofline)."""
+    dev = torch.device("cuda:0")
+    vd = v if torch.is_tensor(v) else torch.from_numpy(v).to(dev)
+    tk = dict(taper=taper, want_voltages=want_voltages)
+    out = cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, **tk)   # allocate
+    info = out["info"]
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, out=out, **tk)
+    torch.cuda.synchronize()
+    cdd.profile_read()
+    cdd.profile_enable(False, stages=["block"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        if i % every == 0:
+            cdd.lib.cdd_profile_enable(1)
+        cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, out=out, **tk)
+        if i % every == 0:
+            cdd.lib.cdd_profile_enable(0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    timed_steps = (steps + every - 1) // every
+    stages = cdd.profile_read()
+    nst = min(steps, 20)
+    cdd.profile_enable(True)
+    for _ in range(nst):
+        cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, out=out, **tk)
+    torch.cuda.synchronize()
+    cdd.profile_enable(False)
+    all_stages = cdd.profile_read()
+
+    ms = dt / steps * 1e3
+    samples = b.nchan * b.nsamp
+    duration_s = b.nsamp / (b.bw / b.nchan * 1e6)
+    blk_ms, blk_n = stages["block"]
+    blk_avg = blk_ms / max(blk_n, 1)
+    # the one-shot call may split the blocks over several launches: per-launch
+    # figures are the step's totals divided by the launches per step
+    per_step = max(1, round(blk_n / timed_steps))
+    N, M = info["fft_len"], info["step"]
+    fps = flops_per_output_sample(N, M)
+    flops = fps * samples / per_step
+    achieved = flops / (blk_avg * 1e-3) / 1e12
+    in_bytes = 2 if b.int8 else 8
+    out_bytes = 8 if want_voltages else 0
+    alg_bytes = (samples * (in_bytes + out_bytes) + b.nchan * info["t_int"] * 4) / per_step
+    res = {
+        "value": round(samples / (ms * 1e-3) / 1e6, 1),
+        "ms_per_step": round(ms, 4),
+        "steps": steps, "warmup": warmup,
+        "config": {"workload": workload, "nchan": b.nchan, "nsamp": b.nsamp,
+                   "fft_len": N, "overlap": info["overlap"], "nfront": info["nfront"],
+                   "n_int": b.n_int, "dm": b.dm,
+                   "input": ("int8" if b.int8 else "complex64") + " time-major, resident in HBM",
+                   "voltages_out": bool(want_voltages), "taper": taper},
+        "x_realtime": round(duration_s / (ms * 1e-3), 1),
+        "stages_ms_per_step": {k: round(t / nst, 4) for k, (t, n) in all_stages.items()},
+        "stages_note": "from a separate run of %d profiled steps after the timed ones" % nst,
+    }
+    if N <= 16384:
+        traffic = measured_traffic("block_kernel", workload)
+        res["roofline"] = {
+            "kernel": "block_kernel (FFT+chirp+IFFT+detect+integrate)",
+            "bound": "alu", "achieved": round(achieved, 2),
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "peak_without_packed_fp32": PEAK_FP32_TFLOPS / 2,
+            "frac_without_packed_fp32": round(achieved / (PEAK_FP32_TFLOPS / 2), 4),
+            "traffic": traffic,
+            "avg_ms": round(blk_avg, 4),
+            "launches_per_step": per_step,
+            "timed_launches": blk_n, "events_on_every_nth_step": every,
+            "alg_flops_per_output_sample": round(fps, 3),
+            "output_samples_per_launch": samples / per_step,
+            "alg_flops_per_launch": round(flops),
+            "alg_hbm_bytes_per_launch": round(alg_bytes),
+            "alg_hbm_frac": round(alg_bytes / (blk_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+        res["gflops_paper_eq5"] = round(flops / (blk_avg * 1e-3) / 1e9, 1)
+    else:
+        # long transforms: four passes over HBM (columns, rows, inverse columns
+        # with voltages and |y|^2 out, integration).  Algorithmic bytes per
+        # sample: input, voltages (if asked) and the integrated output; design
+        # bytes at R = N/M: input R + 8R spectra, 8R + 8R, 8R + 4 (|y|^2) +
+        # voltages, 4 + 4/n_int
+        R = N / M
+        alg = in_bytes + out_bytes + 4.0 / b.n_int
+        design = (in_bytes + 32.0) * R + 8.0 + 4.0 / b.n_int + out_bytes
+        gbs = alg * samples / (blk_avg * 1e-3) / 1e9
+        dgbs = design * samples / (blk_avg * 1e-3) / 1e9
+        res["roofline"] = {"kernel": "four-step passes (cols_fwd, rows, cols_inv, integrate)",
+                           "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                           "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                           "traffic": measured_traffic("fourstep_passes", workload),
+                           "avg_ms": round(blk_avg, 4), "launches_per_step": per_step,
+                           "alg_bytes_per_sample": round(alg, 3),
+                           "design_bytes_per_sample": round(design, 2),
+                           "design_gbs": round(dgbs, 1),
+                           "design_frac": round(dgbs / PEAK_HBM_GBS, 4),
+                           "alg_flops_per_launch": round(flops)}
+    return res, out, vd
+
+
+def config1_leg(cdd, torch, steps: int, warmup: int, nsamp: int | None = None):
+    """Single-channel 16 MHz complex baseband at 610 MHz, DM 10, N 2^18,
+    L 2^17, voltages out.  At its own length (2^23 samples, with the dispersed
+    pulse) or, with ``nsamp``, a longer noise-only record whose working set
+    does not fit the 256 MB last-level cache."""
+    import synth
+    if nsamp is None:
+        b, v = make_input(1)
+        wl = WORKLOADS[1]
+    else:
+        b = synth.scaled(synth.config(1), nsamp=nsamp)
+        v = synth.noise_cf32(synth.rng_for(1, salt=7), nsamp)[:, None]
+        wl = WORKLOADS[1].replace("2^23", "2^%d" % int(round(math.log2(nsamp))))
+        wl = wl.replace("_dm10", "_dm10_noise")
+    res, out, vd = time_beam(cdd, torch, b, v, steps, warmup, want_voltages=True, workload=wl)
+    del out, vd
+    torch.cuda.empty_cache()
+    return res
+
+
+def config3_leg(cdd, torch, steps: int, warmup: int, nerr_chan: int = 48):
+    """200 MHz at 400 MHz, 4096 channels, 2 s, DM 120: throughput with the
+    FP64-reduced phase, and the error of both phase modes against the FP64
+    oracle on sampled channels (the lowest, largest-phase ones included),
+    each channel computed by the oracle as a one-channel beam at its centre."""
+    import oracle as O
+    import synth
+    b = synth.config(3)
+    v = synth.make_beam(b, synth.rng_for(3))
+    res, out, vd = time_beam(cdd, torch, b, v, steps, warmup, workload=WORKLOADS[3])
+    del out
+    chans = sorted(set(list(range(16)) + list(np.linspace(16, b.nchan - 1, nerr_chan - 16)
+                                              .astype(int))))
+    df = b.bw / b.nchan
+    errs = {}
+    t0 = time.perf_counter()
+    orc = {}
+    for c in chans:
+        col, fc, dfc, dm, n_int, N = _channel_task(v, b, c)
+        orc[c] = O.dedisperse(col, fc, dfc, dm, n_int, fft_len=N, overlap=128, nfront=64,
+                              want_voltages=True)
+    t_or = time.perf_counter() - t0
+    for mode, name in ((0, "fp64_reduced"), (1, "fp32")):
+        g = cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, want_chan=True,
+                           want_voltages=True, phase_mode=mode)
+        torch.cuda.synchronize()
+        idx = torch.tensor(chans, device=vd.device)
+        y = g["y"].index_select(0, idx).cpu().numpy()
+        P = g["P"].index_select(0, idx).cpu().numpy()
+        del g
+        torch.cuda.empty_cache()
+        num_v = den_v = num_p = den_p = 0.0
+        num_lo = den_lo = 0.0
+        for i, c in enumerate(chans):
+            oy, oP = orc[c]["y"][0], orc[c]["P"][0]
+            dv = float(np.sum(np.abs(y[i] - oy) ** 2))
+            nv = float(np.sum(np.abs(oy) ** 2))
+            num_v += dv
+            den_v += nv
+            num_p += float(np.sum((P[i] - oP) ** 2))
+            den_p += float(np.sum(oP ** 2))
+            if c < 16:
+                num_lo += dv
+                den_lo += nv
+        errs[name] = {"voltages_rel_l2": (num_v / den_v) ** 0.5,
+                      "voltages_rel_l2_lowest_16_channels": (num_lo / den_lo) ** 0.5,
+                      "chan_intensity_rel_l2": (num_p / den_p) ** 0.5}
+    res["precision"] = dict(errs, channels=len(chans),
+                            sample="%d channels (0-15 at the 300 MHz end, the rest spread "
+                                   "over the band), whole 2 s each; oracle %.1f s" %
+                                   (len(chans), t_or),
+                            note="the full-size comparison over every channel is a GPU test")
+    del vd
+    torch.cuda.empty_cache()
+    return res
+
+
+def other_legs(cdd, torch, vd, b, args):
+    """Every other workload of the benchmark, each a sub-object of the line:
+    DM trials (batched against the loop, fixed and autotuned N), the full
+    band, the single-channel long transforms (at 2^23 samples and at 2^26,
+    beyond the last-level cache), the 4096-channel beam with both phase
+    modes' errors, the four uneven beams in one plan against the loop, and
+    the serving loop paced at real time and unpaced."""
+    legs = []
+    if not args.no_dm_trials:
+        legs += [("dm_trials", lambda: dm_trials(cdd, torch, vd, b, None, taper=args.taper)),
+                 ("dm_trials_autotuned",
+                  lambda: dm_trials(cdd, torch, vd, b, None, taper=args.taper, autotune=True))]
+    if not args.no_fullband:
+        legs += [("fullband", lambda: fullband(cdd, torch, args.steps, args.warmup))]
+    legs += [("config1_single_channel", lambda: config1_leg(cdd, torch, args.steps, args.warmup)),
+             ("config1_single_channel_2^26",
+              lambda: config1_leg(cdd, torch, max(5, args.steps // 4), max(2, args.warmup // 4),
+                                  nsamp=1 << 26)),
+             ("config3_4096ch", lambda: config3_leg(cdd, torch, args.steps, args.warmup)),
+             ("config4_multibeam", lambda: multibeam(cdd, torch)),
+             ("config5_serving_paced", lambda: serving(cdd, 4.0, paced=True)),
+             ("config5_serving_unpaced", lambda: serving(cdd, 2.0, paced=False))]
+    out = {}
+    for name, fn in legs:
+        try:
+            out[name] = fn()
+        except Exception as e:  # a failing leg is reported, not fatal to the line
+            out[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        print("leg done: %s" % name, file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    # the GPU raises its clocks over the first ~0.1 s of sustained work: the
-    # default warm-up covers that before the timed steps
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -406,12 +629,14 @@ def main():
     ap.add_argument("--no-dm-trials", action="store_true")
     ap.add_argument("--no-fullband", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="only the timed steps (no incoherent baseline, polarisations, fold)")
+                    help="only the timed steps of the chosen workload")
     ap.add_argument("--no-fullband-sweep", action="store_true",
                     help="full band at the rule's transform length only")
     ap.add_argument("--taper", default="none", choices=["none", "hann", "welch"],
                     help="taper of the chirp function over each channel")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving run length (config 5)")
+    ap.add_argument("--nsamp", type=int, default=0,
+                    help="config 1 only: a noise record of this many samples instead")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -424,7 +649,8 @@ def main():
     # The host-side oracle on all cores runs first, in spawned worker
     # processes, before this process touches the GPU.
     pre, all_cores = None, None
-    if args.config in (1, 2, 3) and not args.no_cpu_baseline and not args.calibrate_copy_mb:
+    if args.config in (1, 2, 3) and not args.nsamp and not args.no_cpu_baseline \
+            and not args.calibrate_copy_mb:
         pre = make_input(args.config)
         b0, v0 = pre
         if b0.nchan >= 16:
@@ -444,12 +670,13 @@ def main():
         return
     import paper_1509_00186_amd as cdd
 
+    common = {"n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+              "dtype": "f32"}
     if args.config == 4:
         mb = multibeam(cdd, torch)
         res = {"metric": "Msamples/s dedispersed (four uneven beams, one plan)",
-               "value": mb["plan_msamples_per_s"], "unit": "Msamples/s", "n_gpus": 1,
-               "steps": 3, "warmup": 1, "ms_per_step": mb["plan_ms"], "higher_is_better": True,
-               "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+               "value": mb["plan_msamples_per_s"], "unit": "Msamples/s", "steps": 3,
+               "warmup": 1, "ms_per_step": mb["plan_ms"], **common,
                "data": "synthetic (seeded int8 noise)", "config": {"workload": WORKLOADS[4]},
                "x_realtime": mb["x_realtime"], "multibeam": mb}
         print(json.dumps(res), flush=True)
@@ -457,10 +684,9 @@ def main():
     if args.config == 6:
         fb = fullband(cdd, torch, args.steps, args.warmup, sweep=not args.no_fullband_sweep)
         res = {"metric": "Msamples/s dedispersed (full band, real samples)",
-               "value": fb["msamples_per_s"], "unit": "Msamples/s", "n_gpus": 1,
-               "steps": args.steps, "warmup": args.warmup, "ms_per_step": fb["ms_per_call"],
-               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-               "dtype": "f32", "data": "synthetic (seeded int8 noise records)",
+               "value": fb["msamples_per_s"], "unit": "Msamples/s", "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": fb["ms_per_call"], **common,
+               "data": "synthetic (seeded int8 noise records)",
                "config": {"workload": WORKLOADS[6]}, "x_realtime": fb["x_realtime"],
                "fullband": fb}
         print(json.dumps(res), flush=True)
@@ -469,142 +695,58 @@ def main():
         paced = serving(cdd, args.seconds, paced=True)
         burst = serving(cdd, max(2.0, args.seconds / 5), paced=False)
         res = {"metric": "Msamples/s dedispersed (serving)", "value": burst["msamples_per_s"],
-               "unit": "Msamples/s", "n_gpus": 1, "steps": 0, "warmup": 0,
-               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-               "dtype": "f32", "data": "synthetic",
+               "unit": "Msamples/s", "steps": 0, "warmup": 0, **common, "data": "synthetic",
                "config": {"workload": WORKLOADS[5]}, "paced": paced, "unpaced": burst}
+        print(json.dumps(res), flush=True)
+        return
+    if args.config == 1 and args.nsamp:
+        r = config1_leg(cdd, torch, args.steps, args.warmup, nsamp=args.nsamp)
+        res = {"metric": "Msamples/s dedispersed", "unit": "Msamples/s", **common,
+               "data": "synthetic", **r}
         print(json.dumps(res), flush=True)
         return
 
     b, v = pre if pre is not None else make_input(args.config)
-    dev = torch.device("cuda:0")
-    vd = torch.from_numpy(v).to(dev)
-    tk = dict(taper=args.taper, want_voltages=args.config == 1)
-    out = cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, **tk)   # allocate
-    info = out["info"]
-    torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, out=out, **tk)
-    torch.cuda.synchronize()
-    cdd.profile_read()
-    # timed steps: HIP events around the transform kernel only, on every
-    # fifth step (each event record costs the stream a few microseconds)
-    every = 5
-    cdd.profile_enable(False, stages=["block"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        if i % every == 0:
-            cdd.lib.cdd_profile_enable(1)
-        cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, out=out, **tk)
-        if i % every == 0:
-            cdd.lib.cdd_profile_enable(0)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    timed_steps = (args.steps + every - 1) // every
-    stages = cdd.profile_read()
-    # every stage, in a separate profiled run of the same steps
-    nst = min(args.steps, 20)
-    cdd.profile_enable(True)
-    for _ in range(nst):
-        cdd.dedisperse(vd, b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, out=out, **tk)
-    torch.cuda.synchronize()
-    cdd.profile_enable(False)
-    all_stages = cdd.profile_read()
-
-    ms = dt / args.steps * 1e3
+    vd = torch.from_numpy(v).to(torch.device("cuda:0"))
     samples = b.nchan * b.nsamp
-    value = samples / (ms * 1e-3) / 1e6
-    duration_s = b.nsamp / (b.bw / b.nchan * 1e6)
-    blk_ms, blk_n = stages["block"]
-    blk_avg = blk_ms / max(blk_n, 1)
-    # the one-shot call may split the blocks over several launches (time
-    # chunks overlapped with the layout change): per-launch figures are the
-    # step's totals divided by the launches per step
-    per_step = max(1, round(blk_n / timed_steps))
-    flops = b.nchan * info["nblocks"] * block_flops(info["fft_len"], info["step"]) / per_step
-    achieved = flops / (blk_avg * 1e-3) / 1e12
-    traffic = measured_traffic("block_kernel", WORKLOADS[args.config])
-    in_bytes = 2 if b.int8 else 8
-    alg_bytes = (b.nchan * b.nsamp * in_bytes + b.nchan * info["t_int"] * 4) / per_step
-    res = {
-        "metric": "Msamples/s dedispersed",
-        "value": round(value, 1),
-        "unit": "Msamples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.config], "nchan": b.nchan, "nsamp": b.nsamp,
-                   "fft_len": info["fft_len"], "overlap": info["overlap"],
-                   "nfront": info["nfront"], "n_int": b.n_int, "dm": b.dm,
-                   "input": ("int8" if b.int8 else "complex64") + " time-major, resident in HBM",
-                   "taper": args.taper},
-        "x_realtime": round(duration_s / (ms * 1e-3), 1),
-        "stages_ms_per_step": {k: round(t / nst, 4) for k, (t, n) in all_stages.items()},
-        "stages_note": "from a separate run of %d profiled steps after the timed ones" % nst,
-        "roofline": {"kernel": "block_kernel (FFT+chirp+IFFT+detect+integrate)",
-                     "bound": "alu", "achieved": round(achieved, 2),
-                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "peak_without_packed_fp32": PEAK_FP32_TFLOPS / 2,
-                     "frac_without_packed_fp32": round(achieved / (PEAK_FP32_TFLOPS / 2), 4),
-                     "traffic": traffic,
-                     "avg_ms": round(blk_avg, 4),
-                     "launches_per_step": per_step,
-                     "timed_launches": blk_n, "events_on_every_nth_step": every,
-                     "alg_flops_per_launch": round(flops),
-                     "alg_hbm_bytes_per_launch": round(alg_bytes),
-                     "alg_hbm_frac": round(alg_bytes / (blk_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
-        "gflops_paper_eq5": round(flops / (blk_avg * 1e-3) / 1e9, 1),
-    }
-    if info["fft_len"] > 16384:
-        # long transforms: four passes over HBM (columns, rows, inverse columns
-        # with voltages out, integration), bound by HBM; design bytes per sample
-        # at R = N/M: input R + 8R spectra, 8R + 8R, 8R + 4 (|y|^2) + 8 (voltages),
-        # 4 + 4/n_int
-        R = info["fft_len"] / info["step"]
-        design = ((in_bytes + 32.0) * R + 8.0 + 4.0 / b.n_int +
-                  (8.0 if args.config == 1 else 0.0))
-        dbytes = design * b.nchan * b.nsamp
-        gbs = dbytes / (blk_avg * 1e-3) / 1e9
-        res["roofline"] = {"kernel": "four-step passes (cols_fwd, rows, cols_inv, integrate)",
-                           "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
-                           "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
-                           "traffic": None, "avg_ms": round(blk_avg, 4),
-                           "launches_per_step": per_step,
-                           "design_bytes_per_sample": round(design, 2),
-                           "alg_flops_per_launch": round(flops)}
-    if args.no_extras:
-        print(json.dumps(res), flush=True)
-        return
-    # the incoherent baseline (no coherent step) on the same resident beam
-    oi = cdd.incoherent(vd, b.f_centre, b.bw, b.dm, b.n_int)
-    for _ in range(args.warmup):
-        cdd.incoherent(vd, b.f_centre, b.bw, b.dm, b.n_int, out=oi)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        cdd.incoherent(vd, b.f_centre, b.bw, b.dm, b.n_int, out=oi)
-    torch.cuda.synchronize()
-    mi = (time.perf_counter() - t0) / args.steps * 1e3
-    res["incoherent_baseline"] = {"ms_per_step": round(mi, 4),
-                                  "msamples_per_s": round(samples / (mi * 1e-3) / 1e6, 1),
-                                  "coherent_cost_ratio": round(ms / mi, 2)}
-    if args.config == 2 and not args.no_dm_trials:
-        res["dm_trials"] = dm_trials(cdd, torch, vd, b, info, taper=args.taper)
-        res["dm_trials_autotuned"] = dm_trials(cdd, torch, vd, b, info, taper=args.taper,
-                                               autotune=True)
-    if args.config == 2:
+    extras = {}
+    if args.config == 2 and not args.no_extras:
+        # the other workloads first (each timed the same way, W warm-up + K
+        # steps), so that the headline below runs at steady GPU clocks, as a
+        # continuously fed pipeline does
+        extras = other_legs(cdd, torch, vd, b, args)
+    r, out, vd = time_beam(cdd, torch, b, vd, args.steps, args.warmup, taper=args.taper,
+                           want_voltages=args.config == 1, workload=WORKLOADS[args.config])
+    ms = r["ms_per_step"]
+    res = {"metric": "Msamples/s dedispersed", "value": r["value"], "unit": "Msamples/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": r["config"], "x_realtime": r["x_realtime"],
+           "stages_ms_per_step": r["stages_ms_per_step"], "stages_note": r["stages_note"],
+           "roofline": r["roofline"]}
+    if "gflops_paper_eq5" in r:
+        res["gflops_paper_eq5"] = r["gflops_paper_eq5"]
+    if not args.no_extras:
+        # the incoherent baseline (no coherent step) on the same resident beam
+        oi = cdd.incoherent(vd, b.f_centre, b.bw, b.dm, b.n_int)
+        for _ in range(args.warmup):
+            cdd.incoherent(vd, b.f_centre, b.bw, b.dm, b.n_int, out=oi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            cdd.incoherent(vd, b.f_centre, b.bw, b.dm, b.n_int, out=oi)
+        torch.cuda.synchronize()
+        mi = (time.perf_counter() - t0) / args.steps * 1e3
+        res["incoherent_baseline"] = {"ms_per_step": round(mi, 4),
+                                      "msamples_per_s": round(samples / (mi * 1e-3) / 1e6, 1),
+                                      "coherent_cost_ratio": round(ms / mi, 2)}
+    if args.config == 2 and not args.no_extras:
         res["polarisations_and_fold"] = polarisations_and_fold(cdd, torch, vd, b, args.steps, ms)
-    if args.config == 2 and not args.no_fullband:
-        res["fullband"] = fullband(cdd, torch, args.steps, args.warmup)
-    if not args.no_cpu_baseline:
+        res.update(extras)
+        res["order_note"] = ("legs other than the headline ran before it; the headline's "
+                             "warm-up and timed steps follow them")
+    if not args.no_cpu_baseline and pre is not None:
         res["cpu_baseline"] = cpu_baseline(v, b, args.cpu_seconds)
         res["cpu_baseline_all_cores"] = all_cores
     print(json.dumps(res), flush=True)

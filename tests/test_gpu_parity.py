@@ -237,32 +237,6 @@ def test_two_polarisations_sum_their_intensities():
         cdd.dedisperse(to_dev(both), fcen, nchan * df, dm, N, 4, npol=2, time_chunks=2)
 
 
-def test_config2_full_size():
-    """512 channels x 4 s at 32 MHz, N = 8192, n_int = 4, DM 67.9, in the
-    launch shape the benchmark times: per-channel intensities of 64 sampled
-    channels against the oracle, the aligned sum against the oracle's delay
-    sum of the GPU's per-channel intensities, coverage exact."""
-    import torch
-    cdd = _cdd()
-    b = synth.config(2)
-    fc, _ = O.channel_centres(b.f_centre, b.bw, b.nchan)
-    v = synth.make_beam(b, synth.rng_for(2), arrival_law(b.dm, fc[-1]))
-    flush("config 2 full size")
-    g = cdd.dedisperse(to_dev(v), b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, want_chan=True)
-    torch.cuda.synchronize()
-    info = g["info"]
-    assert (info["fft_len"], info["overlap"], info["nfront"]) == (8192, 128, 64)
-    P = g["P"].cpu().numpy()
-    chans = list(range(3, 512, 8)) + [0, 511]
-    o = O.dedisperse(v, b.f_centre, b.bw, b.dm, b.n_int, fft_len=8192, overlap=128,
-                     nfront=64, channels=chans)
-    assert rel_l2(P[chans], o["P"]) <= TOL_I, rel_l2(P[chans], o["P"])
-    d = O.channel_delays(b.f_centre, b.bw, b.nchan, b.dm, b.n_int)
-    I, cov = O.delay_sum(P.astype(np.float64), d)
-    assert rel_l2(g["I"].cpu().numpy(), I) <= 1e-5
-    assert np.array_equal(g["cov"].cpu().numpy(), cov)
-
-
 @pytest.mark.parametrize("chunks", [1, 3, 8, 12])
 def test_time_chunks_do_not_change_results(chunks):
     """The record split that overlaps the layout change and the aligned sums
@@ -284,27 +258,6 @@ def test_time_chunks_do_not_change_results(chunks):
     assert rel_l2(g["P"].cpu().numpy()[[0, 50, 95]], o["P"]) <= TOL_I
     d = O.channel_delays(fcen, nchan * df, nchan, dm, 4)
     I, cov = O.delay_sum(g["P"].cpu().numpy().astype(np.float64), d)
-    assert rel_l2(g["I"].cpu().numpy(), I) <= 1e-5
-    assert np.array_equal(g["cov"].cpu().numpy(), cov)
-
-
-def test_config3_sampled_channels():
-    """4096 channels x 2 s at 200 MHz, DM 120: per-channel intensities of
-    sampled channels against the oracle; the aligned sum against the oracle's
-    delay-sum of the GPU's own per-channel intensities (delays exact)."""
-    import torch
-    cdd = _cdd()
-    b = synth.config(3)
-    v = synth.make_beam(b, synth.rng_for(3))
-    g = cdd.dedisperse(to_dev(v), b.f_centre, b.bw, b.dm, b.fft_len, b.n_int, want_chan=True)
-    torch.cuda.synchronize()
-    P = g["P"].cpu().numpy()
-    chans = list(range(0, 4096, 257)) + [4095]
-    o = O.dedisperse(v, b.f_centre, b.bw, b.dm, b.n_int, fft_len=8192, overlap=128,
-                     nfront=64, channels=chans)
-    assert rel_l2(P[chans], o["P"]) <= TOL_I
-    d = O.channel_delays(b.f_centre, b.bw, b.nchan, b.dm, b.n_int)
-    I, cov = O.delay_sum(P.astype(np.float64), d)
     assert rel_l2(g["I"].cpu().numpy(), I) <= 1e-5
     assert np.array_equal(g["cov"].cpu().numpy(), cov)
 
