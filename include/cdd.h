@@ -184,6 +184,32 @@ cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp,
                           float* chan_intensity, void* volt_out,
                           const cdd_opts* opts, void* workspace,
                           size_t ws_bytes, void* stream);
+/*
+ * cdd_dedisperse_noalloc -- cdd_dedisperse for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation): the same path and results, with the workspace in
+ * a static device array of CDD_NOALLOC_SCRATCH_BYTES that the library holds
+ * on every GPU it runs on until the process ends.  A call issues kernel
+ * launches on `stream` only (no auxiliary stream, no stage timing) and
+ * never allocates device memory; its first call on a device looks the
+ * array up and uploads the transform's FP64-built twiddle tables (into a
+ * static table pool).
+ *   arguments    as cdd_dedisperse without workspace/ws_bytes; opts may be
+ *                NULL; npol and time_chunks above 1 are not taken
+ * All calls on one GPU share that GPU's array, which keeps the last call's
+ * contents (nothing needs to start at zero): calls that overlap in time on
+ * one GPU race and must be serialised by the caller.
+ * Errors: as cdd_dedisperse; EINVAL when the call's workspace (cdd_query's
+ * ws_bytes) exceeds CDD_NOALLOC_SCRATCH_BYTES, checked before any launch;
+ * ENOTSUP for npol > 1 or time_chunks > 1.
+ */
+#define CDD_NOALLOC_SCRATCH_BYTES (512u << 20)
+cdd_status cdd_dedisperse_noalloc(const void* voltages, int32_t dtype, int64_t nsamp,
+                                  int32_t nchan, double f_centre_mhz, double bw_mhz,
+                                  double dm, int32_t fft_len, int32_t n_int,
+                                  float* intensity, int32_t* coverage,
+                                  float* chan_intensity, void* volt_out,
+                                  const cdd_opts* opts, void* stream);
 cdd_status cdd_incoherent(const void* voltages, int32_t dtype, int64_t nsamp,
                           int32_t nchan, double f_centre_mhz, double bw_mhz,
                           double dm, int32_t n_int, float* intensity,

@@ -114,6 +114,9 @@ def _load():
                               ctypes.POINTER(Opts), ctypes.POINTER(PlanInfo)]
     lib.cdd_dedisperse.argtypes = [vp, i32, i64, i32, f64, f64, f64, i32, i32, vp, vp, vp,
                                    vp, ctypes.POINTER(Opts), vp, sz, vp]
+    lib.cdd_dedisperse_noalloc.argtypes = [vp, i32, i64, i32, f64, f64, f64, i32, i32, vp, vp,
+                                           vp, vp, ctypes.POINTER(Opts), vp]
+    lib.cdd_dedisperse_noalloc.restype = ctypes.c_int
     lib.cdd_plan_create.argtypes = [ctypes.POINTER(BeamDesc), i32, ctypes.POINTER(Opts),
                                     ctypes.POINTER(vp)]
     lib.cdd_plan_info_get.argtypes = [vp, i32, ctypes.POINTER(PlanInfo)]
@@ -300,6 +303,43 @@ def dedisperse(voltages, f_centre, bw, dm, fft_len=0, n_int=1, *, want_chan=Fals
                               ptr("I"), ptr("cov"), ptr("P") if want_chan else None,
                               ptr("y") if want_voltages else None, ctypes.byref(o),
                               ptr("ws"), out["ws"].numel(), _stream_handle(stream)))
+    out["info"] = info.as_dict()
+    return out
+
+
+def dedisperse_noalloc(voltages, f_centre, bw, dm, fft_len=0, n_int=1, *, want_chan=False,
+                       want_voltages=False, overlap=None, nfront=None, dm_const=0.0,
+                       phase_mode=0, taper="none", stream=None, out=None):
+    """Run cdd_dedisperse_noalloc (the library's static scratch instead of a
+    workspace).  Outputs as dedisperse; ``out`` may pass preallocated tensors
+    (keys I, cov, P, y), and with all of them given this call allocates
+    nothing on the device."""
+    import torch
+    if not voltages.is_cuda or not voltages.is_contiguous():
+        raise ValueError("voltages must be a contiguous device tensor")
+    dt, nsamp, nchan = _layout(voltages)
+    o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode, 0, taper=taper)
+    info = PlanInfo()
+    _check(lib.cdd_query(dt, nsamp, nchan, float(f_centre), float(bw), float(dm), int(fft_len),
+                         int(n_int), int(want_voltages), ctypes.byref(o), ctypes.byref(info)))
+    dev = voltages.device
+    out = dict(out or {})
+    t_int = info.t_int
+    if "I" not in out:
+        out["I"] = torch.empty(t_int, dtype=torch.float32, device=dev)
+    if "cov" not in out:
+        out["cov"] = torch.empty(t_int, dtype=torch.int32, device=dev)
+    if want_chan and "P" not in out:
+        out["P"] = torch.empty((nchan, t_int), dtype=torch.float32, device=dev)
+    if want_voltages and "y" not in out:
+        out["y"] = torch.empty((nchan, nsamp), dtype=torch.complex64, device=dev)
+    ptr = lambda k: ctypes.c_void_p(out[k].data_ptr()) if k in out else None  # noqa: E731
+    _check(lib.cdd_dedisperse_noalloc(ctypes.c_void_p(voltages.data_ptr()), dt, nsamp, nchan,
+                                      float(f_centre), float(bw), float(dm), int(fft_len),
+                                      int(n_int), ptr("I"), ptr("cov"),
+                                      ptr("P") if want_chan else None,
+                                      ptr("y") if want_voltages else None, ctypes.byref(o),
+                                      _stream_handle(stream)))
     out["info"] = info.as_dict()
     return out
 

@@ -16,7 +16,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["cdd_plan.cpp", "cdd_api.cpp", "cdd_fullband.cpp", "cdd_aux.hip", "cdd_profile.hip", "cdd_block.hip",
            "cdd_large.hip", "cdd_server.hip",
-           "cdd_pipeline.hip", "cdd_tune.hip"]
+           "cdd_pipeline.hip", "cdd_tune.hip", "cdd_static.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-I", INCLUDE, "-I", CSRC]

@@ -9,13 +9,15 @@
 
 using namespace cdd;
 
-namespace {
-
-bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
-
+namespace cdd {
 cdd_status device_fail(const char* what, int err) {
   return fail(CDD_EDEVICE, "%s: %s", what, hip_error_string(err));
 }
+}  // namespace cdd
+
+namespace {
+
+bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 
 // Layout change with stage timing.
 int launch_transposed(const BeamPlan& p, const void* in, void* out, void* stream) {
@@ -26,17 +28,29 @@ int launch_transposed(const BeamPlan& p, const void* in, void* out, void* stream
   return stage_end(kStageTranspose, stream, tok);
 }
 
-// Run the path for one beam and one tile of DM trials.
+}  // namespace
+
+namespace cdd {
+
+// Run the path for one beam and one tile of DM trials, every kernel in order
+// on the one stream.  With timed, stage timing records events when
+// profiling is enabled; without, nothing but kernel launches is issued.
 cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
                     const void* xt_ready, char* ws, const WsLayout& lay, float* chan_P,
                     void* volt_out, float* intensity, int32_t* coverage, int64_t out_stride,
-                    void* stream) {
+                    void* stream, bool timed) {
   const void* xt = xt_ready;
   void* tok = nullptr;
   int e = 0;
+  auto begin = [&](int stage) { return timed ? stage_begin(stage, stream, &tok) : 0; };
+  auto end = [&](int stage) { return timed ? stage_end(stage, stream, tok) : 0; };
   if (xt == nullptr) {
     if (p.nchan > 1) {
-      if ((e = launch_transposed(p, voltages, ws + lay.xt_off, stream))) return device_fail("transpose launch", e);
+      if ((e = begin(kStageTranspose)) ||
+          (e = launch_transpose(voltages, ws + lay.xt_off, p.dtype, p.nsamp, p.nchan, p.nsamp,
+                                stream)) ||
+          (e = end(kStageTranspose)))
+        return device_fail("transpose launch", e);
       xt = ws + lay.xt_off;
     } else {
       xt = voltages;
@@ -44,7 +58,7 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
   }
   float* P = chan_P ? chan_P : (float*)(ws + lay.p_off);
   int32_t* d = (int32_t*)(ws + lay.d_off);
-  if ((e = stage_begin(kStageDelays, stream, &tok))) return device_fail("event record", e);
+  if ((e = begin(kStageDelays))) return device_fail("event record", e);
   if ((e = launch_delays(p, tile, d, stream))) return device_fail("delay launch", e);
   void* H = nullptr;
   if (block_supported(p.N) && tile.ndm == 1) {
@@ -53,8 +67,8 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
     if ((e = launch_chirp_table(p, tile.dm[0], H, stream)))
       return device_fail("chirp table launch", e);
   }
-  if ((e = stage_end(kStageDelays, stream, tok))) return device_fail("event record", e);
-  if ((e = stage_begin(kStageBlock, stream, &tok))) return device_fail("event record", e);
+  if ((e = end(kStageDelays))) return device_fail("event record", e);
+  if ((e = begin(kStageBlock))) return device_fail("event record", e);
   if (block_supported(p.N)) {
     if ((e = launch_block(p, xt, tile, P, volt_out, H, stream)))
       return device_fail("block kernel launch", e);
@@ -67,15 +81,16 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
         return device_fail("long-transform launch", e);
     }
   }
-  if ((e = stage_end(kStageBlock, stream, tok))) return device_fail("event record", e);
-  if ((e = stage_begin(kStageDsum, stream, &tok))) return device_fail("event record", e);
+  if ((e = end(kStageBlock))) return device_fail("event record", e);
+  if ((e = begin(kStageDsum))) return device_fail("event record", e);
   if ((e = launch_dsum(p, tile.ndm, P, d, intensity, coverage, out_stride, stream)))
     return device_fail("delay-sum launch", e);
-  if ((e = stage_end(kStageDsum, stream, tok))) return device_fail("event record", e);
+  if ((e = end(kStageDsum))) return device_fail("event record", e);
   return CDD_OK;
 }
 
-}  // namespace
+}  // namespace cdd
+
 
 struct cdd_plan {
   std::vector<BeamPlan> beams;
@@ -177,7 +192,7 @@ cdd_status cdd_dedisperse(const void* voltages, int32_t dtype, int64_t nsamp, in
     tile.ndm = 1;
     tile.dm[0] = dm;
     s = run_tile(p, voltages, tile, nullptr, (char*)workspace, lay, chan_intensity, volt_out,
-                 intensity, coverage, p.t_int, stream);
+                 intensity, coverage, p.t_int, stream, true);
     if (s == CDD_OK) clear_error();
     return s;
   } catch (const std::bad_alloc&) {

@@ -459,8 +459,20 @@ __global__ __launch_bounds__(256) void chirp_table_kernel(float2* __restrict__ H
 // Host side: FP64 twiddle tables (cached per device, length and schedule)
 // and launch
 // ---------------------------------------------------------------------------
+// The tables of every schedule live in one static device pool, filled on
+// first use per device and kept until the process ends, so that building a
+// table never allocates device memory.  Entries are placed at 256-byte
+// boundaries.
+constexpr size_t kTablePoolEntries = (size_t)1 << 20;  // float2 entries, 8 MiB
+static __device__ __align__(256) float2 g_table_pool[kTablePoolEntries];
+
 static std::mutex g_tab_mu;
 static std::map<std::pair<int, std::string>, float2*> g_tab;  // (device, key)
+struct TablePool {
+  float2* base = nullptr;  // this device's copy of g_table_pool
+  size_t used = 0;         // entries handed out
+};
+static std::map<int, TablePool> g_pool;
 
 int cached_table(const char* key, std::vector<float2> (*make)(), const float2** out) {
   int dev = 0;
@@ -473,15 +485,20 @@ int cached_table(const char* key, std::vector<float2> (*make)(), const float2** 
     *out = it->second;
     return 0;
   }
-  std::vector<float2> h = make();
-  float2* d = nullptr;
-  e = hipMalloc(&d, h.size() * sizeof(float2));
-  if (e != hipSuccess) return (int)e;
-  e = hipMemcpy(d, h.data(), h.size() * sizeof(float2), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(d);
-    return (int)e;
+  TablePool& pool = g_pool[dev];
+  if (pool.base == nullptr) {
+    void* addr = nullptr;
+    e = hipGetSymbolAddress(&addr, HIP_SYMBOL(g_table_pool));
+    if (e != hipSuccess) return (int)e;
+    pool.base = (float2*)addr;
   }
+  std::vector<float2> h = make();
+  const size_t n = (h.size() + 31) & ~(size_t)31;
+  if (pool.used + n > kTablePoolEntries) return (int)hipErrorOutOfMemory;
+  float2* d = pool.base + pool.used;
+  e = hipMemcpy(d, h.data(), h.size() * sizeof(float2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return (int)e;
+  pool.used += n;
   g_tab[k] = d;
   *out = d;
   return 0;

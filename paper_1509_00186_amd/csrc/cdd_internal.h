@@ -117,6 +117,14 @@ int launch_multi_single(const BatchBeam* beams, const void* const* H, int nbeams
 int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_tab,
                  unsigned int* counter, void* stream);
 int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream);
+// The whole path for one beam and one tile of DM trials, every launch on the
+// one stream (workspace regions per ws_layout; xt_ready = an existing
+// channel-major copy or NULL).  timed: record stage events when profiling.
+cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
+                    const void* xt_ready, char* ws, const WsLayout& lay, float* chan_P,
+                    void* volt_out, float* intensity, int32_t* coverage, int64_t out_stride,
+                    void* stream, bool timed);
+cdd_status device_fail(const char* what, int err);
 // P[c][u] = sum of |x[c][u n_int + r]|^2, r < n_int (channel-major x).
 int launch_detect(const BeamPlan& p, const void* xt, float* P, void* stream);
 int launch_fold(const float* I, int64_t t_int, double period, double phase0, int32_t nbins,

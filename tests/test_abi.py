@@ -273,3 +273,27 @@ def test_fullband_entry_points_validate_without_device():
            ctypes.c_void_p(aligned), None, ctypes.byref(o))
     assert L.cdd_fullband_dedisperse(*bad, ctypes.c_void_p(aligned), 1 << 40, None) == -1
     assert "n_int" in L.cdd_last_error().decode()
+
+
+def test_noalloc_refuses_a_workspace_beyond_its_scratch_before_any_launch():
+    """cdd_dedisperse_noalloc checks the call's workspace against its static
+    scratch (CDD_NOALLOC_SCRATCH_BYTES) before touching the device, so the
+    refusal needs no GPU; pointers are never dereferenced on that path."""
+    cdd = _lib()
+    src = open(HEADER).read()
+    m = re.search(r"#define CDD_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", src)
+    cap = int(m.group(1)) << int(m.group(2))
+    # 4096 channels x 97,656 int8 samples: the channel-major copy alone is 800 MB
+    q = cdd.query(0, 97_656, 4096, 400.0, 200.0, 120.0, 8192, 4)
+    assert q["ws_bytes"] > cap
+    fake = ctypes.c_void_p(1 << 20)
+    st = cdd.lib.cdd_dedisperse_noalloc(fake, 0, 97_656, 4096, 400.0, 200.0, 120.0, 8192, 4,
+                                        fake, None, None, None, None, None)
+    assert st == -1
+    assert b"scratch" in cdd.lib.cdd_last_error()
+    # npol 2 is not taken
+    o = cdd._binding.make_opts(8192)
+    o.npol = 2
+    st = cdd.lib.cdd_dedisperse_noalloc(fake, 0, 1000, 4, 325.0, 0.25, 1.0, 8192, 4, fake, None,
+                                        None, None, ctypes.byref(o), None)
+    assert st == -7
