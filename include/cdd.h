@@ -128,7 +128,15 @@ typedef struct {
                               the delay-aligned sum (Sec. 4.3 and 4.5, one
                               polarisation per host, summed); N <= 16384,
                               nchan > 1, one time chunk, no voltages out   */
-  int32_t reserved[2];
+  int32_t chirp_in_kernel; /* cdd_plan_*: beams with one DM trial form their
+                              chirp inside the batched kernel like beams
+                              with several, instead of reading a table built
+                              per execute                                  */
+  int32_t single_launch;   /* cdd_plan_*: per round of DM tiles, every beam
+                              of length <= 8192 (per sample type) in one
+                              persistent launch after all layout changes,
+                              instead of one launch per beam pipelined
+                              behind the layout changes                    */
 } cdd_opts;
 
 /* Plan figures for one beam (filled by cdd_query / cdd_plan_info). */
@@ -319,7 +327,18 @@ cdd_status cdd_fullband_dedisperse(const void* spectra, int64_t nspec, int32_t n
  * forward transform of each (beam, channel, block) is computed once and
  * every DM trial reuses it; the chirp is generated on the fly per trial.
  * All trials of a beam share one (N, L, nfront), planned for the largest
- * |DM| of the beam (overlap rules as cdd_query over all its DMs).
+ * |DM| of the beam (overlap rules as cdd_query over all its DMs).  By
+ * default the layout change of each beam runs on a second stream and the
+ * beam's launch (the kernel specialised for its length: a persistent one
+ * over its DM tile, or one workgroup per block for a single DM) follows as
+ * soon as its input is in place, so the memory-bound layout changes of
+ * later beams run beside the transforms of earlier ones.  With
+ * opts->single_launch, every beam of length 256 .. 8192 (and one sample
+ * type) shares one persistent launch per round of DM tiles instead, longest
+ * work per workgroup first (that kernel holds the largest length's register
+ * budget, which lowers the occupancy of the short lengths).  A beam with a
+ * single DM reads its chirp from a table built once per execute unless
+ * opts->chirp_in_kernel asks for the in-kernel chirp.
  * ------------------------------------------------------------------- */
 typedef struct {
   const void* voltages;   /* device, layout as cdd_dedisperse               */
@@ -362,8 +381,9 @@ void cdd_plan_destroy(cdd_plan* plan);
  * input (the samples a block loses to overlap-save are prefixed to the next
  * block, Sec. 4.3) and the per-channel intensities still needed by the
  * delay-aligned sum.  A scheduler thread folds every block that is ready,
- * from every stream, into the next launch (one persistent launch per
- * transform length), so streams that arrive while others are on the GPU are
+ * from every stream, into the next launch (one persistent launch for every
+ * transform length up to 8192, one per longer length), so streams that
+ * arrive while others are on the GPU are
  * served as slots and memory free up, and their work overlaps on the device.
  * The result of a stream depends only on its own data and plan: the same
  * alone or in any mix, and equal to cdd_dedisperse on the whole record.

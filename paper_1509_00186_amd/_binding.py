@@ -31,7 +31,8 @@ class Opts(ctypes.Structure):
                 ("dm_const", ctypes.c_double), ("phase_mode", ctypes.c_int32),
                 ("kernel_variant", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("time_chunks", ctypes.c_int32), ("taper", ctypes.c_int32),
-                ("npol", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("npol", ctypes.c_int32), ("chirp_in_kernel", ctypes.c_int32),
+                ("single_launch", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -458,7 +459,8 @@ class Plan:
     """
 
     def __init__(self, beams, dm_const=0.0, phase_mode=0, fft_len=0, overlap=None,
-                 nfront=None, autotune=False, variant=0, taper="none"):
+                 nfront=None, autotune=False, variant=0, taper="none", chirp_in_kernel=False,
+                 single_launch=False):
         import torch
         self._descs = (BeamDesc * len(beams))()
         self._keep = []
@@ -482,6 +484,8 @@ class Plan:
             d.intensity, d.coverage = I.data_ptr(), cov.data_ptr()
         o = make_opts(fft_len, overlap, nfront, dm_const, phase_mode, variant=variant,
                       autotune=autotune, taper=taper)
+        o.chirp_in_kernel = int(bool(chirp_in_kernel))
+        o.single_launch = int(bool(single_launch))
         h = ctypes.c_void_p()
         _check(lib.cdd_plan_create(self._descs, len(beams), ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -1,4 +1,6 @@
 // C-ABI entry points: one-shot dedispersion and batched plans.
+#include <hip/hip_runtime.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -101,18 +103,39 @@ struct cdd_plan {
   size_t tab_off = 0, cnt_off = 0;
   int rounds = 0;
   size_t ws = 0;
+  int chirp_in_kernel = 0;       // one-DM beams form their chirp in the kernel
+  int single_launch = 0;         // every length up to 8192 in one launch per round
+  // Launch tables of every round in pinned host memory, copied into the
+  // workspace on each execute.  They are rewritten only when their contents
+  // change (another workspace), and then only once the previous execute's
+  // copies have run.
+  void* host_tab = nullptr;
+  size_t host_tab_bytes = 0;
+  hipEvent_t tab_done = nullptr;
+  bool tab_pending = false;
+  ~cdd_plan() {
+    if (tab_done) (void)hipEventDestroy(tab_done);
+    if (host_tab) (void)hipHostFree(host_tab);
+  }
 };
 
 namespace {
 constexpr size_t kPlanPBudget = (size_t)8 << 30;  // per-channel intensities held at once
+// launch kinds of the single-launch form: (lengths up to 8192; 16384 with
+// tables; 16384 in-kernel) x (int8, complex float)
+constexpr int kGroupKinds = 6;
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-bool one_dm(const BeamPlan& p) { return block_supported(p.N) && p.dms.size() == 1; }
+// Whether a beam reads a chirp table built per execute (one DM trial, unless
+// the plan forms every chirp in the kernel).
+bool table_chirp(const cdd_plan* pl, const BeamPlan& p) {
+  return block_supported(p.N) && p.dms.size() == 1 && !pl->chirp_in_kernel;
+}
 
 // DM tiles and workspace layout of a plan: each beam gets its own channel-major
-// copy, intensity and delay regions; then one launch table per round and the
-// work counter.
+// copy, intensity and delay regions (and its chirp table if it reads one);
+// then the launch tables of every round and the work counters.
 void layout_plan(cdd_plan* pl) {
   const size_t nb = pl->beams.size();
   pl->tile.assign(nb, 1);
@@ -120,25 +143,35 @@ void layout_plan(cdd_plan* pl) {
   pl->ws_base.assign(nb, 0);
   size_t off = 0;
   pl->rounds = 0;
+  // DM tiles: as many trials per launch as a beam has (up to kMaxDmTile),
+  // scaled down in proportion when the intensities of all tiles would exceed
+  // the budget
+  double need = 0;
+  for (size_t b = 0; b < nb; ++b) {
+    const BeamPlan& p = pl->beams[b];
+    if (block_supported(p.N))
+      need += (double)std::min((int)p.dms.size(), kMaxDmTile) * p.nchan * p.t_int * sizeof(float);
+  }
+  const double scale = need > (double)kPlanPBudget ? (double)kPlanPBudget / need : 1.0;
   for (size_t b = 0; b < nb; ++b) {
     const BeamPlan& p = pl->beams[b];
     const int ndm = (int)p.dms.size();
     int t = 1;
-    if (block_supported(p.N)) {
-      const size_t per_dm = (size_t)p.nchan * p.t_int * sizeof(float);
-      const size_t budget = kPlanPBudget / nb;
-      t = (int)std::min<size_t>((size_t)std::min(ndm, kMaxDmTile),
-                                std::max<size_t>(1, budget / std::max<size_t>(per_dm, 1)));
-    }
+    if (block_supported(p.N))
+      t = std::max(1, (int)std::floor(std::min(ndm, kMaxDmTile) * scale));
     pl->tile[b] = t;
-    // a one-DM beam takes the chirp from a table, like the one-shot call
-    pl->lay[b] = ws_layout(p, t, true, one_dm(p));
+    pl->lay[b] = ws_layout(p, t, true, table_chirp(pl, p));
     pl->ws_base[b] = off;
     off = align256(off + pl->lay[b].total);
     pl->rounds = std::max(pl->rounds, (ndm + t - 1) / t);
   }
+  // launch-table slots: one per beam and round (pipelined form) or one per
+  // launch kind and round (single-launch form), each big enough for all beams
   pl->tab_off = off;
-  off = align256(off + batch_table_bytes((int)nb) * (size_t)std::max(pl->rounds, 1));
+  pl->host_tab_bytes = align256(batch_table_bytes((int)nb)) *
+                       (size_t)std::max<size_t>(nb, kGroupKinds) *
+                       (size_t)std::max(pl->rounds, 1);
+  off = align256(off + pl->host_tab_bytes);
   pl->cnt_off = off;
   off = align256(off + 256);
   pl->ws = off;
@@ -354,6 +387,8 @@ cdd_status cdd_plan_create(const cdd_beam* beams, int32_t nbeam, const cdd_opts*
       copy.host_dms = nullptr;
       pl->desc.push_back(copy);
     }
+    pl->chirp_in_kernel = (opts && opts->chirp_in_kernel) ? 1 : 0;
+    pl->single_launch = (opts && opts->single_launch) ? 1 : 0;
     layout_plan(pl);
     *out = pl;
     clear_error();
@@ -385,6 +420,43 @@ cdd_status cdd_plan_info_get(const cdd_plan* plan, int32_t beam, cdd_plan_info* 
   return CDD_OK;
 }
 
+// Delays and aligned sums of beam b's tile of round r (and, for lengths above
+// the block kernel's, its four-step transforms first), on `stream`.
+static cdd_status finish_beam(cdd_plan* plan, char* ws, size_t b, int r, const void* xt,
+                              void* stream) {
+  const BeamPlan& p = plan->beams[b];
+  const cdd_beam& d = plan->desc[b];
+  const int i0 = r * plan->tile[b];
+  DmTile tile;
+  tile.ndm = std::max(0, std::min(plan->tile[b], (int)p.dms.size() - i0));
+  if (tile.ndm == 0) return CDD_OK;
+  for (int i = 0; i < tile.ndm; ++i) tile.dm[i] = p.dms[i0 + i];
+  char* wb = ws + plan->ws_base[b];
+  const WsLayout& lay = plan->lay[b];
+  float* P = (float*)(wb + lay.p_off);
+  void* tok = nullptr;
+  int e = 0;
+  if (!block_supported(p.N)) {
+    if ((e = stage_begin(kStageBlock, stream, &tok))) return device_fail("event record", e);
+    for (int i = 0; i < tile.ndm; ++i)
+      if ((e = launch_large(p, xt, tile.dm[i], wb + lay.s_off, (float*)(wb + lay.pb_off),
+                            P + (int64_t)i * p.nchan * p.t_int, nullptr, stream)))
+        return device_fail("long-transform launch", e);
+    if ((e = stage_end(kStageBlock, stream, tok))) return device_fail("event record", e);
+  }
+  int32_t* dl = (int32_t*)(wb + lay.d_off);
+  if ((e = stage_begin(kStageDelays, stream, &tok))) return device_fail("event record", e);
+  if ((e = launch_delays(p, tile, dl, stream))) return device_fail("delay launch", e);
+  if ((e = stage_end(kStageDelays, stream, tok))) return device_fail("event record", e);
+  if ((e = stage_begin(kStageDsum, stream, &tok))) return device_fail("event record", e);
+  if ((e = launch_dsum(p, tile.ndm, P, dl, d.intensity + (int64_t)i0 * p.t_int,
+                       d.coverage ? d.coverage + (int64_t)i0 * p.t_int : nullptr, p.t_int,
+                       stream)))
+    return device_fail("delay-sum launch", e);
+  if ((e = stage_end(kStageDsum, stream, tok))) return device_fail("event record", e);
+  return CDD_OK;
+}
+
 cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, void* stream) {
   try {
     if (!plan) return fail(CDD_EINVAL, "plan is NULL");
@@ -393,112 +465,171 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
     if (!aligned256(workspace)) return fail(CDD_EINVAL, "workspace must be 256-byte aligned");
     char* ws = (char*)workspace;
     const size_t nb = plan->beams.size();
-    std::vector<const void*> xt(nb, nullptr);
+    const size_t slot_bytes = align256(batch_table_bytes((int)nb));
+    const size_t slots_per_round = std::max<size_t>(nb, kGroupKinds);
     int e = 0;
-    // layout change once per beam
+    if (!plan->host_tab) {
+      hipError_t he = hipHostMalloc(&plan->host_tab, plan->host_tab_bytes);
+      if (he != hipSuccess) {
+        plan->host_tab = nullptr;
+        return device_fail("pinned launch tables", (int)he);
+      }
+      std::memset(plan->host_tab, 0, plan->host_tab_bytes);
+      if ((he = hipEventCreateWithFlags(&plan->tab_done, hipEventDisableTiming)) != hipSuccess)
+        return device_fail("event create", (int)he);
+    }
+    std::vector<const void*> xt(nb, nullptr);
+    std::vector<void*> H(nb, nullptr);
     for (size_t b = 0; b < nb; ++b) {
       const BeamPlan& p = plan->beams[b];
-      char* wb = ws + plan->ws_base[b];
-      if (p.nchan > 1) {
-        if ((e = launch_transposed(p, plan->desc[b].voltages, wb + plan->lay[b].xt_off, stream)))
-          return device_fail("transpose launch", e);
-        xt[b] = wb + plan->lay[b].xt_off;
-      } else {
-        xt[b] = plan->desc[b].voltages;
-      }
+      xt[b] = p.nchan > 1 ? (const void*)(ws + plan->ws_base[b] + plan->lay[b].xt_off)
+                          : plan->desc[b].voltages;
+      if (table_chirp(plan, p)) H[b] = ws + plan->ws_base[b] + plan->lay[b].h_off;
     }
-    std::vector<BatchBeam> group;
-    std::vector<std::vector<char>> host_tabs;  // kept until return
+    auto tile_of = [&](size_t b, int r, BatchBeam* bb) {
+      const BeamPlan& p = plan->beams[b];
+      const int i0 = r * plan->tile[b];
+      const int ndm = std::max(0, std::min(plan->tile[b], (int)p.dms.size() - i0));
+      bb->p = &p;
+      bb->xt = xt[b];
+      bb->dms.ndm = ndm;
+      for (int i = 0; i < ndm; ++i) bb->dms.dm[i] = p.dms[i0 + i];
+      bb->P = (float*)(ws + plan->ws_base[b] + plan->lay[b].p_off);
+      bb->co = offline_coords(p);
+      return ndm;
+    };
+    // Every block-kernel launch of the execute with its argument table, formed
+    // on the host first.  Pipelined form (default): one launch per beam and
+    // round, the specialised kernel of the beam's length.  Single-launch form:
+    // per round, every beam of length <= 8192 and one sample type in one
+    // persistent launch, the 16384-point beams in one more per kind.
+    struct Launch {
+      LaunchDesc d;
+      size_t slot = 0;
+      int round = 0;
+      size_t beam = 0;  // pipelined form
+    };
+    std::vector<Launch> launches;
+    std::vector<char> staged(plan->host_tab_bytes, 0);
+    // beams in the order their inputs are ready: shortest layout change first
+    std::vector<size_t> order(nb);
+    for (size_t b = 0; b < nb; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+      auto bytes = [&](size_t b) {
+        const BeamPlan& p = plan->beams[b];
+        return p.nchan > 1 ? (double)p.nchan * p.nsamp * (p.dtype == CDD_CI8 ? 2 : 8) : 0.0;
+      };
+      return bytes(x) < bytes(y);
+    });
     for (int r = 0; r < plan->rounds; ++r) {
-      // tiles of this round
-      std::vector<DmTile> tiles(nb);
-      for (size_t b = 0; b < nb; ++b) {
-        const BeamPlan& p = plan->beams[b];
-        const int i0 = r * plan->tile[b];
-        tiles[b].ndm = std::max(0, std::min(plan->tile[b], (int)p.dms.size() - i0));
-        for (int i = 0; i < tiles[b].ndm; ++i) tiles[b].dm[i] = p.dms[i0 + i];
-      }
-      // per transform length: one launch over the one-DM beams (chirp tables)
-      // and one persistent launch over the beams with DM tiles
-      std::vector<bool> done(nb, false);
-      void* tab_dev = ws + plan->tab_off + batch_table_bytes((int)nb) * (size_t)r;
-      size_t tab_used = 0;
-      for (size_t b0 = 0; b0 < nb; ++b0) {
-        if (done[b0] || tiles[b0].ndm == 0 || !block_supported(plan->beams[b0].N)) continue;
-        const bool single = one_dm(plan->beams[b0]);
-        group.clear();
-        std::vector<const void*> H;
-        for (size_t b = b0; b < nb; ++b) {
-          if (done[b] || tiles[b].ndm == 0 || plan->beams[b].N != plan->beams[b0].N ||
-              one_dm(plan->beams[b]) != single)
-            continue;
-          done[b] = true;
-          if (single) {
-            char* h = ws + plan->ws_base[b] + plan->lay[b].h_off;
-            if ((e = launch_chirp_table(plan->beams[b], tiles[b].dm[0], h, stream)))
-              return device_fail("chirp table launch", e);
-            H.push_back(h);
-          }
+      if (!plan->single_launch) {
+        for (size_t j = 0; j < nb; ++j) {
+          const size_t b = order[j];
           BatchBeam bb;
-          bb.p = &plan->beams[b];
-          bb.xt = xt[b];
-          bb.dms = tiles[b];
-          bb.P = (float*)(ws + plan->ws_base[b] + plan->lay[b].p_off);
-          bb.co = offline_coords(plan->beams[b]);
-          group.push_back(bb);
+          if (!block_supported(plan->beams[b].N) || tile_of(b, r, &bb) == 0) continue;
+          Launch L;
+          L.round = r;
+          L.beam = b;
+          L.slot = slot_bytes * ((size_t)r * slots_per_round + j);
+          const void* h = H[b];
+          if ((e = prepare_launch(h ? kLaunchTables : kLaunchBatch, &bb, &h, 1,
+                                  staged.data() + L.slot, &L.d)))
+            return device_fail("launch table", e);
+          launches.push_back(L);
         }
-        host_tabs.emplace_back(batch_table_bytes((int)group.size()), 0);
-        void* tok = nullptr;
-        if ((e = stage_begin(kStageBlock, stream, &tok))) return device_fail("event record", e);
-        if (single) {
-          if ((e = launch_multi_single(group.data(), H.data(), (int)group.size(),
-                                       host_tabs.back().data(), (char*)tab_dev + tab_used,
-                                       stream)))
-            return device_fail("multi-beam launch", e);
-        } else {
-          // longest work first
-          std::stable_sort(group.begin(), group.end(),
-                           [](const BatchBeam& x, const BatchBeam& y) {
-                             return x.dms.ndm > y.dms.ndm;
-                           });
-          if ((e = launch_batch(group.data(), (int)group.size(), host_tabs.back().data(),
-                                (char*)tab_dev + tab_used,
-                                (unsigned int*)(ws + plan->cnt_off), stream)))
-            return device_fail("batched launch", e);
-        }
-        if ((e = stage_end(kStageBlock, stream, tok))) return device_fail("event record", e);
-        tab_used += batch_table_bytes((int)group.size());
+        continue;
       }
-      // long transforms, then delays and aligned sums per beam
+      std::vector<BatchBeam> group[kGroupKinds];
+      std::vector<const void*> gh[kGroupKinds];
       for (size_t b = 0; b < nb; ++b) {
-        if (tiles[b].ndm == 0) continue;
         const BeamPlan& p = plan->beams[b];
-        const cdd_beam& d = plan->desc[b];
-        char* wb = ws + plan->ws_base[b];
-        const WsLayout& lay = plan->lay[b];
-        float* P = (float*)(wb + lay.p_off);
-        void* tok = nullptr;
-        if (!block_supported(p.N)) {
-          if ((e = stage_begin(kStageBlock, stream, &tok))) return device_fail("event record", e);
-          for (int i = 0; i < tiles[b].ndm; ++i)
-            if ((e = launch_large(p, xt[b], tiles[b].dm[i], wb + lay.s_off,
-                                  (float*)(wb + lay.pb_off), P + (int64_t)i * p.nchan * p.t_int,
-                                  nullptr, stream)))
-              return device_fail("long-transform launch", e);
-          if ((e = stage_end(kStageBlock, stream, tok))) return device_fail("event record", e);
-        }
-        int32_t* dl = (int32_t*)(wb + lay.d_off);
-        const int64_t i0 = (int64_t)r * plan->tile[b];
-        if ((e = stage_begin(kStageDelays, stream, &tok))) return device_fail("event record", e);
-        if ((e = launch_delays(p, tiles[b], dl, stream))) return device_fail("delay launch", e);
-        if ((e = stage_end(kStageDelays, stream, tok))) return device_fail("event record", e);
-        if ((e = stage_begin(kStageDsum, stream, &tok))) return device_fail("event record", e);
-        if ((e = launch_dsum(p, tiles[b].ndm, P, dl, d.intensity + i0 * p.t_int,
-                             d.coverage ? d.coverage + i0 * p.t_int : nullptr, p.t_int, stream)))
-          return device_fail("delay-sum launch", e);
-        if ((e = stage_end(kStageDsum, stream, tok))) return device_fail("event record", e);
+        BatchBeam bb;
+        if (!block_supported(p.N) || tile_of(b, r, &bb) == 0) continue;
+        const int kind =
+            mixed_supported(p.N) ? kLaunchMixed : (H[b] ? kLaunchTables : kLaunchBatch);
+        const int k = kind * 2 + (p.dtype == CDD_CI8 ? 0 : 1);
+        group[k].push_back(bb);
+        gh[k].push_back(H[b]);
+      }
+      for (int k = 0; k < kGroupKinds; ++k) {
+        if (group[k].empty()) continue;
+        Launch L;
+        L.round = r;
+        L.slot = slot_bytes * ((size_t)r * slots_per_round + k);
+        if ((e = prepare_launch(k / 2, group[k].data(), gh[k].data(), (int)group[k].size(),
+                                staged.data() + L.slot, &L.d)))
+          return device_fail("launch table", e);
+        launches.push_back(L);
       }
     }
+    // Publish the tables into the pinned buffer if they changed; a rewrite
+    // first waits for the previous execute's copies out of it.
+    if (std::memcmp(plan->host_tab, staged.data(), plan->host_tab_bytes) != 0) {
+      if (plan->tab_pending) {
+        hipError_t he = hipEventSynchronize(plan->tab_done);
+        if (he != hipSuccess) return device_fail("launch table wait", (int)he);
+      }
+      std::memcpy(plan->host_tab, staged.data(), plan->host_tab_bytes);
+    }
+    unsigned int* counter = (unsigned int*)(ws + plan->cnt_off);  // launches share one stream
+    auto enqueue = [&](const Launch& L) -> cdd_status {
+      void* tok = nullptr;
+      int err = 0;
+      if ((err = stage_begin(kStageBlock, stream, &tok))) return device_fail("event record", err);
+      if ((err = enqueue_launch(L.d, (char*)plan->host_tab + L.slot, ws + plan->tab_off + L.slot,
+                                counter, stream)))
+        return device_fail("batched launch", err);
+      if ((err = stage_end(kStageBlock, stream, tok))) return device_fail("event record", err);
+      return CDD_OK;
+    };
+    // Round 0: the layout change (and chirp table) of each beam on the
+    // auxiliary stream, in the order above; in the pipelined form each beam's
+    // launch follows on the caller's stream as soon as its input is in place,
+    // so later beams' layout changes run beside earlier beams' transforms.
+    AuxSession aux;
+    if ((e = aux_open(stream, &aux))) return device_fail("auxiliary stream", e);
+    size_t li = 0;
+    cdd_status st = CDD_OK;
+    for (size_t j = 0; j < nb && st == CDD_OK; ++j) {
+      const size_t b = order[j];
+      const BeamPlan& p = plan->beams[b];
+      int err = 0;
+      void* tok = nullptr;
+      if (H[b]) {
+        if ((err = stage_begin(kStageDelays, aux.aux, &tok)) ||
+            (err = launch_chirp_table(p, p.dms[0], H[b], aux.aux)) ||
+            (err = stage_end(kStageDelays, aux.aux, tok))) {
+          st = device_fail("chirp table launch", err);
+          break;
+        }
+      }
+      if (p.nchan > 1 && (err = launch_transposed(p, plan->desc[b].voltages, (void*)xt[b],
+                                                  aux.aux))) {
+        st = device_fail("transpose launch", err);
+        break;
+      }
+      if (plan->single_launch) continue;
+      if ((err = aux_mark(&aux, stream))) {
+        st = device_fail("stream wait", err);
+        break;
+      }
+      while (st == CDD_OK && li < launches.size() && launches[li].round == 0 &&
+             launches[li].beam == b)
+        st = enqueue(launches[li++]);
+      if (st == CDD_OK) st = finish_beam(plan, ws, b, 0, xt[b], stream);
+    }
+    const int ce = aux_close(stream, &aux);
+    if (st != CDD_OK) return st;
+    if (ce) return device_fail("auxiliary stream", ce);
+    for (int r = plan->single_launch ? 0 : 1; r < plan->rounds; ++r) {
+      while (li < launches.size() && launches[li].round == r)
+        if ((st = enqueue(launches[li++])) != CDD_OK) return st;
+      for (size_t j = 0; j < nb; ++j)
+        if ((st = finish_beam(plan, ws, order[j], r, xt[order[j]], stream)) != CDD_OK) return st;
+    }
+    hipError_t he = hipEventRecord(plan->tab_done, (hipStream_t)stream);
+    if (he != hipSuccess) return device_fail("event record", (int)he);
+    plan->tab_pending = true;
     clear_error();
     return CDD_OK;
   } catch (const std::bad_alloc&) {

@@ -21,6 +21,7 @@
 // time; inter-pass twiddles come from tables computed on the host in FP64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -81,7 +82,8 @@ struct BlockArgs {
   int64_t v_stride, o_lim;
   int64_t nblocks, item0;   // blocks per channel; first work item of this beam
   int32_t nchan, M, nfront, n_int, dtype, phase_mode, exact_div, taper;
-  int32_t accum, pad;   // accum: add to P instead of storing (second polarisation)
+  int32_t accum;        // add to P instead of storing (second polarisation)
+  int32_t lgn;          // log2 N (mixed launches switch on it)
   double f_lo, df, dconst;
   DmTile dms;
 };
@@ -249,10 +251,10 @@ __device__ __forceinline__ void load_block(float2* v, const BlockArgs& a, int c,
 
 template <class S, bool VOUT>
 __device__ __forceinline__ void epilogue(const float2* v, float* lds, const BlockArgs& a, int c,
-                                         int64_t k, int dmi, int t) {
+                                         int64_t k, int dmi, int t, bool live = true) {
   constexpr int N = S::N, R = S::rad_i(S::NP - 1), BPT = N / (R * S::T);
   if constexpr (VOUT) {
-    if (a.vout) {
+    if (a.vout && live) {
 #pragma unroll
       for (int b = 0; b < BPT; ++b) {
 #pragma unroll
@@ -278,6 +280,7 @@ __device__ __forceinline__ void epilogue(const float2* v, float* lds, const Bloc
     }
   }
   __syncthreads();
+  if (!live) return;  // a workgroup's spare transform: its barriers only
   const int nu = a.M / a.n_int;
   const int64_t u0 = k * (a.M / a.n_int);
   float* P = a.P + (int64_t)dmi * a.p_dm_stride + (int64_t)c * a.p_stride;
@@ -303,7 +306,7 @@ __device__ __forceinline__ void epilogue(const float2* v, float* lds, const Bloc
 
 template <class S, int DT, bool MULTI>
 __device__ __forceinline__ void process_item(const BlockArgs& a, int c, int64_t k, float* lds,
-                                             int t) {
+                                             int t, bool live = true) {
   const double fc = a.f_lo + ((double)c + 0.5) * a.df;
   float2 v[S::E];
   load_block<S, DT>(v, a, c, k, t);
@@ -314,7 +317,7 @@ __device__ __forceinline__ void process_item(const BlockArgs& a, int c, int64_t 
     asm volatile("" : "+v"(tt));
     chirp_from_table<S>(v, a.H + (int64_t)c * S::N, tt);
     fft_inverse<S>(v, lds, a.tw, tt);
-    epilogue<S, true>(v, lds, a, c, k, 0, tt);
+    epilogue<S, true>(v, lds, a, c, k, 0, tt, live);
   } else {
     // The taper depends on the bin only: it scales the shared spectrum once,
     // and the per-trial chirp is a pure rotation.
@@ -334,7 +337,7 @@ __device__ __forceinline__ void process_item(const BlockArgs& a, int c, int64_t 
       for (int e = 0; e < S::E; ++e) v[e] = X[e];
       apply_chirp<S>(v, a.dms.dm[i], fc, a, tt);
       fft_inverse<S>(v, lds, a.tw, tt);
-      epilogue<S, false>(v, lds, a, c, k, i, tt);
+      epilogue<S, false>(v, lds, a, c, k, i, tt, live);
     }
   }
 }
@@ -362,11 +365,13 @@ __global__ __launch_bounds__(S::T, MULTI ? (S::MINB + 1) / 2 : S::MINB) void blo
   process_item<S, DT, MULTI>(a, c, k, lds, threadIdx.x);
 }
 
-// Persistent form for several beams sharing one transform length: a grid
-// sized to the machine pulls work items (beam, channel, block) from a
-// counter until all are taken; beams are listed longest work first.  Every
-// wave leaves the loop once the counter passes the item count.
-template <class S>
+// Persistent form for several beams sharing one transform length and sample
+// type (one instantiation per type: a run-time switch between the two load
+// paths makes the register allocator spill): a grid sized to the machine
+// pulls work items (beam, channel, block) from a counter until all are
+// taken; beams are listed longest work first.  Every wave leaves the loop
+// once the counter passes the item count.
+template <class S, int DT>
 __global__ __launch_bounds__(S::T, (S::MINB + 1) / 2) void batch_kernel(
     const BlockArgs* __restrict__ beams, int32_t nbeams, int64_t total,
     unsigned int* __restrict__ counter) {
@@ -375,7 +380,9 @@ __global__ __launch_bounds__(S::T, (S::MINB + 1) / 2) void batch_kernel(
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
     __syncthreads();
-    const int64_t item = s_item;
+    // uniform across the workgroup: kept in a scalar register, so the beam's
+    // arguments below are scalar loads and stay out of the vector registers
+    const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (item >= total) break;
     int b = 0;
@@ -384,10 +391,12 @@ __global__ __launch_bounds__(S::T, (S::MINB + 1) / 2) void batch_kernel(
     const int64_t local = item - a.item0;
     const int c = (int)(local / a.nblocks);
     const int64_t k = local - (int64_t)c * a.nblocks;
-    if (a.dtype == CDD_CI8)
-      process_item<S, CDD_CI8, true>(a, c, k, lds, threadIdx.x);
-    else
-      process_item<S, CDD_CF32, true>(a, c, k, lds, threadIdx.x);
+    // an opaque copy of the thread index per item keeps the compiler from
+    // hoisting per-thread index math out of this loop (and holding it in
+    // registers across it)
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    process_item<S, DT, true>(a, c, k, lds, t);
   }
 }
 
@@ -395,7 +404,7 @@ __global__ __launch_bounds__(S::T, (S::MINB + 1) / 2) void batch_kernel(
 // per (beam, channel, block) over the concatenated items (beams listed with
 // their first item), XCD-aware as block_kernel; each beam's chirp comes from
 // its own table.
-template <class S>
+template <class S, int DT>
 __global__ __launch_bounds__(S::T, S::MINB) void multi_single_kernel(
     const BlockArgs* __restrict__ beams, int32_t nbeams, int64_t total) {
   __shared__ __align__(16) float lds[S::lds_floats()];
@@ -406,53 +415,154 @@ __global__ __launch_bounds__(S::T, S::MINB) void multi_single_kernel(
   const int64_t local = item - a.item0;
   const int c = (int)(local / a.nblocks);
   const int64_t k = local - (int64_t)c * a.nblocks;
-  if (a.dtype == CDD_CI8)
-    process_item<S, CDD_CI8, false>(a, c, k, lds, threadIdx.x);
+  process_item<S, DT, false>(a, c, k, lds, threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// One persistent launch for beams of different transform lengths
+// ---------------------------------------------------------------------------
+// Workgroups of kMixT threads; a length whose schedule has T < kMixT threads
+// runs G = kMixT / T transforms side by side, each on its own slice of the
+// LDS.  A unit of work is G consecutive (channel, block) items of one beam;
+// the last unit of a beam may hold fewer items, and its spare transforms run
+// on a valid block without storing anything (they keep the workgroup's
+// barriers in step).  Beams are listed longest work per unit first; the
+// workgroups pull units from a counter until none are left, and every wave
+// leaves the loop once the counter passes the unit count.
+constexpr int kMixT = 256;
+template <int N>
+struct MixSchedOf {
+  using type = typename SchedFor<N, 0>::type;
+};
+// 4096 with 256 threads (its default 128-thread schedule prefetches twiddles
+// and needs more registers than the one-DM budget holds)
+template <>
+struct MixSchedOf<4096> {
+  using type = typename SchedFor<4096, 3>::type;
+};
+template <int N>
+using MixSched = typename MixSchedOf<N>::type;
+template <class S>
+constexpr int mix_lds_floats() {
+  return (kMixT / S::T) * S::lds_floats();
+}
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kMixLds =
+    cmax(cmax(cmax(mix_lds_floats<MixSched<256>>(), mix_lds_floats<MixSched<512>>()),
+              cmax(mix_lds_floats<MixSched<1024>>(), mix_lds_floats<MixSched<2048>>())),
+         cmax(mix_lds_floats<MixSched<4096>>(), mix_lds_floats<MixSched<8192>>()));
+constexpr bool mix_len_ok(int lg) { return lg >= 8 && lg <= 13; }
+static_assert(MixSched<8192>::T == kMixT && MixSched<256>::T <= kMixT, "mixed schedules");
+
+template <class S, int DT, bool MULTI>
+__device__ __forceinline__ void mix_unit(const BlockArgs& a, int64_t unit, float* lds) {
+  constexpr int G = kMixT / S::T;
+  static_assert(G * S::T == kMixT, "schedule threads must divide the workgroup");
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));  // per-unit opaque copy (see batch_kernel)
+  const int g = tid / S::T, t = tid - g * S::T;
+  const int64_t items = (int64_t)a.nchan * a.nblocks;
+  int64_t item = unit * G + g;
+  const bool live = item < items;
+  if (!live) item = 0;  // a valid block, nothing stored
+  const int c = (int)(item / a.nblocks);
+  const int64_t k = item - (int64_t)c * a.nblocks;
+  float* my = lds + g * S::lds_floats();
+  if (MULTI && a.H == nullptr)
+    process_item<S, DT, true>(a, c, k, my, t, live);
   else
-    process_item<S, CDD_CF32, false>(a, c, k, lds, threadIdx.x);
+    process_item<S, DT, false>(a, c, k, my, t, live);
+}
+
+// MULTI: some beam carries DM trials or generates its one-DM chirp in the
+// kernel (register budget of the batched path); otherwise every beam reads
+// its chirp table (register budget of the one-DM path).  DT: the sample type
+// of every beam in the launch.
+template <bool MULTI, int DT>
+__global__ __launch_bounds__(kMixT, MULTI ? 2 : 3) void mixed_kernel(
+    const BlockArgs* __restrict__ beams, int32_t nbeams, int64_t total,
+    unsigned int* __restrict__ counter) {
+  __shared__ __align__(16) float lds[kMixLds];
+  __shared__ unsigned int s_unit;
+  for (;;) {
+    if (threadIdx.x == 0) s_unit = atomicAdd(counter, 1u);
+    __syncthreads();
+    const int64_t unit = (int64_t)__builtin_amdgcn_readfirstlane(s_unit);  // scalar (see above)
+    __syncthreads();
+    if (unit >= total) break;
+    int b = 0;
+    while (b + 1 < nbeams && unit >= beams[b + 1].item0) ++b;
+    const BlockArgs& a = beams[b];
+    const int64_t u = unit - a.item0;
+    switch (a.lgn) {
+      case 8: mix_unit<MixSched<256>, DT, MULTI>(a, u, lds); break;
+      case 9: mix_unit<MixSched<512>, DT, MULTI>(a, u, lds); break;
+      case 10: mix_unit<MixSched<1024>, DT, MULTI>(a, u, lds); break;
+      case 11: mix_unit<MixSched<2048>, DT, MULTI>(a, u, lds); break;
+      case 12: mix_unit<MixSched<4096>, DT, MULTI>(a, u, lds); break;
+      default: mix_unit<MixSched<8192>, DT, MULTI>(a, u, lds); break;
+    }
+  }
 }
 
 __global__ void zero_counter_kernel(unsigned int* c) { *c = 0u; }
 
 // Chirp table of one DM: H[c*N + i] = exp(-2 pi i q)/N for bin i of channel c
 // (signed bin s = i or i - N, offset f = s*df/N from the channel centre fc),
-// q = D*DM*f^2/(fc^2 (fc + f)) turns (Eq. 3).  q (up to ~1e5 turns) and its
-// reduction r = q - rint(q) to [-1/2, 1/2] turns are FP64 with an exact
-// division; sin/cos of 2 pi r are FP32.  The FP32 phase mode forms q itself
-// in FP32 (precision study).  The taper (Sec. 2.2) scales the entry with the
-// 1/N of the inverse transform.
+// q = D*DM*f^2/(fc^2 (fc + f)) turns (Eq. 3), evaluated in FP64 exactly as
+// apply_chirp does -- q = B s^2 / (1 + beta s) with B = D*DM*(df/N)^2/fc^3 and
+// beta = (df/N)/fc, the division replaced by the series s^2 (B - B beta s +
+// B beta^2 s^2) where its truncation is negligible (exact_div = 0) -- so the
+// table and the in-kernel chirp give the same numbers.  The channel
+// constants are formed once per thread for kpt entries of one channel.  The
+// reduction r = q - rint(q) to [-1/2, 1/2] turns is FP64; sin/cos of 2 pi r
+// are FP32.  The FP32 phase mode forms q itself in FP32 (precision study).
+// The taper (Sec. 2.2) scales the entry with the 1/N of the inverse transform.
 __global__ __launch_bounds__(256) void chirp_table_kernel(float2* __restrict__ H, int32_t lgN,
-                                                          int32_t nchan, double f_lo, double df,
+                                                          int32_t kpt, double f_lo, double df,
                                                           double dconst, double dm,
-                                                          int32_t phase_mode, int32_t taper) {
-  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (g >= ((int64_t)nchan << lgN)) return;
+                                                          int32_t phase_mode, int32_t taper,
+                                                          int32_t exact_div) {
   const int N = 1 << lgN;
-  const int c = (int)(g >> lgN);
-  const int i = (int)(g & (N - 1));
-  const int s = i < N / 2 ? i : i - N;
+  const int per_wg = 256 * kpt;
+  const int bpc = N / per_wg;                       // workgroups per channel
+  const int c = (int)(blockIdx.x / bpc);
+  const int i0 = (int)(blockIdx.x - (unsigned)c * bpc) * per_wg + threadIdx.x;
   const double fc = f_lo + ((double)c + 0.5) * df;
-  float2 h;
+  const float inv_n = ldexpf(1.0f, -lgN);
+  float2* row = H + ((int64_t)c << lgN);
   if (phase_mode == CDD_PHASE_FP64_REDUCED) {
-    const double f = (double)s * (df / (double)N);
-    const double q = dconst * dm * (f * f) / (fc * fc * (fc + f));
-    // r in [-1/2, 1/2] turns: the hardware sine and cosine take turns
-    // (absolute error about 1.2e-7)
-    const float r = (float)(q - rint(q));
-    const float inv_n = ldexpf(1.0f, -lgN);
-    const float gn = taper_gain<false>(taper, (float)s * inv_n) * inv_n;
-    h = make_float2(__builtin_amdgcn_cosf(r) * gn, -__builtin_amdgcn_sinf(r) * gn);
+    const double dfn = df / (double)N;
+    const double B = dconst * dm * dfn * dfn / (fc * fc * fc);  // turns
+    const double beta = dfn / fc;
+    const double Bb = B * beta, Bbb = Bb * beta;
+    for (int k = 0; k < kpt; ++k) {
+      const int i = i0 + 256 * k;
+      const int s = i < N / 2 ? i : i - N;
+      const double sd = (double)s;
+      const double q = exact_div ? (B * (sd * sd)) / fma(beta, sd, 1.0)
+                                 : (sd * sd) * fma(sd, fma(sd, Bbb, -Bb), B);
+      // r in [-1/2, 1/2] turns: the hardware sine and cosine take turns
+      // (absolute error about 1.2e-7)
+      const float r = (float)(q - rint(q));
+      const float gn = taper_gain<false>(taper, (float)s * inv_n) * inv_n;
+      row[i] = make_float2(__builtin_amdgcn_cosf(r) * gn, -__builtin_amdgcn_sinf(r) * gn);
+    }
   } else {
     const float fcf = (float)fc;
     const float Af = (float)(dconst * dm) / (fcf * fcf);
-    const float f = (float)s * ((float)df / (float)N);
-    const float q = Af * (f * f) / (fcf + f);
-    float sn, cs;
-    sincospif(2.0f * q, &sn, &cs);
-    const float gn = taper_gain<false>(taper, (float)s / (float)N) / (float)N;
-    h = make_float2(cs * gn, -sn * gn);
+    const float dff = (float)df * inv_n;
+    for (int k = 0; k < kpt; ++k) {
+      const int i = i0 + 256 * k;
+      const int s = i < N / 2 ? i : i - N;
+      const float f = (float)s * dff;
+      const float q = Af * (f * f) / (fcf + f);
+      float sn, cs;
+      sincospif(2.0f * q, &sn, &cs);
+      const float gn = taper_gain<false>(taper, (float)s * inv_n) * inv_n;
+      row[i] = make_float2(cs * gn, -sn * gn);
+    }
   }
-  H[g] = h;
 }
 
 // ---------------------------------------------------------------------------
@@ -553,6 +663,8 @@ static BlockArgs make_args(const BeamPlan& p, const Coords& co, const void* xt, 
   a.nblocks = co.nblocks;
   a.accum = co.accum;
   a.item0 = 0;
+  a.lgn = 0;
+  while ((1 << a.lgn) < p.N) ++a.lgn;
   a.nchan = p.nchan;
   a.M = p.M;
   a.nfront = p.nfront;
@@ -566,6 +678,34 @@ static BlockArgs make_args(const BeamPlan& p, const Coords& co, const void* xt, 
   a.dconst = p.dconst;
   a.dms = dms;
   return a;
+}
+
+// Workgroups of a persistent kernel that fit on the device at once, per
+// (device, kernel), computed once under a lock (callers on several threads
+// may launch at the same time).
+static std::mutex g_occ_mu;
+static std::map<std::pair<int, const void*>, int64_t> g_occ;
+
+static int resident_workgroups(const void* fn, int threads, int64_t* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  auto key = std::make_pair(dev, fn);
+  auto it = g_occ.find(key);
+  if (it != g_occ.end()) {
+    *out = it->second;
+    return 0;
+  }
+  int ncu = 0, per_cu = 0;
+  if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return (int)e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0)) != hipSuccess)
+    return (int)e;
+  const int64_t n = (int64_t)std::max(ncu, 1) * std::max(per_cu, 1);
+  g_occ[key] = n;
+  *out = n;
+  return 0;
 }
 
 template <int N, int V>
@@ -589,59 +729,9 @@ static int launch_block_t(const BlockArgs& a0, void* stream) {
   return (int)hipGetLastError();
 }
 
-// Persistent batched launch; host_tab is pinned host memory that stays
-// unchanged while the copy is in flight, dev_tab and counter are device memory.
-template <int N, int V>
-static int launch_batch_t(BlockArgs* host_tab, int nbeams, int64_t total, BlockArgs* dev_tab,
-                          unsigned int* counter, void* stream) {
-  using S = typename SchedFor<N, V>::type;
-  const float2* tw = nullptr;
-  int err = twiddles_of<S>(&tw);
-  if (err) return err;
-  for (int b = 0; b < nbeams; ++b) host_tab[b].tw = tw;
-  hipStream_t st = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(dev_tab, host_tab, sizeof(BlockArgs) * nbeams,
-                                hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, st, counter);
-  static int per_cu = 0;
-  static int ncu = 0;
-  if (per_cu == 0) {
-    int dev = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return (int)e;
-    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) !=
-        hipSuccess)
-      return (int)e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<S>, S::T, 0)) !=
-        hipSuccess)
-      return (int)e;
-    if (per_cu < 1) per_cu = 1;
-  }
-  const int64_t grid = std::min<int64_t>(total, (int64_t)ncu * per_cu);
-  if (grid <= 0) return 0;
-  hipLaunchKernelGGL(batch_kernel<S>, dim3((unsigned)grid), dim3(S::T), 0, st, dev_tab, nbeams,
-                     total, counter);
-  return (int)hipGetLastError();
-}
-
-template <int N>
-static int launch_multi_single_t(BlockArgs* host_tab, int nbeams, int64_t total,
-                                 BlockArgs* dev_tab, void* stream) {
-  using S = typename SchedFor<N, 0>::type;
-  const float2* tw = nullptr;
-  int err = twiddles_of<S>(&tw);
-  if (err) return err;
-  for (int b = 0; b < nbeams; ++b) host_tab[b].tw = tw;
-  hipStream_t st = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(dev_tab, host_tab, sizeof(BlockArgs) * nbeams,
-                                hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return (int)e;
-  if (total <= 0) return 0;
-  hipLaunchKernelGGL(multi_single_kernel<S>, dim3((unsigned)total), dim3(S::T), 0, st, dev_tab,
-                     nbeams, total);
-  return (int)hipGetLastError();
-}
-
+// Persistent batched launch; host_tab must stay unchanged until the copy has
+// run (the plan and the server keep it for that long), dev_tab and counter
+// are device memory.
 static int log2i(int n) {
   int l = 0;
   while ((1 << l) < n) ++l;
@@ -703,84 +793,239 @@ int launch_block_co(const BeamPlan& p, const Coords& co, const void* xt, const D
 
 size_t batch_table_bytes(int nbeams) { return sizeof(BlockArgs) * (size_t)nbeams; }
 
-int launch_multi_single(const BatchBeam* beams, const void* const* H, int nbeams,
-                        void* host_tab, void* dev_tab, void* stream) {
-  if (nbeams < 1) return 0;
-  const int N = beams[0].p->N;
-  BlockArgs* ht = (BlockArgs*)host_tab;
-  int64_t total = 0;
-  for (int b = 0; b < nbeams; ++b) {
-    const BeamPlan& p = *beams[b].p;
-    if (p.N != N || beams[b].dms.ndm != 1 || H[b] == nullptr) return (int)hipErrorInvalidValue;
-    ht[b] = make_args(p, beams[b].co, beams[b].xt, beams[b].dms, beams[b].P, nullptr,
-                      (const float2*)H[b]);
-    ht[b].item0 = total;
-    total += (int64_t)p.nchan * beams[b].co.nblocks;
-  }
-  if (total > 0x7fffffffLL) return (int)hipErrorInvalidValue;
-  BlockArgs* dt = (BlockArgs*)dev_tab;
-  switch (N) {
-    case 256: return launch_multi_single_t<256>(ht, nbeams, total, dt, stream);
-    case 512: return launch_multi_single_t<512>(ht, nbeams, total, dt, stream);
-    case 1024: return launch_multi_single_t<1024>(ht, nbeams, total, dt, stream);
-    case 2048: return launch_multi_single_t<2048>(ht, nbeams, total, dt, stream);
-    case 4096: return launch_multi_single_t<4096>(ht, nbeams, total, dt, stream);
-    case 8192: return launch_multi_single_t<8192>(ht, nbeams, total, dt, stream);
-    case 16384: return launch_multi_single_t<16384>(ht, nbeams, total, dt, stream);
-  }
-  return (int)hipErrorInvalidValue;
-}
-
 size_t chirp_table_bytes(const BeamPlan& p) {
   return block_supported(p.N) ? (size_t)p.nchan * p.N * sizeof(float2) : 0;
 }
 
 int launch_chirp_table(const BeamPlan& p, double dm, void* H, void* stream) {
   if (!block_supported(p.N) || H == nullptr) return (int)hipErrorInvalidValue;
-  const int64_t n = (int64_t)p.nchan * p.N;
-  const int64_t grid = (n + 255) / 256;
+  const int kpt = std::max(1, std::min(8, p.N / 256));
+  const int64_t grid = (int64_t)p.nchan * (p.N / (256 * kpt));
   if (grid > 0x7fffffffLL) return (int)hipErrorInvalidValue;
   hipLaunchKernelGGL(chirp_table_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
-                     (float2*)H, log2i(p.N), p.nchan, p.f_lo, p.df, p.dconst, dm, p.phase_mode,
-                     p.taper);
+                     (float2*)H, log2i(p.N), kpt, p.f_lo, p.df, p.dconst, dm, p.phase_mode,
+                     p.taper, exact_division_needed(p, std::fabs(dm)));
   return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches in two steps: prepare_launch forms the table of per-beam
+// arguments in host memory, enqueue_launch copies it to the device and
+// launches.  The host table must stay unchanged until the stream has run the
+// copy (the plan keeps it in pinned memory and rewrites it only after the
+// previous copy; the server keeps one per batch in flight).
+// ---------------------------------------------------------------------------
+bool batch_variant_ok(int N, int V) {
+  if (V == 0) return block_supported(N);
+  if (N == 4096) return V == 3;
+  if (N == 8192) return V == 1 || V == 2;
+  if (N == 16384) return V == 2;
+  return false;
+}
+
+bool mixed_supported(int N) { return N >= 256 && N <= 8192 && (N & (N - 1)) == 0; }
+
+static int mix_group(int N) {
+  switch (N) {
+    case 256: return kMixT / MixSched<256>::T;
+    case 512: return kMixT / MixSched<512>::T;
+    case 1024: return kMixT / MixSched<1024>::T;
+    case 2048: return kMixT / MixSched<2048>::T;
+    case 4096: return kMixT / MixSched<4096>::T;
+    case 8192: return kMixT / MixSched<8192>::T;
+  }
+  return 0;
+}
+
+// Twiddle table of the schedule a launch kind runs for (N, V).
+static int launch_twiddles(int kind, int N, int V, const float2** tw) {
+  if (kind == kLaunchMixed) {
+    switch (N) {
+      case 256: return twiddles_of<MixSched<256>>(tw);
+      case 512: return twiddles_of<MixSched<512>>(tw);
+      case 1024: return twiddles_of<MixSched<1024>>(tw);
+      case 2048: return twiddles_of<MixSched<2048>>(tw);
+      case 4096: return twiddles_of<MixSched<4096>>(tw);
+      case 8192: return twiddles_of<MixSched<8192>>(tw);
+    }
+    return (int)hipErrorInvalidValue;
+  }
+  if (kind == kLaunchBatch && V != 0) {
+    if (N == 4096 && V == 3) return twiddles_of<SchedFor<4096, 3>::type>(tw);
+    if (N == 8192 && V == 1) return twiddles_of<SchedFor<8192, 1>::type>(tw);
+    if (N == 8192 && V == 2) return twiddles_of<SchedFor<8192, 2>::type>(tw);
+    if (N == 16384 && V == 2) return twiddles_of<SchedFor<16384, 2>::type>(tw);
+    return (int)hipErrorInvalidValue;
+  }
+  switch (N) {
+    case 256: return twiddles_of<SchedFor<256, 0>::type>(tw);
+    case 512: return twiddles_of<SchedFor<512, 0>::type>(tw);
+    case 1024: return twiddles_of<SchedFor<1024, 0>::type>(tw);
+    case 2048: return twiddles_of<SchedFor<2048, 0>::type>(tw);
+    case 4096: return twiddles_of<SchedFor<4096, 0>::type>(tw);
+    case 8192: return twiddles_of<SchedFor<8192, 0>::type>(tw);
+    case 16384: return twiddles_of<SchedFor<16384, 0>::type>(tw);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+int prepare_launch(int kind, const BatchBeam* beams, const void* const* H, int nbeams,
+                   void* host_tab, LaunchDesc* d) {
+  if (nbeams < 1 || !d) return (int)hipErrorInvalidValue;
+  BlockArgs* ht = (BlockArgs*)host_tab;
+  LaunchDesc out;
+  out.kind = kind;
+  out.nbeams = nbeams;
+  out.N = beams[0].p->N;
+  out.dtype = beams[0].p->dtype;
+  out.variant = kind == kLaunchBatch ? beams[0].p->variant : 0;
+  if (!batch_variant_ok(out.N, out.variant)) out.variant = 0;
+  // order: longest work per unit first (a unit = the transforms one
+  // workgroup runs at once, each N log N per DM trial)
+  std::vector<int> order(nbeams);
+  std::vector<double> work(nbeams);
+  for (int b = 0; b < nbeams; ++b) {
+    const BeamPlan& p = *beams[b].p;
+    const int ndm = beams[b].dms.ndm;
+    const void* h = H ? H[b] : nullptr;
+    if (ndm < 1 || ndm > kMaxDmTile || p.dtype != out.dtype) return (int)hipErrorInvalidValue;
+    if (kind == kLaunchMixed) {
+      if (!mixed_supported(p.N) || (ndm > 1 && h)) return (int)hipErrorInvalidValue;
+    } else {
+      if (p.N != out.N || !block_supported(p.N)) return (int)hipErrorInvalidValue;
+      if (kind == kLaunchTables && (ndm != 1 || !h)) return (int)hipErrorInvalidValue;
+      if (kind == kLaunchBatch && h) return (int)hipErrorInvalidValue;
+    }
+    if (!h) out.multi = 1;
+    order[b] = b;
+    const int G = kind == kLaunchMixed ? mix_group(p.N) : 1;
+    work[b] = (double)G * p.N * std::log2((double)p.N) * (1 + ndm);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+  int64_t total = 0;
+  for (int i = 0; i < nbeams; ++i) {
+    const int b = order[i];
+    const BeamPlan& p = *beams[b].p;
+    ht[i] = make_args(p, beams[b].co, beams[b].xt, beams[b].dms, beams[b].P, nullptr,
+                      (const float2*)(H ? H[b] : nullptr));
+    int err = launch_twiddles(kind, p.N, out.variant, &ht[i].tw);
+    if (err) return err;
+    ht[i].item0 = total;
+    const int64_t items = (int64_t)p.nchan * beams[b].co.nblocks;
+    const int G = kind == kLaunchMixed ? mix_group(p.N) : 1;
+    total += (items + G - 1) / G;
+  }
+  if (total > (kind == kLaunchTables ? 0x7fffffffLL : 0xffffffffLL))
+    return (int)hipErrorInvalidValue;
+  out.total = total;
+  *d = out;
+  return 0;
+}
+
+template <int N, int V, int DT>
+static int enqueue_batch_t(const LaunchDesc& d, const void* dev_tab, unsigned int* counter,
+                           hipStream_t st) {
+  using S = typename SchedFor<N, V>::type;
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+  int64_t resident = 0;
+  int err = resident_workgroups(reinterpret_cast<const void*>(&batch_kernel<S, DT>), S::T,
+                                &resident);
+  if (err) return err;
+  const int64_t grid = std::min<int64_t>(d.total, resident);
+  hipLaunchKernelGGL((batch_kernel<S, DT>), dim3((unsigned)grid), dim3(S::T), 0, st,
+                     (const BlockArgs*)dev_tab, d.nbeams, d.total, counter);
+  return (int)hipGetLastError();
+}
+
+template <int N, int V>
+static int enqueue_batch_dt(const LaunchDesc& d, const void* dev_tab, unsigned int* counter,
+                            hipStream_t st) {
+  return d.dtype == CDD_CI8 ? enqueue_batch_t<N, V, CDD_CI8>(d, dev_tab, counter, st)
+                            : enqueue_batch_t<N, V, CDD_CF32>(d, dev_tab, counter, st);
+}
+
+template <int N>
+static int enqueue_tables_t(const LaunchDesc& d, const void* dev_tab, hipStream_t st) {
+  using S = typename SchedFor<N, 0>::type;
+  if (d.dtype == CDD_CI8)
+    hipLaunchKernelGGL((multi_single_kernel<S, CDD_CI8>), dim3((unsigned)d.total), dim3(S::T), 0,
+                       st, (const BlockArgs*)dev_tab, d.nbeams, d.total);
+  else
+    hipLaunchKernelGGL((multi_single_kernel<S, CDD_CF32>), dim3((unsigned)d.total), dim3(S::T),
+                       0, st, (const BlockArgs*)dev_tab, d.nbeams, d.total);
+  return (int)hipGetLastError();
+}
+
+template <bool MULTI, int DT>
+static int enqueue_mixed_t(const LaunchDesc& d, const void* dev_tab, unsigned int* counter,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+  int64_t resident = 0;
+  int err = resident_workgroups(reinterpret_cast<const void*>(&mixed_kernel<MULTI, DT>), kMixT,
+                                &resident);
+  if (err) return err;
+  const int64_t grid = std::min<int64_t>(d.total, resident);
+  hipLaunchKernelGGL((mixed_kernel<MULTI, DT>), dim3((unsigned)grid), dim3(kMixT), 0, st,
+                     (const BlockArgs*)dev_tab, d.nbeams, d.total, counter);
+  return (int)hipGetLastError();
+}
+
+static int enqueue_mixed(const LaunchDesc& d, const void* dev_tab, unsigned int* counter,
+                         hipStream_t st) {
+  if (d.dtype == CDD_CI8)
+    return d.multi ? enqueue_mixed_t<true, CDD_CI8>(d, dev_tab, counter, st)
+                   : enqueue_mixed_t<false, CDD_CI8>(d, dev_tab, counter, st);
+  return d.multi ? enqueue_mixed_t<true, CDD_CF32>(d, dev_tab, counter, st)
+                 : enqueue_mixed_t<false, CDD_CF32>(d, dev_tab, counter, st);
+}
+
+int enqueue_launch(const LaunchDesc& d, const void* host_tab, void* dev_tab,
+                   unsigned int* counter, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(dev_tab, host_tab, batch_table_bytes(d.nbeams),
+                                hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return (int)e;
+  if (d.total <= 0) return 0;
+  if (d.kind == kLaunchMixed) return enqueue_mixed(d, dev_tab, counter, st);
+  if (d.kind == kLaunchTables) {
+    switch (d.N) {
+      case 256: return enqueue_tables_t<256>(d, dev_tab, st);
+      case 512: return enqueue_tables_t<512>(d, dev_tab, st);
+      case 1024: return enqueue_tables_t<1024>(d, dev_tab, st);
+      case 2048: return enqueue_tables_t<2048>(d, dev_tab, st);
+      case 4096: return enqueue_tables_t<4096>(d, dev_tab, st);
+      case 8192: return enqueue_tables_t<8192>(d, dev_tab, st);
+      case 16384: return enqueue_tables_t<16384>(d, dev_tab, st);
+    }
+    return (int)hipErrorInvalidValue;
+  }
+  switch (d.N) {
+    case 256: return enqueue_batch_dt<256, 0>(d, dev_tab, counter, st);
+    case 512: return enqueue_batch_dt<512, 0>(d, dev_tab, counter, st);
+    case 1024: return enqueue_batch_dt<1024, 0>(d, dev_tab, counter, st);
+    case 2048: return enqueue_batch_dt<2048, 0>(d, dev_tab, counter, st);
+    case 4096:
+      return d.variant == 3 ? enqueue_batch_dt<4096, 3>(d, dev_tab, counter, st)
+                            : enqueue_batch_dt<4096, 0>(d, dev_tab, counter, st);
+    case 8192:
+      switch (d.variant) {
+        case 1: return enqueue_batch_dt<8192, 1>(d, dev_tab, counter, st);
+        case 2: return enqueue_batch_dt<8192, 2>(d, dev_tab, counter, st);
+        default: return enqueue_batch_dt<8192, 0>(d, dev_tab, counter, st);
+      }
+    case 16384:
+      return d.variant == 2 ? enqueue_batch_dt<16384, 2>(d, dev_tab, counter, st)
+                            : enqueue_batch_dt<16384, 0>(d, dev_tab, counter, st);
+  }
+  return (int)hipErrorInvalidValue;
 }
 
 int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_tab,
                  unsigned int* counter, void* stream) {
   if (nbeams < 1) return 0;
-  const int N = beams[0].p->N, v = beams[0].p->variant;
-  BlockArgs* ht = (BlockArgs*)host_tab;
-  int64_t total = 0;
-  for (int b = 0; b < nbeams; ++b) {
-    const BeamPlan& p = *beams[b].p;
-    if (p.N != N || beams[b].dms.ndm < 1 || beams[b].dms.ndm > kMaxDmTile)
-      return (int)hipErrorInvalidValue;
-    ht[b] = make_args(p, beams[b].co, beams[b].xt, beams[b].dms, beams[b].P, nullptr, nullptr);
-    ht[b].item0 = total;
-    total += (int64_t)p.nchan * beams[b].co.nblocks;
-  }
-  if (total > 0xffffffffLL) return (int)hipErrorInvalidValue;
-  BlockArgs* dt = (BlockArgs*)dev_tab;
-  switch (N) {
-    case 256: return launch_batch_t<256, 0>(ht, nbeams, total, dt, counter, stream);
-    case 512: return launch_batch_t<512, 0>(ht, nbeams, total, dt, counter, stream);
-    case 1024: return launch_batch_t<1024, 0>(ht, nbeams, total, dt, counter, stream);
-    case 2048: return launch_batch_t<2048, 0>(ht, nbeams, total, dt, counter, stream);
-    case 4096:
-      return v == 3 ? launch_batch_t<4096, 3>(ht, nbeams, total, dt, counter, stream)
-                    : launch_batch_t<4096, 0>(ht, nbeams, total, dt, counter, stream);
-    case 8192:
-      switch (v) {
-        case 1: return launch_batch_t<8192, 1>(ht, nbeams, total, dt, counter, stream);
-        case 2: return launch_batch_t<8192, 2>(ht, nbeams, total, dt, counter, stream);
-        default: return launch_batch_t<8192, 0>(ht, nbeams, total, dt, counter, stream);
-      }
-    case 16384:
-      return v == 2 ? launch_batch_t<16384, 2>(ht, nbeams, total, dt, counter, stream)
-                    : launch_batch_t<16384, 0>(ht, nbeams, total, dt, counter, stream);
-  }
-  return (int)hipErrorInvalidValue;
+  LaunchDesc d;
+  int err = prepare_launch(kLaunchBatch, beams, nullptr, nbeams, host_tab, &d);
+  return err ? err : enqueue_launch(d, host_tab, dev_tab, counter, stream);
 }
 
 const char* hip_error_string(int err) { return hipGetErrorString((hipError_t)err); }

@@ -3,6 +3,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -99,8 +101,24 @@ int launch_chirp_table(const BeamPlan& p, double dm, void* H, void* stream);
 int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, float* P,
                   int32_t* d, void* H, void* volt_out, float* I, int32_t* cov, int chunks,
                   int npol, void* stream);
-// Batched form: beams that share one transform length, each with its DM
-// tile, in one persistent launch.
+// aux_work(aux stream) and main_work(stream) enqueued so that they run side
+// by side: the library's auxiliary stream starts after the work already on
+// `stream`, and `stream` goes on past this point only once both are done.
+int fork_join(void* stream, const std::function<int(void*)>& aux_work,
+              const std::function<int(void*)>& main_work);
+// The library's auxiliary stream of the current device, held (one user at a
+// time) from aux_open to aux_close: aux_open makes it start after the work
+// already on `stream`; aux_mark makes `waiting` wait for everything enqueued
+// on it so far; aux_close makes `stream` wait for all of it and releases it.
+struct AuxSession {
+  std::unique_lock<std::mutex> lk;
+  void* aux = nullptr;   // hipStream_t
+  void* impl = nullptr;
+};
+int aux_open(void* stream, AuxSession* session);
+int aux_mark(AuxSession* session, void* waiting);
+int aux_close(void* stream, AuxSession* session);
+// Batched form: beams, each with its DM tile, in one launch.
 struct BatchBeam {
   const BeamPlan* p;
   const void* xt;    // channel-major input
@@ -109,11 +127,33 @@ struct BatchBeam {
   Coords co;
 };
 size_t batch_table_bytes(int nbeams);
-// One-DM beams sharing a transform length: one launch over all their
-// (channel, block) items, beam b's chirp from its table H[b]; tables as for
-// launch_batch (host_tab pinned or kept alive until the copy completes).
-int launch_multi_single(const BatchBeam* beams, const void* const* H, int nbeams,
-                        void* host_tab, void* dev_tab, void* stream);
+// Launch kinds of the batched form:
+//   kLaunchMixed  beams of any length in [256, 8192] (mixed_supported) in one
+//                 persistent launch, each reading its chirp table (H[b]) or,
+//                 with H[b] NULL, forming its chirp in the kernel;
+//   kLaunchTables one-DM beams of one length, chirps from tables, one
+//                 workgroup per (beam, channel, block);
+//   kLaunchBatch  beams of one length with DM tiles, chirps in the kernel,
+//                 one persistent launch (schedule variant of the first beam,
+//                 if batch_variant_ok).
+// All beams of a launch share one sample type; they are listed longest work
+// per unit first.
+enum { kLaunchMixed = 0, kLaunchTables = 1, kLaunchBatch = 2 };
+struct LaunchDesc {
+  int kind = 0, N = 0, variant = 0, nbeams = 0, multi = 0, dtype = 0;
+  int64_t total = 0;  // work units
+};
+bool mixed_supported(int N);
+bool batch_variant_ok(int N, int V);  // schedules the persistent batch kernel has
+// Form the per-beam argument table of one launch in host_tab
+// (batch_table_bytes(nbeams) bytes); H may be NULL (no tables).
+int prepare_launch(int kind, const BatchBeam* beams, const void* const* H, int nbeams,
+                   void* host_tab, LaunchDesc* d);
+// Copy host_tab (unchanged until the stream has run the copy) to dev_tab and
+// launch; counter is a device word for the persistent kinds.
+int enqueue_launch(const LaunchDesc& d, const void* host_tab, void* dev_tab,
+                   unsigned int* counter, void* stream);
+// prepare_launch(kLaunchBatch) + enqueue_launch.
 int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_tab,
                  unsigned int* counter, void* stream);
 int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream);

@@ -11,6 +11,7 @@
 // the block kernel down, so one chunk is the default.)
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -107,6 +108,58 @@ static int run_single(Aux& ax, const BeamPlan& p, const void* voltages, double d
   if ((err = stage_begin(kStageDsum, S, &tok))) return err;
   if ((err = launch_dsum(p, 1, P, d, I, cov, p.t_int, S))) return err;
   return stage_end(kStageDsum, S, tok);
+}
+
+int fork_join(void* stream, const std::function<int(void*)>& aux_work,
+              const std::function<int(void*)>& main_work) {
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  Aux* axp = nullptr;
+  int err = aux_of(&axp);
+  if (err) return err;
+  Aux& ax = *axp;
+  hipStream_t S = (hipStream_t)stream, A = ax.s;
+  hipError_t e;
+  hipEvent_t e0 = take(ax);
+  if ((e = hipEventRecord(e0, S)) != hipSuccess) return (int)e;
+  if ((e = hipStreamWaitEvent(A, e0, 0)) != hipSuccess) return (int)e;
+  if ((err = aux_work((void*)A))) return err;
+  hipEvent_t eA = take(ax);
+  if ((e = hipEventRecord(eA, A)) != hipSuccess) return (int)e;
+  if ((err = main_work((void*)S))) return err;
+  if ((e = hipStreamWaitEvent(S, eA, 0)) != hipSuccess) return (int)e;
+  return 0;
+}
+
+int aux_open(void* stream, AuxSession* session) {
+  session->lk = std::unique_lock<std::mutex>(g_aux_mu);
+  Aux* axp = nullptr;
+  int err = aux_of(&axp);
+  if (err) {
+    session->lk.unlock();
+    return err;
+  }
+  session->impl = axp;
+  session->aux = (void*)axp->s;
+  hipEvent_t e0 = take(*axp);
+  hipError_t e = hipEventRecord(e0, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(axp->s, e0, 0);
+  return (int)e;
+}
+
+int aux_mark(AuxSession* session, void* waiting) {
+  Aux& ax = *(Aux*)session->impl;
+  hipEvent_t ev = take(ax);
+  hipError_t e = hipEventRecord(ev, ax.s);
+  if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)waiting, ev, 0);
+  return (int)e;
+}
+
+int aux_close(void* stream, AuxSession* session) {
+  int err = session->impl ? aux_mark(session, stream) : 0;
+  session->impl = nullptr;
+  session->aux = nullptr;
+  if (session->lk.owns_lock()) session->lk.unlock();
+  return err;
 }
 
 int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, float* P,

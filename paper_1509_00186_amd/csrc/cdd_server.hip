@@ -11,8 +11,9 @@
 //   d        channel delays; Iout staging for finished I[u];
 //   slots    device staging for pushed blocks (time-major).
 // A scheduler thread forms batches: every stream with consumed data gets its
-// complete overlap-save blocks folded into one persistent launch per
-// transform length; aligned sums and copies to the host follow on the same
+// complete overlap-save blocks folded into one persistent launch (every
+// transform length up to 8192 together, one launch per longer length);
+// aligned sums and copies to the host follow on the same
 // HIP stream.  Pushes copy into pinned slots and start the host-to-device
 // copy on a second HIP stream; the compute stream waits on its event.
 #include <hip/hip_runtime.h>
@@ -217,7 +218,12 @@ int issue_batch(cdd_server* sv, BatchRec& br) {
     if (flush) s->flushed = true;
   }
   if (work.empty()) return 0;
-  // 2. one persistent launch per transform length
+  // 2. one persistent launch for every stream of a sample type whose length
+  //    the mixed-length kernel takes, one per length above that
+  auto group_key = [&](size_t w) {
+    const BeamPlan& p = work[w].s->p;
+    return (mixed_supported(p.N) ? 0 : p.N) * 2 + p.dtype;
+  };
   std::vector<BatchBeam> group;
   std::vector<bool> done(work.size(), false);
   size_t tab_used = 0;
@@ -226,7 +232,7 @@ int issue_batch(cdd_server* sv, BatchRec& br) {
     if (done[w0] || work[w0].nproc == 0) continue;
     group.clear();
     for (size_t w = w0; w < work.size(); ++w) {
-      if (done[w] || work[w].nproc == 0 || work[w].s->p.N != work[w0].s->p.N) continue;
+      if (done[w] || work[w].nproc == 0 || group_key(w) != group_key(w0)) continue;
       done[w] = true;
       Stream* s = work[w].s;
       BatchBeam bb;
@@ -254,8 +260,13 @@ int issue_batch(cdd_server* sv, BatchRec& br) {
     br.host_tabs.emplace_back(batch_table_bytes((int)group.size()), 0);
     void* tok = nullptr;
     if ((e = stage_begin(kStageBlock, cs, &tok))) return e;
-    if ((e = launch_batch(group.data(), (int)group.size(), br.host_tabs.back().data(),
-                          (char*)br.tab_dev + tab_used, br.counter + 64 * ngroup, cs)))
+    LaunchDesc ld;
+    const int kind = mixed_supported(group[0].p->N) ? kLaunchMixed : kLaunchBatch;
+    if ((e = prepare_launch(kind, group.data(), nullptr, (int)group.size(),
+                            br.host_tabs.back().data(), &ld)))
+      return e;
+    if ((e = enqueue_launch(ld, br.host_tabs.back().data(), (char*)br.tab_dev + tab_used,
+                            br.counter + 64 * ngroup, cs)))
       return e;
     if ((e = stage_end(kStageBlock, cs, tok))) return e;
     tab_used += batch_table_bytes((int)group.size());

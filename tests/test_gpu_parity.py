@@ -458,6 +458,51 @@ def test_plan_of_one_dm_beams_uses_tables_and_matches_oracle():
     plan.close()
 
 
+def test_mixed_lengths_one_persistent_launch():
+    """Beams of transform lengths 512 to 8192 -- one-DM beams reading their
+    chirp tables, a beam with three DM trials, uneven channel counts and
+    durations -- in one persistent launch per execute with single_launch
+    (checked with the stage timer: one block-kernel launch), every beam and
+    DM against the oracle; the same with every chirp formed in the kernel,
+    and the default pipelined plan (one launch per beam), match the oracle
+    too."""
+    import torch
+    cdd = _cdd()
+    spec = [(610.0, 16, 0.03125, 9_000, [10.0], 512),
+            (400.0, 8, 0.048828125, 7_001, [30.0], 1024),
+            (325.0, 24, 0.0625, 11_000, [67.9, 69.0, 66.5], 2048),
+            (325.0, 6, 0.0625, 13_000, [50.0], 4096),
+            (325.0, 4, 0.0625, 20_000, [67.9], 8192)]
+    raw = []
+    for k, (fcen, nchan, df, nsamp, dms, N) in enumerate(spec):
+        raw.append((_beam_int8(170 + k, nsamp, nchan, fcen, nchan * df, dms[0]), fcen,
+                    nchan * df, dms, N))
+    devs = [to_dev(r[0]) for r in raw]
+    for single, in_kernel in ((True, False), (True, True), (False, False)):
+        flush("case: mixed lengths, single_launch=%s chirp_in_kernel=%s" % (single, in_kernel))
+        plan = cdd.Plan([dict(voltages=vd, f_centre=f, bw=bw, dms=dms, n_int=4, fft_len=N)
+                         for vd, (v, f, bw, dms, N) in zip(devs, raw)],
+                        chirp_in_kernel=in_kernel, single_launch=single)
+        plan.execute()
+        torch.cuda.synchronize()
+        cdd.profile_read()
+        cdd.profile_enable(True, stages=["block"])
+        plan.execute()
+        torch.cuda.synchronize()
+        cdd.profile_enable(False)
+        st = cdd.profile_read()
+        assert st["block"][1] == (1 if single else len(raw)), st
+        for bi, (v, fcen, bw, dms, N) in enumerate(raw):
+            info = plan.info(bi)
+            assert info["fft_len"] == N
+            for i, dm in enumerate(dms):
+                o = O.dedisperse(v, fcen, bw, dm, 4, fft_len=N, overlap=info["overlap"],
+                                 nfront=info["nfront"])
+                assert rel_l2(plan.I[bi][i].cpu().numpy(), o["I"]) <= TOL_I, (bi, i)
+                assert np.array_equal(plan.cov[bi][i].cpu().numpy(), o["cov"])
+        plan.close()
+
+
 def test_dm_tiles_beyond_one_launch():
     """More DM trials than one launch holds (70 > 64): two rounds."""
     import torch
