@@ -411,7 +411,12 @@ typedef struct {
   int64_t max_block;      /* largest block a push may carry (samples/chan)   */
   int32_t phase_mode;
   int32_t taper;          /* cdd_taper                                      */
-  int32_t reserved[4];
+  int64_t block_len;      /* samples per channel of every push but the last
+                             (0: pushes of any size).  With it, blocks lost
+                             before a push are re-inserted as zeros at their
+                             true position, so later outputs keep their
+                             absolute indices                               */
+  int32_t reserved[2];
 } cdd_stream_desc;
 
 typedef struct {
@@ -443,12 +448,16 @@ cdd_status cdd_stream_open(cdd_server* server, const cdd_stream_desc* desc,
 /* Queue the next block: host_block [nsamp][nchan] (time-major), copied
  * before return.  seq must be the stream's next sequence number (first 0):
  * a smaller seq is refused (EINVAL, counted as rejected); a larger one means
- * blocks were lost -- it is accepted, counted as a gap, and the block is
- * processed as if preceded by zeros (the overlap tail and any samples not
- * yet part of a complete block are dropped; absolute sample numbering
- * continues without the lost span).  EAGAIN
- * when queue_depth blocks are already waiting (retry later); EINVAL for
- * nsamp < 1 or > max_block, or a closed stream. */
+ * blocks were lost -- it is accepted and counted as a gap.  With the
+ * stream's block_len set, the lost blocks' samples are inserted as zeros at
+ * their true position (the result is that of the record with those samples
+ * zero); without it the block joins the data before the gap.  Either way the
+ * aligned-sum outputs whose inputs include the lost span (or the junction)
+ * are reported by cdd_stream_invalid (the paper's real-time check is that
+ * no block is lost, Sec. 4.5).  EAGAIN when queue_depth blocks are already
+ * waiting (retry later); EINVAL for nsamp < 1 or > max_block (or >
+ * block_len, or any push after one shorter than block_len), or a closed
+ * stream. */
 cdd_status cdd_stream_push(cdd_server* server, int32_t stream_id,
                            const void* host_block, int64_t nsamp, uint64_t seq);
 /* Copy up to cap finished samples of the stream's aligned sum I[u] (FP32,
@@ -457,6 +466,14 @@ cdd_status cdd_stream_push(cdd_server* server, int32_t stream_id,
  * intensity is known (after the dispersion sweep), or at close. */
 cdd_status cdd_stream_poll(cdd_server* server, int32_t stream_id, float* host_out,
                            int64_t cap, int64_t* n, int64_t* u_first);
+/* Output spans [begin, end) (aligned-sum indices, absolute) whose inputs
+ * include lost samples or a junction across lost blocks, in the order the
+ * gaps arrived: up to cap pairs into spans[2 i], spans[2 i + 1]; *n receives
+ * the number recorded so far.  The span covers every output the lost input
+ * can reach through the filter's impulse response, the integration and the
+ * channel delays. */
+cdd_status cdd_stream_invalid(cdd_server* server, int32_t stream_id, int64_t* spans,
+                              int64_t cap, int64_t* n);
 /* End of stream: the tail is processed with zeros after the last sample and
  * every I[u], u < total/n_int, becomes available (with partial coverage at
  * the end, as cdd_dedisperse).  The stream's memory is returned to the
@@ -488,21 +505,29 @@ cdd_status cdd_profile_select(uint32_t stage_mask);
 cdd_status cdd_profile_read(cdd_profile* out);
 
 /* ---------------------------------------------------------------------
- * Autotuner: transform length and block-kernel schedule for a beam shape.
- * Every N in [n_min, n_max] (powers of two; 0 = 2^11 and 2^14) for which the
- * overlap fits, and every schedule compiled for that N, is timed on the
- * current device on a random int8 record of the beam's shape (up to sixteen
- * DM trials per work item), in two sweeps whose best time per candidate
- * counts; the fastest in input samples x DM trials per second wins.  Results are cached per device and shape in memory, and
- * appended to the text file named by the environment variable CDD_TUNE_CACHE
- * (read back on first use).  Allocates and frees its own device memory and
- * waits for the device.  ENOTSUP for complex-float records.
+ * Autotuner: transform length, block-kernel schedule and DM tile for a beam
+ * shape, timed in the form a plan runs them.  Every N in [n_min, n_max]
+ * (powers of two; 0 = 2^11 and 2^14; at most 2^14, the longest transform a
+ * workgroup holds: beyond it the four-step kernels take several passes over
+ * HBM per block) for which the overlap fits is timed on the current device
+ * on a random int8 record of the beam's channel count.  With one DM trial:
+ * the per-execute chirp table and the one-workgroup-per-block kernel.  With
+ * several: the persistent batched kernel in each schedule it is compiled
+ * for, over tiles of 16, 32 and 64 trials (no more than the beam has).  Two
+ * sweeps; the best time per candidate counts; the fastest in input samples
+ * x DM trials per second wins.  Results are cached per device and shape in
+ * memory, and appended to the text file named by the environment variable
+ * CDD_TUNE_CACHE (read back on first use).  Allocates and frees its own
+ * device memory and waits for the device.  ENOTSUP for complex-float
+ * records.
  * ------------------------------------------------------------------- */
 typedef struct {
   int32_t fft_len;
-  int32_t kernel_variant;
+  int32_t kernel_variant;  /* schedule of the kernel that won               */
   double ms;               /* one launch over the timing record              */
   double msamples_per_s;   /* input samples x DM trials per second           */
+  int32_t dm_tile;         /* DM trials per launch that won (1 for one DM)   */
+  int32_t reserved;
 } cdd_tune_result;
 cdd_status cdd_autotune(int32_t dtype, int32_t nchan, double f_centre_mhz, double bw_mhz,
                         const double* host_dms, int32_t ndm, int32_t n_int,

@@ -84,7 +84,8 @@ class StreamDesc(ctypes.Structure):
                 ("f_centre_mhz", ctypes.c_double), ("bw_mhz", ctypes.c_double),
                 ("dm", ctypes.c_double), ("fft_len", ctypes.c_int32), ("n_int", ctypes.c_int32),
                 ("max_block", ctypes.c_int64), ("phase_mode", ctypes.c_int32),
-                ("taper", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("taper", ctypes.c_int32), ("block_len", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class ServerStats(ctypes.Structure):
@@ -102,7 +103,8 @@ class ServerStats(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("fft_len", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
-                ("ms", ctypes.c_double), ("msamples_per_s", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("msamples_per_s", ctypes.c_double),
+                ("dm_tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def _load():
@@ -140,10 +142,12 @@ def _load():
     lib.cdd_stream_push.argtypes = [vp, i32, vp, i64, ctypes.c_uint64]
     lib.cdd_stream_poll.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.cdd_stream_close.argtypes = [vp, i32]
+    lib.cdd_stream_invalid.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
     lib.cdd_server_sync.argtypes = [vp]
     lib.cdd_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
     for f in ("cdd_server_create", "cdd_stream_open", "cdd_stream_push", "cdd_stream_poll",
-              "cdd_stream_close", "cdd_server_sync", "cdd_server_stats_get"):
+              "cdd_stream_close", "cdd_stream_invalid", "cdd_server_sync",
+              "cdd_server_stats_get"):
         getattr(lib, f).restype = ctypes.c_int
     lib.cdd_autotune.argtypes = [i32, i32, f64, f64, ctypes.POINTER(f64), i32, i32, i32, i32,
                                  ctypes.POINTER(TuneResult)]
@@ -527,8 +531,9 @@ class Server:
         self._h = h
 
     def open(self, dtype, nchan, f_centre, bw, dm, n_int, max_block, fft_len=0, phase_mode=0,
-             taper="none"):
+             taper="none", block_len=0):
         d = StreamDesc()
+        d.block_len = int(block_len)
         d.dtype, d.nchan, d.f_centre_mhz, d.bw_mhz, d.dm = int(dtype), int(nchan), \
             float(f_centre), float(bw), float(dm)
         d.fft_len, d.n_int, d.max_block, d.phase_mode = int(fft_len), int(n_int), \
@@ -556,6 +561,13 @@ class Server:
         _check(lib.cdd_stream_poll(self._h, int(sid), ctypes.c_void_p(out.ctypes.data), cap,
                                    ctypes.byref(n), ctypes.byref(u0)))
         return u0.value, out[:n.value].copy()
+
+    def invalid(self, sid, cap=1024):
+        """[(begin, end)] output spans that include lost input."""
+        buf = (ctypes.c_int64 * (2 * cap))()
+        n = ctypes.c_int64()
+        _check(lib.cdd_stream_invalid(self._h, int(sid), buf, cap, ctypes.byref(n)))
+        return [(buf[2 * i], buf[2 * i + 1]) for i in range(min(n.value, cap))]
 
     def close_stream(self, sid):
         _check(lib.cdd_stream_close(self._h, int(sid)))

@@ -14,7 +14,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "_lib", "libcdd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["cdd_plan.cpp", "cdd_api.cpp", "cdd_fullband.cpp", "cdd_aux.hip", "cdd_profile.hip", "cdd_block.hip",
+SOURCES = ["cdd_plan.cpp", "cdd_sched.cpp", "cdd_api.cpp", "cdd_fullband.cpp", "cdd_aux.hip", "cdd_profile.hip", "cdd_block.hip",
            "cdd_large.hip", "cdd_server.hip",
            "cdd_pipeline.hip", "cdd_tune.hip", "cdd_static.hip"]
 

@@ -159,6 +159,7 @@ void layout_plan(cdd_plan* pl) {
     int t = 1;
     if (block_supported(p.N))
       t = std::max(1, (int)std::floor(std::min(ndm, kMaxDmTile) * scale));
+    if (p.dm_tile > 0) t = std::min(t, p.dm_tile);
     pl->tile[b] = t;
     pl->lay[b] = ws_layout(p, t, true, table_chirp(pl, p));
     pl->ws_base[b] = off;
@@ -360,6 +361,7 @@ cdd_status cdd_plan_create(const cdd_beam* beams, int32_t nbeam, const cdd_opts*
       }
       BeamPlan p;
       int32_t fft_len = d.fft_len;
+      int32_t tuned_tile = 0;
       cdd_opts o2 = opts ? *opts : cdd_opts{};
       if (opts && opts->autotune && fft_len == 0 && !opts->explicit_plan &&
           d.dtype == CDD_CI8 && d.host_dms && d.ndm > 0) {
@@ -369,6 +371,7 @@ cdd_status cdd_plan_create(const cdd_beam* beams, int32_t nbeam, const cdd_opts*
         if (ts == CDD_OK) {
           fft_len = tr.fft_len;
           o2.kernel_variant = tr.kernel_variant;
+          tuned_tile = tr.dm_tile;
         }
       }
       cdd_status s = make_plan(d.dtype, d.nsamp, d.nchan, d.f_centre_mhz, d.bw_mhz, d.host_dms,
@@ -382,6 +385,7 @@ cdd_status cdd_plan_create(const cdd_beam* beams, int32_t nbeam, const cdd_opts*
         delete pl;
         return fail(CDD_ENOTSUP, "beam %d: fft_len %d is not supported", b, p.N);
       }
+      p.dm_tile = tuned_tile;
       pl->beams.push_back(p);
       cdd_beam copy = d;
       copy.host_dms = nullptr;

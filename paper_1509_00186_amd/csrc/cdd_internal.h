@@ -32,6 +32,7 @@ struct BeamPlan {
   int32_t phase_mode = CDD_PHASE_FP64_REDUCED;
   int32_t taper = CDD_TAPER_NONE;
   int32_t variant = 0;  // block-kernel schedule (autotuner choice)
+  int32_t dm_tile = 0;  // DM trials per batched launch (autotuner choice; 0 = as many as fit)
   std::vector<double> dms;
   int32_t N = 0, L = 0, nfront = 0, M = 0;
   int32_t front = 0, back = 0;

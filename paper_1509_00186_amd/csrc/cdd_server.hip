@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "cdd_internal.h"
+#include "cdd_sched.h"
 
 namespace cdd {
 namespace {
@@ -52,7 +53,7 @@ struct Slot {
   void* dev = nullptr;
   int64_t nsamp = 0;
   uint64_t seq = 0;
-  bool gap = false;
+  int64_t zeros = 0;  // lost samples to insert (as zeros) before this block
   double t_arrive = 0;
   hipEvent_t h2d = nullptr;
   SlotState state = FREE;
@@ -60,9 +61,13 @@ struct Slot {
 
 struct Stream {
   int id = -1;
-  bool closing = false, flushed = false, released = false;
+  bool closing = false, flushed = false, released = false, releasing = false;
   BeamPlan p;
+  StreamGeom g;
+  Timeline tl;
   int64_t max_block = 0;
+  int64_t block_len = 0;    // declared length of every push but the last (0: any)
+  bool short_seen = false;  // a push shorter than block_len (must be the last)
   size_t elem = 2;
   char* pend[2] = {nullptr, nullptr};
   int cur = 0;
@@ -75,10 +80,7 @@ struct Stream {
   int64_t icap = 0;
   float* Ihost = nullptr;  // pinned, icap floats per batch ring entry
   std::vector<Slot> slots;
-  uint64_t next_seq = 0;
   size_t bytes = 0;
-  // stream positions (absolute sample / integrated-sample indices)
-  int64_t E = 0, kn = 0, pbase = 0, U = 0, ubase = 0, Inext = 0;
   // host results
   std::deque<float> ready;
   int64_t ready_first = 0;
@@ -147,19 +149,6 @@ hipError_t free_stream_mem(Stream* s) {
   return hipSuccess;
 }
 
-// Device bytes a stream holds (admission).
-size_t stream_bytes(const BeamPlan& p, int64_t max_block, int depth, int64_t* cap,
-                    int64_t* pcap, int64_t* icap) {
-  const size_t elem = p.dtype == CDD_CI8 ? 2 : 8;
-  *cap = (int64_t)p.N + max_block;
-  const int64_t per_batch = (max_block + p.N) / p.n_int + p.M / p.n_int + 2;
-  *pcap = p.d_max + 2 + per_batch;
-  *icap = per_batch + p.d_max + 2;
-  return 2 * al256((size_t)p.nchan * *cap * elem) + 2 * al256((size_t)p.nchan * *pcap * 4) +
-         al256((size_t)p.nchan * 4) + al256((size_t)*icap * 4) +
-         (size_t)depth * al256((size_t)max_block * p.nchan * elem);
-}
-
 // Issue the work of one batch on the compute stream (scheduler thread, lock
 // held for the host-side bookkeeping).
 int issue_batch(cdd_server* sv, BatchRec& br) {
@@ -176,6 +165,7 @@ int issue_batch(cdd_server* sv, BatchRec& br) {
     Stream* s = kv.second.get();
     if (s->released || s->flushed) continue;
     bool any = false;
+    Timeline& tl = s->tl;
     while (true) {
       // consume in sequence order, as far as the pending buffer has room
       int best = -1;
@@ -184,20 +174,28 @@ int issue_batch(cdd_server* sv, BatchRec& br) {
           best = (int)q;
       if (best < 0) break;
       Slot& sl = s->slots[best];
-      const int64_t off = s->E - s->pbase;
-      if (off + sl.nsamp > s->cap) break;  // next batch, after compaction
-      if (sl.gap && any) break;            // a gap starts a fresh batch
-      if ((e = (int)hipStreamWaitEvent(cs, sl.h2d, 0))) return e;
-      if (sl.gap) {
-        // lost blocks: restart the history from zeros
-        if ((e = (int)hipMemsetAsync(s->pend[s->cur], 0, (size_t)s->p.nchan * s->cap * s->elem,
-                                     cs)))
-          return e;
+      if (sl.zeros > 0) {
+        // lost blocks of a stream with a declared block length: zeros at
+        // their true position, as much as fits now
+        const int64_t z = std::min<int64_t>(sl.zeros, s->cap - (tl.E - tl.pbase));
+        if (z > 0) {
+          if ((e = (int)hipMemset2DAsync(s->pend[s->cur] + (tl.E - tl.pbase) * s->elem,
+                                         (size_t)s->cap * s->elem, 0, (size_t)z * s->elem,
+                                         (size_t)s->p.nchan, cs)))
+            return e;
+          tl.E += z;
+          sl.zeros -= z;
+          any = true;
+        }
+        if (sl.zeros > 0) break;  // the rest after this batch's compaction
       }
+      const int64_t off = tl.E - tl.pbase;
+      if (off + sl.nsamp > s->cap) break;  // next batch, after compaction
+      if ((e = (int)hipStreamWaitEvent(cs, sl.h2d, 0))) return e;
       if ((e = launch_transpose(sl.dev, s->pend[s->cur] + off * s->elem, s->p.dtype, sl.nsamp,
                                 s->p.nchan, s->cap, cs)))
         return e;
-      s->E += sl.nsamp;
+      tl.E += sl.nsamp;
       sl.state = TAKEN;
       br.slots.push_back({s->id, best});
       br.arrivals.push_back(sl.t_arrive);
@@ -207,13 +205,7 @@ int issue_batch(cdd_server* sv, BatchRec& br) {
         s->slots.begin(), s->slots.end(), [](const Slot& x) { return x.state != FREE; });
     if (!any && !flush) continue;
     // complete blocks: block k reads [k M - nfront, k M - nfront + N)
-    int64_t nproc = 0;
-    const BeamPlan& p = s->p;
-    if (flush) {
-      while ((s->kn + nproc) * p.M < s->E) ++nproc;
-    } else {
-      while ((s->kn + nproc) * p.M - p.nfront + p.N <= s->E) ++nproc;
-    }
+    const int64_t nproc = blocks_ready(s->tl, s->g, flush);
     work.push_back({s, nproc, 0});
     if (flush) s->flushed = true;
   }
@@ -240,14 +232,15 @@ int issue_batch(cdd_server* sv, BatchRec& br) {
       bb.xt = s->pend[s->cur];
       bb.dms.ndm = 1;
       bb.dms.dm[0] = s->p.dms[0];
-      bb.P = s->Pb[s->pcur] + (s->U - s->ubase);
+      bb.P = s->Pb[s->pcur] + (s->tl.U - s->tl.ubase);
       Coords co;
       co.x_stride = s->cap;
-      co.x_len = s->E - s->pbase;
+      co.x_len = s->tl.E - s->tl.pbase;
       co.load_off = 0;
       co.p_stride = s->pcap;
       co.p_dm_stride = (int64_t)s->p.nchan * s->pcap;
-      co.u_lim = s->closing ? s->E / s->p.n_int - s->U : s->pcap - (s->U - s->ubase);
+      co.u_lim = s->closing ? s->tl.E / s->p.n_int - s->tl.U
+                            : s->pcap - (s->tl.U - s->tl.ubase);
       co.v_stride = 0;
       co.o_lim = 0;
       co.nblocks = work[w].nproc;
@@ -277,19 +270,17 @@ int issue_batch(cdd_server* sv, BatchRec& br) {
   for (auto& w : work) {
     Stream* s = w.s;
     const BeamPlan& p = s->p;
-    const int64_t step = p.M / p.n_int;
-    int64_t U_new = s->U + w.nproc * step;
-    if (s->closing) U_new = std::min<int64_t>(U_new, s->E / p.n_int);
-    s->kn += w.nproc;
-    s->U = U_new;
-    const int64_t u_fin = s->flushed ? s->U : std::max<int64_t>(s->Inext, s->U - p.d_max);
-    const int64_t cnt = u_fin - s->Inext;
+    Timeline& tl = s->tl;
+    const int64_t U_old = tl.U, ub_old = tl.ubase;
+    const Advance adv = timeline_advance(&tl, s->g, w.nproc, s->closing, s->flushed);
+    (void)U_old;
+    const int64_t cnt = adv.count;
     if (cnt > 0) {
       if (cnt > s->icap) return (int)hipErrorInvalidValue;
       void* tok = nullptr;
       if ((e = stage_begin(kStageDsum, cs, &tok))) return e;
       if ((e = launch_dsum_range(p.nchan, 1, s->Pb[s->pcur], s->pcap, (int64_t)p.nchan * s->pcap,
-                                 s->U - s->ubase, s->Inext - s->ubase, cnt, s->d, s->Iout,
+                                 tl.U - ub_old, adv.u_first - ub_old, cnt, s->d, s->Iout,
                                  nullptr, cnt, cs)))
         return e;
       if ((e = stage_end(kStageDsum, cs, tok))) return e;
@@ -297,34 +288,33 @@ int issue_batch(cdd_server* sv, BatchRec& br) {
       if ((e = (int)hipMemcpyAsync(hout, s->Iout, cnt * sizeof(float), hipMemcpyDeviceToHost,
                                    cs)))
         return e;
-      br.outs.push_back({s->id, {s->Inext, cnt}});
+      br.outs.push_back({s->id, {adv.u_first, cnt}});
       br.host_outs.push_back(hout);
-      s->Inext = u_fin;
     }
-    // compaction: keep input from the next block's start, intensities from Inext
-    const int64_t pb_new = s->kn * p.M - p.nfront;
-    const int64_t keep = s->E - pb_new;
-    if (pb_new != s->pbase && !s->flushed) {
-      char* src = s->pend[s->cur] + (pb_new - s->pbase) * s->elem;
+    // compaction: keep input from the next block's start, intensities from
+    // the first output not yet final
+    const int64_t keep = tl.E - adv.pb_new;
+    if (adv.pb_new != tl.pbase && !s->flushed) {
+      char* src = s->pend[s->cur] + (adv.pb_new - tl.pbase) * s->elem;
       char* dst = s->pend[s->cur ^ 1];
       if (keep > 0 &&
           (e = (int)hipMemcpy2DAsync(dst, s->cap * s->elem, src, s->cap * s->elem,
                                      keep * s->elem, p.nchan, hipMemcpyDeviceToDevice, cs)))
         return e;
       s->cur ^= 1;
-      s->pbase = pb_new;
+      tl.pbase = adv.pb_new;
     }
-    if (s->Inext != s->ubase && !s->flushed) {
-      const int64_t pk = s->U - s->Inext;
+    if (adv.ub_new != tl.ubase && !s->flushed) {
+      const int64_t pk = tl.U - adv.ub_new;
       if (pk > 0 &&
           (e = (int)hipMemcpy2DAsync(s->Pb[s->pcur ^ 1], s->pcap * 4,
-                                     s->Pb[s->pcur] + (s->Inext - s->ubase), s->pcap * 4, pk * 4,
+                                     s->Pb[s->pcur] + (adv.ub_new - tl.ubase), s->pcap * 4, pk * 4,
                                      p.nchan, hipMemcpyDeviceToDevice, cs)))
         return e;
       s->pcur ^= 1;
-      s->ubase = s->Inext;
+      tl.ubase = adv.ub_new;
     }
-    if (s->flushed) s->total_int = s->E / p.n_int;
+    if (s->flushed) s->total_int = tl.E / p.n_int;
   }
   return (int)hipEventRecord(br.done, cs);
 }
@@ -492,16 +482,33 @@ cdd_status cdd_stream_open(cdd_server* sv, const cdd_stream_desc* d, int32_t* id
   if (s != CDD_OK) return s;
   if (!block_supported(p.N))
     return fail(CDD_ENOTSUP, "streams support fft_len up to 16384 (got %d)", p.N);
+  if (d->block_len < 0 || d->block_len > d->max_block)
+    return fail(CDD_EINVAL, "block_len must be in [0, max_block]");
   std::unique_ptr<Stream> st(new Stream());
   st->p = p;
   st->max_block = d->max_block;
+  st->block_len = d->block_len;
   st->elem = p.dtype == CDD_CI8 ? 2 : 8;
-  const size_t bytes = stream_bytes(p, d->max_block, sv->depth, &st->cap, &st->pcap, &st->icap);
+  st->g.N = p.N;
+  st->g.M = p.M;
+  st->g.nfront = p.nfront;
+  st->g.n_int = p.n_int;
+  st->g.front = p.front;
+  st->g.back = p.back;
+  st->g.d_max = p.d_max;
+  st->g.nchan = p.nchan;
+  st->g.elem = (int64_t)st->elem;
+  const Footprint fp = stream_footprint(st->g, d->max_block, sv->depth);
+  st->cap = fp.cap;
+  st->pcap = fp.pcap;
+  st->icap = fp.icap;
+  const size_t bytes = fp.bytes;
+  timeline_start(&st->tl, st->g);
   std::lock_guard<std::mutex> lk(sv->mu);
   int open = 0;
   for (auto& kv : sv->streams)
     if (!kv.second->released) ++open;
-  if (open >= sv->max_streams || sv->used + bytes > sv->budget) {
+  if (!admit(sv->used, sv->budget, open, sv->max_streams, bytes)) {
     sv->st.refused++;
     return fail(CDD_EAGAIN, "stream needs %zu bytes; %zu of %zu in use, %d streams open", bytes,
                 sv->used, sv->budget, open);
@@ -532,7 +539,6 @@ cdd_status cdd_stream_open(cdd_server* sv, const cdd_stream_desc* d, int32_t* id
     return fail(e == hipErrorOutOfMemory ? CDD_ENOMEM : CDD_EDEVICE, "stream open: %s",
                 hipGetErrorString(e));
   }
-  st->pbase = -p.nfront;  // the first block sees nfront zeros before sample 0
   st->bytes = bytes;
   st->id = sv->next_id++;
   sv->used += bytes;
@@ -555,10 +561,13 @@ cdd_status cdd_stream_push(cdd_server* sv, int32_t id, const void* host_block, i
   if (nsamp < 1 || nsamp > s->max_block)
     return fail(CDD_EINVAL, "block of %lld samples outside [1, %lld]", (long long)nsamp,
                 (long long)s->max_block);
-  if (seq < s->next_seq) {
+  if (s->block_len > 0 && (nsamp > s->block_len || s->short_seen))
+    return fail(CDD_EINVAL, "stream %d declared blocks of %lld samples; only the last may be "
+                "shorter", id, (long long)s->block_len);
+  if (classify_push(s->tl.next_seq, seq) == kPushStale) {
     sv->st.rejected++;
     return fail(CDD_EINVAL, "sequence %llu already seen (next is %llu)", (unsigned long long)seq,
-                (unsigned long long)s->next_seq);
+                (unsigned long long)s->tl.next_seq);
   }
   int free_slot = -1;
   for (size_t q = 0; q < s->slots.size(); ++q)
@@ -575,12 +584,12 @@ cdd_status cdd_stream_push(cdd_server* sv, int32_t id, const void* host_block, i
   if (e != hipSuccess) return fail(CDD_EDEVICE, "push copy: %s", hipGetErrorString(e));
   sl.nsamp = nsamp;
   sl.seq = seq;
-  sl.gap = seq > s->next_seq;
-  if (sl.gap) sv->st.gaps++;
+  if (timeline_push(&s->tl, s->g, seq, nsamp, s->block_len, &sl.zeros) == kPushGap)
+    sv->st.gaps++;
+  if (s->block_len > 0 && nsamp < s->block_len) s->short_seen = true;
   sl.t_arrive = now_s();
   if (sv->t_first < 0) sv->t_first = sl.t_arrive;
   sl.state = PUSHED;
-  s->next_seq = seq + 1;
   sv->st.blocks_in++;
   sv->pending_work++;
   sv->cv.notify_all();
@@ -591,7 +600,7 @@ cdd_status cdd_stream_push(cdd_server* sv, int32_t id, const void* host_block, i
 cdd_status cdd_stream_poll(cdd_server* sv, int32_t id, float* host_out, int64_t cap, int64_t* n,
                            int64_t* u_first) {
   if (!sv || !n || !u_first || (cap > 0 && !host_out)) return fail(CDD_EINVAL, "NULL argument");
-  std::lock_guard<std::mutex> lk(sv->mu);
+  std::unique_lock<std::mutex> lk(sv->mu);
   auto it = sv->streams.find(id);
   if (it == sv->streams.end()) return fail(CDD_EINVAL, "no stream %d", id);
   Stream* s = it->second.get();
@@ -602,7 +611,9 @@ cdd_status cdd_stream_poll(cdd_server* sv, int32_t id, float* host_out, int64_t 
   s->ready_first += k;
   s->polled += k;
   *n = k;
-  if (s->flushed && s->total_int >= 0 && s->polled >= s->total_int && !s->released) {
+  bool release = false;
+  if (s->flushed && s->total_int >= 0 && s->polled >= s->total_int && !s->released &&
+      !s->releasing) {
     bool idle = true;
     for (auto& sl : s->slots)
       if (sl.state != FREE) idle = false;
@@ -610,13 +621,36 @@ cdd_status cdd_stream_poll(cdd_server* sv, int32_t id, float* host_out, int64_t 
       if (br.busy)
         for (auto& o : br.outs)
           if (o.first == id) idle = false;
-    if (idle) {
-      (void)hipStreamSynchronize(sv->compute);
-      free_stream_mem(s);
-      s->released = true;
-      sv->used -= s->bytes;
-    }
+    release = idle;
   }
+  if (release) {
+    // the stream's memory is freed without the server lock held: the
+    // scheduler skips a flushed stream, and `releasing` keeps other callers off
+    s->releasing = true;
+    lk.unlock();
+    (void)hipStreamSynchronize(sv->compute);
+    free_stream_mem(s);
+    lk.lock();
+    s->released = true;
+    sv->used -= s->bytes;
+  }
+  clear_error();
+  return CDD_OK;
+}
+
+cdd_status cdd_stream_invalid(cdd_server* sv, int32_t id, int64_t* spans, int64_t cap,
+                              int64_t* n) {
+  if (!sv || !n || (cap > 0 && !spans)) return fail(CDD_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->streams.find(id);
+  if (it == sv->streams.end()) return fail(CDD_EINVAL, "no stream %d", id);
+  const auto& inv = it->second->tl.invalid;
+  const int64_t k = std::min<int64_t>(cap, (int64_t)inv.size());
+  for (int64_t i = 0; i < k; ++i) {
+    spans[2 * i] = inv[i].first;
+    spans[2 * i + 1] = inv[i].second;
+  }
+  *n = (int64_t)inv.size();
   clear_error();
   return CDD_OK;
 }
@@ -654,12 +688,9 @@ cdd_status cdd_server_stats_get(cdd_server* sv, cdd_server_stats* out) {
   std::lock_guard<std::mutex> lk(sv->mu);
   *out = sv->st;
   if (!sv->lat.empty()) {
-    std::vector<double> l = sv->lat;
-    std::sort(l.begin(), l.end());
-    auto q = [&](double f) { return l[std::min(l.size() - 1, (size_t)(f * (l.size() - 1) + 0.5))]; };
-    out->lat_p50_ms = q(0.50);
-    out->lat_p99_ms = q(0.99);
-    out->lat_max_ms = l.back();
+    out->lat_p50_ms = percentile(sv->lat, 0.50);
+    out->lat_p99_ms = percentile(sv->lat, 0.99);
+    out->lat_max_ms = percentile(sv->lat, 1.0);
   }
   out->wall_s = sv->t_first >= 0 ? sv->t_last - sv->t_first : 0;
   out->hbm_used = sv->used;

@@ -529,7 +529,13 @@ def test_autotuner_picks_a_valid_plan_and_plan_uses_it():
     flush("autotune: %s" % r)
     assert r["fft_len"] in (2048, 4096, 8192, 16384) and r["msamples_per_s"] > 0
     assert 0 <= r["kernel_variant"] < cdd.lib.cdd_kernel_variants(r["fft_len"])
+    # a schedule the persistent batched kernel runs, and a tile of the beam's trials
+    assert r["kernel_variant"] == 0 or (r["fft_len"], r["kernel_variant"]) in (
+        (4096, 3), (8192, 1), (8192, 2), (16384, 2))
+    assert r["dm_tile"] == len(dms)
     assert cdd.autotune(nchan, fcen, nchan * df, dms, 4) == r      # cached
+    one = cdd.autotune(nchan, fcen, nchan * df, [64.0], 4)
+    assert one["dm_tile"] == 1 and one["kernel_variant"] == 0
     v = _beam_int8(120, 20_000, nchan, fcen, nchan * df, 64.0)
     plan = cdd.Plan([dict(voltages=to_dev(v), f_centre=fcen, bw=nchan * df, dms=dms, n_int=4)],
                     autotune=True)

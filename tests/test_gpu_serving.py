@@ -36,6 +36,13 @@ def _stream_all(sv, sid, data, sizes, seq0=0):
     return u0, I
 
 
+def _push_retry(sv, sid, blk, seq):
+    """Push, waiting while the stream's queue is full."""
+    import time
+    while sv.push(sid, blk, seq) == -5:
+        time.sleep(0.0005)
+
+
 def _sizes(rng, total, lo, hi):
     out, s = [], 0
     while s < total:
@@ -211,3 +218,68 @@ def test_sequence_rules():
     sv.close()
     assert st["rejected"] == 1 and st["gaps"] == 1 and st["blocks_done"] == 2
     assert u0 == 0 and len(I) == 6000 // 4 and np.all(np.isfinite(I))
+
+
+def test_lost_blocks_with_declared_length_become_zeros_in_place():
+    """A stream with a declared block length loses two blocks: they come back
+    as zeros at their true position, so every output keeps its absolute
+    index and equals the whole record with those samples zero (and the
+    oracle on it: the values after the gap see a zero history); the outputs
+    the lost samples reach are reported."""
+    import torch
+    cdd = _cdd()
+    fcen, nchan, df, B, dm, n_int, N = 325.0, 16, 0.0625, 3000, 67.9, 4, 2048
+    v = _beam_int8(150, 8 * B, nchan, fcen, nchan * df, dm)
+    flush("stream with lost blocks 3 and 4 of 8, block_len %d" % B)
+    sv = cdd.Server()
+    sid = sv.open(0, nchan, fcen, nchan * df, dm, n_int, max_block=B, fft_len=N, block_len=B)
+    for seq in (0, 1, 2, 5, 6, 7):
+        _push_retry(sv, sid, v[seq * B:(seq + 1) * B], seq)
+    sv.close_stream(sid)
+    sv.sync()
+    u0, I = sv.poll(sid)
+    spans = sv.invalid(sid)
+    st = sv.stats()
+    sv.close()
+    z = v.copy()
+    z[3 * B:5 * B] = 0
+    assert u0 == 0 and len(I) == 8 * B // n_int
+    g = cdd.dedisperse(to_dev(z), fcen, nchan * df, dm, N, n_int)
+    torch.cuda.synchronize()
+    assert rel_l2(I, g["I"].cpu().numpy()) <= 1e-6
+    info = g["info"]
+    o = O.dedisperse(z, fcen, nchan * df, dm, n_int, fft_len=N, overlap=info["overlap"],
+                     nfront=info["nfront"])
+    assert rel_l2(I, o["I"]) <= 1e-4
+    after = slice(5 * B // n_int + info["d_max"] + 64, None)   # past the lost span's reach
+    assert rel_l2(I[after], o["I"][after]) <= 1e-4
+    assert st["gaps"] == 1 and len(spans) == 1
+    b0, b1 = spans[0]
+    d = O.channel_delays(fcen, nchan * df, nchan, dm, n_int)
+    assert b0 <= 3 * B // n_int - int(d.max()) and b1 >= 5 * B // n_int
+    assert 0 <= b0 < b1 <= len(I) + 1
+
+
+def test_lost_blocks_of_unknown_length_join_and_are_marked():
+    """Without a declared block length the block after a gap joins the data
+    before it: the output equals the whole-record result of the joined
+    record, and the outputs the junction reaches are reported."""
+    import torch
+    cdd = _cdd()
+    fcen, nchan, df, dm, n_int, N = 325.0, 8, 0.0625, 40.0, 4, 1024
+    v = _beam_int8(151, 9000, nchan, fcen, nchan * df, dm)
+    sv = cdd.Server()
+    sid = sv.open(0, nchan, fcen, nchan * df, dm, n_int, max_block=4000, fft_len=N)
+    _push_retry(sv, sid, v[:4000], 0)
+    _push_retry(sv, sid, v[4000:7000], 2)            # seq 1 lost, length unknown
+    _push_retry(sv, sid, v[7000:], 3)
+    sv.close_stream(sid)
+    sv.sync()
+    u0, I = sv.poll(sid)
+    spans = sv.invalid(sid)
+    sv.close()
+    g = cdd.dedisperse(to_dev(v), fcen, nchan * df, dm, N, n_int)
+    torch.cuda.synchronize()
+    assert len(I) == 9000 // n_int
+    assert rel_l2(I, g["I"].cpu().numpy()) <= 1e-6
+    assert len(spans) == 1 and spans[0][0] < 4000 // n_int < spans[0][1]
