@@ -537,17 +537,25 @@ def time_beam(cdd, torch, b, v, steps: int, warmup: int, taper: str = "none",
             "alg_hbm_frac": round(alg_bytes / (blk_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
         res["gflops_paper_eq5"] = round(flops / (blk_avg * 1e-3) / 1e9, 1)
     else:
-        # long transforms: four passes over HBM (columns, rows, inverse columns
-        # with voltages and |y|^2 out, integration).  Algorithmic bytes per
-        # sample: input, voltages (if asked) and the integrated output; design
-        # bytes at R = N/M: input R + 8R spectra, 8R + 8R, 8R + 4 (|y|^2) +
-        # voltages, 4 + 4/n_int
+        # long transforms: three passes over HBM (columns, rows, inverse
+        # columns with voltages out and the integration fused in).
+        # Algorithmic bytes per sample: input, voltages (if asked) and the
+        # integrated output; design bytes at R = N/M: input R + 8R spectra, 8R
+        # + 8R, 8R + voltages + 4/n_int, plus the partial sums of the groups
+        # split across column runs (two floats per run of G samples, written
+        # and read: 16R/G) -- or, where n_int does not divide G, |y|^2 written
+        # and read back by a separate integration (8)
         R = N / M
+        lg = int(round(math.log2(N)))
+        G = 16 if (1 << (lg // 2)) <= 512 else 8   # columns per workgroup
+        fused = G % b.n_int == 0
         alg = in_bytes + out_bytes + 4.0 / b.n_int
-        design = (in_bytes + 32.0) * R + 8.0 + 4.0 / b.n_int + out_bytes
+        design = ((in_bytes + 32.0) * R + 4.0 / b.n_int + out_bytes +
+                  (16.0 * R / G if fused else 8.0))
         gbs = alg * samples / (blk_avg * 1e-3) / 1e9
         dgbs = design * samples / (blk_avg * 1e-3) / 1e9
-        res["roofline"] = {"kernel": "four-step passes (cols_fwd, rows, cols_inv, integrate)",
+        res["roofline"] = {"kernel": "four-step passes (cols_fwd, rows, cols_inv with "
+                                     "integration, split-group fix-up)",
                            "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                            "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
                            "traffic": measured_traffic("fourstep_passes", workload),

@@ -56,6 +56,14 @@ struct LargeArgs {
   double bw;
   const float2* hb;
   int32_t lgn;  // log2(N1 N2)
+  // fused detection + integration in cols_inv (n_int divides the G columns
+  // of a workgroup): P and the t_int outputs per channel, and the partial
+  // sums of the groups that straddle two column runs (in p: per item, two
+  // per run of G samples)
+  float* P;
+  int64_t t_int;
+  int32_t n_int;
+  int32_t fuse;
 };
 
 // exp(-2 pi i m / M) for M = 2^lg <= 2^23: (m + M/2) mod M over M is exact in
@@ -225,6 +233,31 @@ __global__ __launch_bounds__(SC::T * G) void cols_inv_kernel(const LargeArgs a) 
       v[b * RI + r] = S[(int64_t)k2 * a.N1 + n1];
     }
   fft_inverse<SC>(v, lds + g * (SC::lds_floats() + 1), a.twc, tl);
+  if (!a.fuse) {
+#pragma unroll
+    for (int b = 0; b < B0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int n2 = tl + SC::T * b + r * (L / R0);
+        const int64_t n = n1 + (int64_t)a.N1 * n2;
+        const int64_t m = n - a.nfront;
+        const int64_t o = k * a.M + m;
+        if (m >= 0 && m < a.M && o < a.nsamp) {
+          const float2 z = v[b * R0 + r];
+          a.p[(int64_t)c * a.nsamp + o] = z.x * z.x + z.y * z.y;
+          if (a.vout) a.vout[(int64_t)c * a.nsamp + o] = z;
+        }
+      }
+    return;
+  }
+  // Fused detection and integration.  The workgroup holds, for each n2, the
+  // run of G consecutive samples n = n1b + N1 n2 + g (g < G).  |z|^2 of the
+  // kept samples goes to LDS as [n2][g]; groups of n_int start where
+  // n = nfront (mod n_int).  Groups inside a run are summed here and stored;
+  // a group split across the end of one run and the start of the next is
+  // left as two partial sums for integrate_fixup_kernel.
+  __syncthreads();  // the transform's last LDS reads are done
+  float* q = lds;
 #pragma unroll
   for (int b = 0; b < B0; ++b)
 #pragma unroll
@@ -233,12 +266,67 @@ __global__ __launch_bounds__(SC::T * G) void cols_inv_kernel(const LargeArgs a) 
       const int64_t n = n1 + (int64_t)a.N1 * n2;
       const int64_t m = n - a.nfront;
       const int64_t o = k * a.M + m;
-      if (m >= 0 && m < a.M && o < a.nsamp) {
-        const float2 z = v[b * R0 + r];
-        a.p[(int64_t)c * a.nsamp + o] = z.x * z.x + z.y * z.y;
-        if (a.vout) a.vout[(int64_t)c * a.nsamp + o] = z;
-      }
+      const float2 z = v[b * R0 + r];
+      const bool kept = m >= 0 && m < a.M && o < a.nsamp;
+      if (kept && a.vout) a.vout[(int64_t)c * a.nsamp + o] = z;
+      q[n2 * G + g] = kept ? z.x * z.x + z.y * z.y : 0.f;
     }
+  __syncthreads();
+  const int ni = a.n_int;
+  const int phi = (int)(a.nfront % ni);
+  const int per_run = G / ni;  // group starts per run
+  const int n1b = n1 - g;
+  const int64_t item_local = item - a.item0;
+  float* part = a.p + item_local * ((int64_t)a.N1 * a.N2 / G) * 2;
+  float* Pc = a.P + (int64_t)c * a.t_int;
+  for (int j = threadIdx.x; j < L * (per_run + 1); j += SC::T * G) {
+    const int n2 = j / (per_run + 1), slot = j - n2 * (per_run + 1);
+    const float* run = q + n2 * G;
+    const int64_t n0 = n1b + (int64_t)a.N1 * n2;  // first sample of the run
+    const int64_t ridx = n0 / G;                   // run index in the block
+    if (slot == per_run) {
+      // partial sums: the head [0, phi) and the tail [G - ni + phi, G)
+      if (phi == 0) continue;
+      float h = 0.f, t = 0.f;
+      for (int i = 0; i < phi; ++i) h += run[i];
+      for (int i = G - ni + phi; i < G; ++i) t += run[i];
+      part[2 * ridx] = h;
+      part[2 * ridx + 1] = t;
+      continue;
+    }
+    const int s0 = phi + slot * ni;  // group start within the run
+    if (s0 + ni > G) continue;       // the split group (partials above)
+    const int64_t m = n0 + s0 - a.nfront;
+    if (m < 0 || m >= a.M) continue;
+    const int64_t u = (k * a.M + m) / ni;
+    if (u >= a.t_int) continue;
+    float acc = 0.f;
+    for (int i = 0; i < ni; ++i) acc += run[s0 + i];
+    Pc[u] = acc;
+  }
+}
+
+// The integration groups split across two runs of G samples: the tail of
+// run j plus the head of run j + 1 (partial sums from cols_inv_kernel).
+__global__ __launch_bounds__(256) void integrate_fixup_kernel(const LargeArgs a, int32_t G,
+                                                              int64_t items) {
+  const int64_t runs = (int64_t)a.N1 * a.N2 / G;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= items * (runs - 1)) return;
+  const int64_t item_local = idx / (runs - 1);
+  const int64_t j = idx - item_local * (runs - 1);
+  const int64_t item = a.item0 + item_local;
+  const int c = (int)(item / a.nblocks);
+  const int64_t k = item - (int64_t)c * a.nblocks;
+  const int ni = a.n_int;
+  const int phi = (int)(a.nfront % ni);
+  const int64_t start = j * G + G - ni + phi;  // first sample of the split group
+  const int64_t m = start - a.nfront;
+  if (m < 0 || m >= a.M) return;
+  const int64_t u = (k * a.M + m) / ni;
+  if (u >= a.t_int) return;
+  const float* part = a.p + item_local * runs * 2;
+  a.P[(int64_t)c * a.t_int + u] = part[2 * j + 1] + part[2 * (j + 1)];
 }
 
 // P[c][u] = sum_{r < n_int} p[c][u n_int + r] in ascending r, grid (u
@@ -284,6 +372,19 @@ static int launch_integrate(const float* p, float* P, int64_t nsamp, int64_t t_i
     hipLaunchKernelGGL(integrate_kernel<2>, grid, dim3(256), 0, st, p, P, nsamp, t_int, n_int);
   else
     hipLaunchKernelGGL(integrate_kernel<1>, grid, dim3(256), 0, st, p, P, nsamp, t_int, n_int);
+  return (int)hipGetLastError();
+}
+
+// The split integration groups of one chunk of items (fused path); none when
+// the groups start on run boundaries.
+static int launch_fixup(const LargeArgs& a, int G, int64_t items, hipStream_t st) {
+  if (a.nfront % a.n_int == 0) return 0;
+  const int64_t runs = (int64_t)a.N1 * a.N2 / G;
+  const int64_t n = items * (runs - 1);
+  const int64_t nb = (n + 255) / 256;
+  if (nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+  if (nb == 0) return 0;
+  hipLaunchKernelGGL(integrate_fixup_kernel, dim3((unsigned)nb), dim3(256), 0, st, a, G, items);
   return (int)hipGetLastError();
 }
 
@@ -538,6 +639,10 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
   a.df = p.df;
   a.dconst = p.dconst;
   a.dm = dm;
+  a.P = P;
+  a.t_int = p.t_int;
+  a.n_int = p.n_int;
+  a.fuse = GC % p.n_int == 0 ? 1 : 0;
   hipStream_t st = (hipStream_t)stream;
   const int64_t items = (int64_t)p.nchan * p.nblocks;
   const int64_t chunk = large_chunk_items(p);
@@ -562,10 +667,11 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
     hipLaunchKernelGGL((rows_kernel<SR, GR>), dim3((unsigned)gr), dim3(SR::T * GR), 0, st, a);
     hipLaunchKernelGGL((cols_inv_kernel<SC, GC>), dim3((unsigned)gc), dim3(SC::T * GC), 0, st,
                        a);
+    if (a.fuse && (e = launch_fixup(a, GC, q, st))) return e;
     e = (int)hipGetLastError();
     if (e) return e;
   }
-  return launch_integrate(pbuf, P, p.nsamp, p.t_int, p.n_int, p.nchan, st);
+  return a.fuse ? 0 : launch_integrate(pbuf, P, p.nsamp, p.t_int, p.n_int, p.nchan, st);
 }
 
 // exp(+i pi c / L), c < L: the post-twiddle of the packed real inverse.
@@ -651,6 +757,10 @@ static int launch_fullband_t(const FullbandPlan& f, const float* series, float2*
   a.dconst = f.dconst;
   a.dm = f.dm;
   a.hb = hb;
+  a.P = I;
+  a.t_int = f.t_int;
+  a.n_int = f.n_int / 2;  // pairs of real samples
+  a.fuse = GC % (f.n_int / 2) == 0 ? 1 : 0;
   hipStream_t st = (hipStream_t)stream;
   constexpr int64_t NP = (int64_t)1 << LGN;
   hipLaunchKernelGGL(band_chirp_table_kernel, dim3((unsigned)((NP + 256) / 256)), dim3(256), 0,
@@ -667,10 +777,11 @@ static int launch_fullband_t(const FullbandPlan& f, const float* series, float2*
                        a);
     hipLaunchKernelGGL((cols_inv_kernel<SC, GC>), dim3((unsigned)gc), dim3(SC::T * GC), 0, st,
                        a);
+    if (a.fuse && (e = launch_fixup(a, GC, q, st))) return e;
     e = (int)hipGetLastError();
     if (e) return e;
   }
-  return launch_integrate(pbuf, I, f.nsamp / 2, f.t_int, f.n_int / 2, 1, st);
+  return a.fuse ? 0 : launch_integrate(pbuf, I, f.nsamp / 2, f.t_int, f.n_int / 2, 1, st);
 }
 
 int launch_fullband(const FullbandPlan& f, const float* series, void* Sv, float* pbuf,
