@@ -60,10 +60,10 @@ def flops_per_output_sample(N: int, M: int) -> float:
     return (10.0 * math.log2(N) + 6.0) * N / M + 4.0
 
 
-def source_digest() -> str:
-    """Digest of the sources the block kernel is compiled from."""
+def source_digest(files=("cdd_block.hip", "cdd_fft.h", "cdd_internal.h")) -> str:
+    """Digest of the sources a kernel is compiled from."""
     h = hashlib.sha256()
-    for f in ("cdd_block.hip", "cdd_fft.h", "cdd_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1509_00186_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -78,7 +78,8 @@ def measured_traffic(kernel: str, workload: str):
         rec = data[kernel][workload]
     except Exception:
         return None
-    if rec.get("source_digest") != source_digest():
+    files = rec.get("sources", ["cdd_block.hip", "cdd_fft.h", "cdd_internal.h"])
+    if rec.get("source_digest") != source_digest(files):
         return None
     return rec.get("bytes_per_launch")
 
@@ -645,7 +646,7 @@ def config3_leg(cdd, torch, steps: int, warmup: int, nerr_chan: int = 48):
     return res
 
 
-def other_legs(cdd, torch, vd, b, args):
+def other_legs(cdd, torch, vd, b, args, only=""):
     """Every other workload of the benchmark, each a sub-object of the line:
     DM trials (batched against the loop, fixed and autotuned N), the full
     band, the single-channel long transforms (at 2^23 samples and at 2^26,
@@ -668,6 +669,10 @@ def other_legs(cdd, torch, vd, b, args):
         legs += [("dm_trials_autotuned",
                   lambda: dm_trials(cdd, torch, vd, b, None, taper=args.taper, autotune=True)),
                  ("dm_trials", lambda: dm_trials(cdd, torch, vd, b, None, taper=args.taper))]
+    if only:
+        legs = [lg for lg in legs if lg[0] == only]
+        if not legs:
+            raise SystemExit("no leg named %r" % only)
     out = {}
     for name, fn in legs:
         try:
@@ -699,6 +704,9 @@ def main():
     ap.add_argument("--seconds", type=float, default=10.0, help="serving run length (config 5)")
     ap.add_argument("--nsamp", type=int, default=0,
                     help="config 1 only: a noise record of this many samples instead")
+    ap.add_argument("--leg", default="",
+                    help="only this sub-object of the default line (e.g. dm_trials, "
+                         "dm_trials_autotuned, config4_multibeam), for profiling")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -770,6 +778,10 @@ def main():
 
     b, v = pre if pre is not None else make_input(args.config)
     vd = torch.from_numpy(v).to(torch.device("cuda:0"))
+    if args.leg:
+        r = other_legs(cdd, torch, vd, b, args, only=args.leg)
+        print(json.dumps({"leg": args.leg, **r}), flush=True)
+        return
     samples = b.nchan * b.nsamp
     extras = {}
     # the headline's outputs and workspace are allocated first, so that no
