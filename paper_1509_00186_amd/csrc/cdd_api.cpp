@@ -511,7 +511,10 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
       LaunchDesc d;
       size_t slot = 0;
       int round = 0;
-      size_t beam = 0;  // pipelined form
+      size_t beam = 0;   // pipelined form
+      bool direct = false;  // one beam, one DM: the one-shot block kernel
+      BatchBeam bb;
+      const void* h = nullptr;
     };
     std::vector<Launch> launches;
     std::vector<char> staged(plan->host_tab_bytes, 0);
@@ -536,9 +539,16 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
           L.beam = b;
           L.slot = slot_bytes * ((size_t)r * slots_per_round + j);
           const void* h = H[b];
-          if ((e = prepare_launch(h ? kLaunchTables : kLaunchBatch, &bb, &h, 1,
-                                  staged.data() + L.slot, &L.d)))
+          if (h) {
+            // a beam with its chirp table: the one-shot call's own kernel,
+            // its arguments passed by value
+            L.direct = true;
+            L.bb = bb;
+            L.h = h;
+          } else if ((e = prepare_launch(kLaunchBatch, &bb, &h, 1, staged.data() + L.slot,
+                                         &L.d))) {
             return device_fail("launch table", e);
+          }
           launches.push_back(L);
         }
         continue;
@@ -580,42 +590,53 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
       void* tok = nullptr;
       int err = 0;
       if ((err = stage_begin(kStageBlock, stream, &tok))) return device_fail("event record", err);
-      if ((err = enqueue_launch(L.d, (char*)plan->host_tab + L.slot, ws + plan->tab_off + L.slot,
-                                counter, stream)))
-        return device_fail("batched launch", err);
+      if (L.direct)
+        err = launch_block_co(*L.bb.p, L.bb.co, L.bb.xt, L.bb.dms, L.bb.P, nullptr, L.h, stream);
+      else
+        err = enqueue_launch(L.d, (char*)plan->host_tab + L.slot, ws + plan->tab_off + L.slot,
+                             counter, stream);
+      if (err) return device_fail("batched launch", err);
       if ((err = stage_end(kStageBlock, stream, tok))) return device_fail("event record", err);
       return CDD_OK;
     };
-    // Round 0: the layout change (and chirp table) of each beam on the
-    // auxiliary stream, in the order above; in the pipelined form each beam's
-    // launch follows on the caller's stream as soon as its input is in place,
-    // so later beams' layout changes run beside earlier beams' transforms.
+    // Round 0.  The chirp tables of the one-DM beams are built on the
+    // auxiliary stream while the caller's stream changes the layout of the
+    // first beam.  In the pipelined form each beam then takes its layout
+    // change, its launch and its delays and aligned sums in turn on the
+    // caller's stream (running the layout changes of later beams beside the
+    // transforms of earlier ones slows both down on this GPU as much as it
+    // hides); the single-launch form changes every layout first.
     AuxSession aux;
     if ((e = aux_open(stream, &aux))) return device_fail("auxiliary stream", e);
     size_t li = 0;
     cdd_status st = CDD_OK;
+    bool tables_waited = false;
     for (size_t j = 0; j < nb && st == CDD_OK; ++j) {
       const size_t b = order[j];
       const BeamPlan& p = plan->beams[b];
       int err = 0;
       void* tok = nullptr;
-      if (H[b]) {
-        if ((err = stage_begin(kStageDelays, aux.aux, &tok)) ||
-            (err = launch_chirp_table(p, p.dms[0], H[b], aux.aux)) ||
-            (err = stage_end(kStageDelays, aux.aux, tok))) {
-          st = device_fail("chirp table launch", err);
-          break;
-        }
-      }
-      if (p.nchan > 1 && (err = launch_transposed(p, plan->desc[b].voltages, (void*)xt[b],
-                                                  aux.aux))) {
+      if (H[b] && ((err = stage_begin(kStageDelays, aux.aux, &tok)) ||
+                   (err = launch_chirp_table(p, p.dms[0], H[b], aux.aux)) ||
+                   (err = stage_end(kStageDelays, aux.aux, tok))))
+        st = device_fail("chirp table launch", err);
+    }
+    for (size_t j = 0; j < nb && st == CDD_OK; ++j) {
+      const size_t b = order[j];
+      const BeamPlan& p = plan->beams[b];
+      int err = 0;
+      if (p.nchan > 1 &&
+          (err = launch_transposed(p, plan->desc[b].voltages, (void*)xt[b], stream))) {
         st = device_fail("transpose launch", err);
         break;
       }
       if (plan->single_launch) continue;
-      if ((err = aux_mark(&aux, stream))) {
-        st = device_fail("stream wait", err);
-        break;
+      if (!tables_waited) {
+        if ((err = aux_mark(&aux, stream))) {
+          st = device_fail("stream wait", err);
+          break;
+        }
+        tables_waited = true;
       }
       while (st == CDD_OK && li < launches.size() && launches[li].round == 0 &&
              launches[li].beam == b)

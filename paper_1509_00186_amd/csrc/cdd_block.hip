@@ -238,10 +238,10 @@ __device__ __forceinline__ void load_block(float2* v, const BlockArgs& a, int c,
       float2 z = make_float2(0.f, 0.f);
       if (tt >= 0 && tt < a.x_len) {
         if constexpr (DT == CDD_CI8) {
-          const short w = ((const short*)a.x)[(int64_t)c * a.x_stride + tt];
+          const short w = gptr((const short*)a.x)[(int64_t)c * a.x_stride + tt];
           z = make_float2((float)(signed char)(w & 0xff), (float)(signed char)(w >> 8));
         } else {
-          z = ((const float2*)a.x)[(int64_t)c * a.x_stride + tt];
+          z = gload2((const float2*)a.x, (int64_t)c * a.x_stride + tt);
         }
       }
       v[b * R + r] = z;
@@ -262,7 +262,7 @@ __device__ __forceinline__ void epilogue(const float2* v, float* lds, const Bloc
           const int n = t + S::T * b + r * (N / R);
           const int m = n - a.nfront;
           const int64_t o = k * a.M + m;
-          if (m >= 0 && m < a.M && o < a.o_lim) a.vout[(int64_t)c * a.v_stride + o] = v[b * R + r];
+          if (m >= 0 && m < a.M && o < a.o_lim) gstore2(a.vout, (int64_t)c * a.v_stride + o, v[b * R + r]);
         }
       }
     }
@@ -283,7 +283,7 @@ __device__ __forceinline__ void epilogue(const float2* v, float* lds, const Bloc
   if (!live) return;  // a workgroup's spare transform: its barriers only
   const int nu = a.M / a.n_int;
   const int64_t u0 = k * (a.M / a.n_int);
-  float* P = a.P + (int64_t)dmi * a.p_dm_stride + (int64_t)c * a.p_stride;
+  const auto P = gptr(a.P) + (int64_t)dmi * a.p_dm_stride + (int64_t)c * a.p_stride;
   if (a.n_int == 4 && (a.nfront & 3) == 0) {
     for (int ul = t; ul < nu; ul += S::T) {
       const int64_t u = u0 + ul;

@@ -52,6 +52,31 @@ constexpr double ct_cos2pi(int m, int R) { return ct_cos(2.0 * kPi * ct_wrap(m, 
 constexpr double ct_sin2pi(int m, int R) { return ct_sin(2.0 * kPi * ct_wrap(m, R) / R); }
 
 // ---------------------------------------------------------------------------
+// Global-memory pointers
+// ---------------------------------------------------------------------------
+// A pointer that a kernel reads out of a table in device memory (rather than
+// receiving as a kernel argument) is generic to the compiler, which then
+// emits flat loads and stores; those also count against the LDS wait
+// counter, so every LDS wait of the transform waits for them too.  gptr
+// states that the pointer is into global memory.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+// float2 element i through a global-memory pointer (the vector type's own
+// assignment cannot take an operand in another address space)
+__device__ __forceinline__ float2 gload2(const float2* p, int64_t i) {
+  return __builtin_bit_cast(float2, gptr((const unsigned long long*)p)[i]);
+}
+__device__ __forceinline__ void gstore2(float2* p, int64_t i, float2 v) {
+  gptr((unsigned long long*)p)[i] = __builtin_bit_cast(unsigned long long, v);
+}
+
+// ---------------------------------------------------------------------------
 // Complex arithmetic on float2
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -277,7 +302,7 @@ struct PassTw {
         const int k = (t + S::T * b) & (NS - 1);
         const float2* col = tw + TWOFF + k;
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[b * (R - 1) + r - 1] = col[r * NS];
+        for (int r = 1; r < R; ++r) w[b * (R - 1) + r - 1] = gload2(col, r * NS);
       }
     }
   }

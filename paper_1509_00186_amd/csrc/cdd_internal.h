@@ -110,7 +110,8 @@ int fork_join(void* stream, const std::function<int(void*)>& aux_work,
 // The library's auxiliary stream of the current device, held (one user at a
 // time) from aux_open to aux_close: aux_open makes it start after the work
 // already on `stream`; aux_mark makes `waiting` wait for everything enqueued
-// on it so far; aux_close makes `stream` wait for all of it and releases it.
+// on it so far; aux_after makes it wait for what `stream` holds so far;
+// aux_close makes `stream` wait for all of it and releases it.
 struct AuxSession {
   std::unique_lock<std::mutex> lk;
   void* aux = nullptr;   // hipStream_t
@@ -118,6 +119,7 @@ struct AuxSession {
 };
 int aux_open(void* stream, AuxSession* session);
 int aux_mark(AuxSession* session, void* waiting);
+int aux_after(AuxSession* session, void* stream);  // aux waits for `stream`'s work so far
 int aux_close(void* stream, AuxSession* session);
 // Batched form: beams, each with its DM tile, in one launch.
 struct BatchBeam {

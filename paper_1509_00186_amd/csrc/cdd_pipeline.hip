@@ -154,6 +154,14 @@ int aux_mark(AuxSession* session, void* waiting) {
   return (int)e;
 }
 
+int aux_after(AuxSession* session, void* stream) {
+  Aux& ax = *(Aux*)session->impl;
+  hipEvent_t ev = take(ax);
+  hipError_t e = hipEventRecord(ev, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(ax.s, ev, 0);
+  return (int)e;
+}
+
 int aux_close(void* stream, AuxSession* session) {
   int err = session->impl ? aux_mark(session, stream) : 0;
   session->impl = nullptr;
