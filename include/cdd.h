@@ -328,11 +328,11 @@ cdd_status cdd_fullband_dedisperse(const void* spectra, int64_t nspec, int32_t n
  * every DM trial reuses it; the chirp is generated on the fly per trial.
  * All trials of a beam share one (N, L, nfront), planned for the largest
  * |DM| of the beam (overlap rules as cdd_query over all its DMs).  By
- * default the layout change of each beam runs on a second stream and the
- * beam's launch (the kernel specialised for its length: a persistent one
- * over its DM tile, or one workgroup per block for a single DM) follows as
- * soon as its input is in place, so the memory-bound layout changes of
- * later beams run beside the transforms of earlier ones.  With
+ * default each beam takes, in turn on the caller's stream, its layout
+ * change, its launch (the kernel specialised for its length: a persistent
+ * one over its DM tile, or one workgroup per block for a single DM) and
+ * its delays and aligned sums; the chirp tables of one-DM beams are built
+ * on an auxiliary stream beside the first layout change.  With
  * opts->single_launch, every beam of length 256 .. 8192 (and one sample
  * type) shares one persistent launch per round of DM tiles instead, longest
  * work per workgroup first (that kernel holds the largest length's register
