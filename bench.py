@@ -178,11 +178,7 @@ def fullband(cdd, torch, steps: int, warmup: int, sweep: bool = True):
     st = cdd.profile_read()
     T = info["nsamp"]
     r = info["fft_len"] / info["step"]
-    # bytes the passes must move per real sample: records in (1) and series out
-    # (4); column, row and column passes each read and write the 8-byte packed
-    # spectra of 2 samples, times the N/M re-transform of the overlap; |y|^2 of
-    # each pair (2) written and read back; I written
-    design = 5.0 + 20.0 * r + 4.0 + 4.0 / n_int
+    design = fullband_design_bytes(r, n_int)
     inv_ms = st["transpose"][0] / max(st["transpose"][1], 1)
     long_ms = st["block"][0] / max(st["block"][1], 1)
     # longer transforms than the rule's minimum re-transform less overlap
@@ -196,6 +192,8 @@ def fullband(cdd, torch, steps: int, warmup: int, sweep: bool = True):
         torch.cuda.synchronize()
         by_len[str(1 << lg)] = round((time.perf_counter() - t1) / steps * 1e3, 4)
         del o2
+    del out
+    limit = fullband_dm_limit(cdd, torch, max(2, steps // 4))
     return {"workload": WORKLOADS[6], "plan": {k: info[k] for k in ("fft_len", "overlap",
                                                                    "nfront", "nblocks")},
             "ms_per_call": round(dt * 1e3, 4),
@@ -206,7 +204,52 @@ def fullband(cdd, torch, steps: int, warmup: int, sweep: bool = True):
             "design_bytes_per_sample": round(design, 2),
             "design_hbm_frac": round(design * T / dt / 1e9 / PEAK_HBM_GBS, 4),
             "inverse_transform_gbs": round(5.0 * T / (inv_ms * 1e-3) / 1e9, 1),
-            "ms_per_call_by_fft_len": by_len}
+            "ms_per_call_by_fft_len": by_len,
+            "dm_limit_sec4_5": limit}
+
+
+def fullband_design_bytes(r, n_int, fft_len=0, group=16):
+    """Bytes the full-band passes must move per real output sample: records in
+    (1) and series out (4); column, row and column passes each read and write
+    the 8-byte packed spectra of 2 samples, times the N/M re-transform of the
+    overlap (above 2^23 real points the column transforms take two passes
+    each way: 16 more); I written.  With integration fused into the last
+    column pass (n_int/2 dividing its group of 16 pairs) two partial sums per
+    group are written and read back; otherwise the power of each pair (4
+    bytes per pair) is written and read back."""
+    passes = 20.0 + (16.0 if fft_len > (1 << 23) else 0.0)
+    base = 5.0 + passes * r + 4.0 / n_int
+    if group % (n_int // 2) == 0:
+        return base + 16.0 * r / (2 * group)
+    return base + 4.0
+
+
+def fullband_dm_limit(cdd, torch, steps):
+    """The first of Sec. 4.5's memory-bound real-time limits: DM 3000 over 16 MHz
+    at 610 MHz, planned by the length rule at 2^27 real points (L = 2^26),
+    on 2^27 real samples (131072 records of 512 bins, 4.19 s): two blocks."""
+    import synth
+    nspec, nchan, fcen, bw, dm, n_int = 1 << 17, 512, 610.0, 16.0, 3000.0, 16
+    sp = torch.from_numpy(synth.noise_int8(synth.rng_for(7), nspec, nchan, 20.0)).cuda()
+    out = cdd.fullband(sp, fcen, bw, dm, n_int)
+    info = out["info"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cdd.fullband(sp, fcen, bw, dm, n_int, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    T = info["nsamp"]
+    r = info["fft_len"] / info["step"]
+    design = fullband_design_bytes(r, n_int, info["fft_len"])
+    del out, sp
+    return {"what": "DM 3000, 16 MHz at 610 MHz, 2^27 real samples (4.19 s), n_int 16",
+            "plan": {k: info[k] for k in ("fft_len", "overlap", "nfront", "nblocks")},
+            "ms_per_call": round(dt * 1e3, 4),
+            "x_realtime": round(T / (2 * bw) / 1e6 / dt, 1),
+            "design_bytes_per_sample": round(design, 2),
+            "design_hbm_frac": round(design * T / dt / 1e9 / PEAK_HBM_GBS, 4),
+            "steps": steps}
 
 
 def _time(fn, torch, reps):
@@ -548,11 +591,13 @@ def time_beam(cdd, torch, b, v, steps: int, warmup: int, taper: str = "none",
         # and read back by a separate integration (8)
         R = N / M
         lg = int(round(math.log2(N)))
-        G = 16 if (1 << (lg // 2)) <= 512 else 8   # columns per workgroup
+        # columns per workgroup of the last column pass (length 2^(lg/2), or
+        # 128 when the column transforms are split in two above 2^22)
+        G = 16 if (lg > 22 or (1 << (lg // 2)) <= 512) else 8
         fused = G % b.n_int == 0
         alg = in_bytes + out_bytes + 4.0 / b.n_int
-        design = ((in_bytes + 32.0) * R + 4.0 / b.n_int + out_bytes +
-                  (16.0 * R / G if fused else 8.0))
+        design = ((in_bytes + 32.0 + (32.0 if lg > 22 else 0.0)) * R + 4.0 / b.n_int +
+                  out_bytes + (16.0 * R / G if fused else 8.0))
         gbs = alg * samples / (blk_avg * 1e-3) / 1e9
         dgbs = design * samples / (blk_avg * 1e-3) / 1e9
         res["roofline"] = {"kernel": "four-step passes (cols_fwd, rows, cols_inv with "

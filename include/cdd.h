@@ -161,7 +161,7 @@ typedef struct {
  * channel edges; L = next power of two >= front + back (>= 1), raised until
  * n_int divides N - L; nfront = front + (L - front - back) / 2; N (if 0) =
  * max(smallest power of two > 2 x the widest channel's dispersion samples,
- * 2L, 256).  EINVAL if N is not a power of two in [256, 2^22], if
+ * 2L, 256).  EINVAL if N is not a power of two in [256, 2^26], if
  * L >= N ("DM too large for fft_len"), or on any invalid argument below.
  */
 cdd_status cdd_query(int32_t dtype, int64_t nsamp, int32_t nchan,
@@ -296,8 +296,8 @@ cdd_status cdd_gsb_inverse(const void* spectra, int64_t nspec, int32_t nchan, fl
  * explicit_plan (fft_len, overlap, nfront even) apply.
  * Errors: EINVAL for nspec < 1, nchan not a power of two in [128, 2048],
  * n_int odd or < 2 or above nsamp, bw <= 0, f_centre - bw/2 <= 0, non-finite
- * values, fft_len not a power of two in [2^16, 2^23], an overlap shorter
- * than the impulse response; ENOTSUP when the rule asks for more than 2^23
+ * values, fft_len not a power of two in [2^16, 2^27], an overlap shorter
+ * than the impulse response; ENOTSUP when the rule asks for more than 2^27
  * points, for CDD_PHASE_FP32, npol, kernel_variant or time_chunks.
  */
 cdd_status cdd_fullband_query(int64_t nspec, int32_t nchan, double f_centre_mhz, double bw_mhz,

@@ -146,7 +146,8 @@ static FullbandWs fullband_ws(const FullbandPlan& f) {
   w.s_off = off;
   off = align256(off + (size_t)fullband_chunk_blocks(f) * (size_t)(f.N / 2) * 8);
   w.pb_off = off;
-  off = align256(off + (size_t)(f.nsamp / 2) * sizeof(float));
+  off = align256(off + std::max((size_t)(f.nsamp / 2) * sizeof(float),
+                                 large_partial_bytes(f.N / 2, fullband_chunk_blocks(f))));
   w.h_off = off;
   off = align256(off + (size_t)(f.N / 2 + 1) * 8);
   w.total = off;

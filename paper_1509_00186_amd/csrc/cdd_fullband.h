@@ -23,7 +23,7 @@ struct FullbandPlan {
 };
 
 constexpr int kMinFullband = 1 << 16;  // real points (2^15 packed complex)
-constexpr int kMaxFullband = 1 << 23;
+constexpr int kMaxFullband = 1 << 27;
 
 bool gsb_supported(int nchan);  // nchan a power of two in [128, 2048]
 // Inverse transform of nspec records of nchan int8 (re, im) bins into
@@ -33,7 +33,8 @@ int launch_gsb_inverse(const void* spec, int64_t nspec, int32_t nchan, float* se
 int64_t fullband_chunk_blocks(const FullbandPlan& f);  // blocks per chunk of spectra
 // Overlap-save of the real series with the band chirp, y^2 integrated into
 // intensity [t_int]; vout (nullable) receives the dedispersed series [nsamp].
-// S holds fullband_chunk_blocks * N/2 complex values, pbuf nsamp/2 floats,
+// S holds fullband_chunk_blocks * N/2 complex values, pbuf nsamp/2 floats
+// (or large_partial_bytes of a chunk, if more),
 // H the call's chirp function, N/2 + 1 complex values.
 int launch_fullband(const FullbandPlan& f, const float* series, void* S, float* pbuf, void* H,
                     float* intensity, float* vout, void* stream);

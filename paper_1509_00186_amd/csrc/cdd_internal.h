@@ -14,7 +14,7 @@ namespace cdd {
 
 constexpr double kDefaultD = 4.148808e9;  // Eq. 3's D (us MHz^2 cm^3 / pc)
 constexpr int kMinFFT = 256;
-constexpr int kMaxFFT = 1 << 22;
+constexpr int kMaxFFT = 1 << 26;
 constexpr int kMaxDmTile = 64;            // DM trials per batched launch
 constexpr int64_t kMaxChunks = 12;        // time chunks of the pipelined one-shot path
 
@@ -184,6 +184,9 @@ int launch_dsum_range(int nchan, int ndm, const float* P, int64_t p_stride,
 bool block_supported(int N);
 bool large_supported(int N);
 int64_t large_chunk_items(const BeamPlan& p);  // (channel, block) items per chunk
+// bytes of the partial integration sums of `items` N-point items (the
+// |y|^2 buffer holds them when integration is fused; it must be this large)
+size_t large_partial_bytes(int64_t N, int64_t items);
 int launch_large(const BeamPlan& p, const void* xt, double dm, void* S, float* pbuf,
                  float* P, void* vout, void* stream);
 int block_variants(int N);  // number of schedules compiled for N

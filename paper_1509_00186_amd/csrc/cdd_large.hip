@@ -1,4 +1,4 @@
-// Long overlap-save transforms (N = 2^15 .. 2^22 complex points) as a four-step FFT.
+// Long overlap-save transforms (N = 2^15 .. 2^26 complex points) as a four-step FFT.
 //
 // The paper dedisperses the full band with transforms of millions of points
 // (Sec. 1.3, 2.3, 4.5); here N = N1 * N2 with n = n1 + N1 n2 and
@@ -12,6 +12,10 @@
 //              samples [nfront, nfront + M) of block k become y[k M + m]:
 //              |y|^2 to a per-sample buffer and, if asked, y itself
 //   integrate: P[u] = sum of n_int consecutive |y|^2
+// Above 2^22 points (N2 > 2048) each column transform is itself split in
+// two, N2 = A B with n2 = a + A b and k2 = kb + B ka, so the column passes
+// become two passes each (see "Three-level transforms" below); the spectrum
+// bin k2 of a block is then stored in row ka + A kb.
 // Every sub-transform reuses the register/LDS Stockham passes of the block
 // kernel; a workgroup runs G sub-transforms side by side, lanes ordered so
 // that global accesses along n1 are contiguous.  The twiddles W_N^(n1 k2)
@@ -64,16 +68,30 @@ struct LargeArgs {
   int64_t t_int;
   int32_t n_int;
   int32_t fuse;
+  // three-level transforms: N2 = A B (A = 1 for the two-level form), the
+  // twiddles of the length-A sub-transform, and log2 of N2 and B
+  int32_t A, lg2, lgB;
+  const float2* twm;
 };
 
-// exp(-2 pi i m / M) for M = 2^lg <= 2^23: (m + M/2) mod M over M is exact in
-// FP32, so t = that - 1/2 is the phase in turns reduced to [-1/2, 1/2), and
-// the hardware sine and cosine take turns (absolute error about 1.2e-7).
+// Row of the intermediate array that holds spectrum bin k2 (< N2): k2 itself
+// in the two-level form; ka + A kb for k2 = kb + B ka in the three-level one.
+__device__ __forceinline__ int64_t spec_row(const LargeArgs& a, int k2) {
+  if (a.A == 1) return k2;
+  return (int64_t)(k2 >> a.lgB) + (int64_t)a.A * (k2 & ((1 << a.lgB) - 1));
+}
+
+// exp(-2 pi i m / M) for M = 2^lg: v = ((m + M/2) mod M) - M/2 is m reduced
+// to [-M/2, M/2), and t = v / M the phase in turns in [-1/2, 1/2).  The
+// conversion of v to FP32 is the only rounding (none up to M = 2^25; beyond,
+// t is the correctly rounded FP32 value, within 2^-26 turns), and the
+// hardware sine and cosine take turns (absolute error about 1.2e-7).
 // Computing the four-step twiddles this way keeps the passes free of table
 // gathers, whose scattered indices (n1 k2) touch a cache line per lane.
 __device__ __forceinline__ float2 expi_pow2(int64_t m, int lg) {
   const int64_t M = (int64_t)1 << lg;
-  const float t = ldexpf((float)((m + (M >> 1)) & (M - 1)), -lg) - 0.5f;
+  const int v = (int)(((m + (M >> 1)) & (M - 1)) - (M >> 1));  // |v| <= 2^26 for lg <= 27
+  const float t = ldexpf((float)v, -lg);
   return make_float2(__builtin_amdgcn_cosf(t), -__builtin_amdgcn_sinf(t));
 }
 
@@ -84,15 +102,22 @@ __device__ __forceinline__ float2 tw4_fwd(const LargeArgs& a, int64_t m) {
 // ---------------------------------------------------------------------------
 // cols_fwd
 // ---------------------------------------------------------------------------
-template <class SC, int G, int DT>
+// Two-level form (THREE = false): the length-N2 column transforms.  Three-
+// level form: the length-B transforms over b of x[n1 + N1 (a + A b)] for
+// each a, times W_N2^(a kb), stored in row a + A kb (the first half of the
+// column transform; cols_mid_kernel does the second).
+template <class SC, int G, int DT, bool THREE>
 __global__ __launch_bounds__(SC::T * G) void cols_fwd_kernel(const LargeArgs a) {
   __shared__ float lds[G * (SC::lds_floats() + 1)];
   constexpr int L = SC::N, R0 = SC::rad_f(0), B0 = L / (R0 * SC::T);
   constexpr int RL = SC::rad_f(SC::NP - 1), BL = L / (RL * SC::T);
   const int t = threadIdx.x, g = t % G, tl = t / G;
   const int ngrp = a.N1 / G;
-  const int64_t item = a.item0 + blockIdx.x / ngrp;
-  const int n1 = (blockIdx.x % ngrp) * G + g;
+  const int nsub = THREE ? a.A : 1;
+  const int64_t item = a.item0 + blockIdx.x / ((unsigned)ngrp * nsub);
+  const int rem = (int)(blockIdx.x % ((unsigned)ngrp * nsub));
+  const int sa = THREE ? rem / ngrp : 0;  // a of this column run
+  const int n1 = (rem % ngrp) * G + g;
   const int c = (int)(item / a.nblocks);
   const int64_t k = item - (int64_t)c * a.nblocks;
   const int64_t base = k * a.M - a.nfront + n1;
@@ -101,7 +126,8 @@ __global__ __launch_bounds__(SC::T * G) void cols_fwd_kernel(const LargeArgs a) 
   for (int b = 0; b < B0; ++b)
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
-      const int n2 = tl + SC::T * b + r * (L / R0);
+      const int l = tl + SC::T * b + r * (L / R0);
+      const int64_t n2 = THREE ? sa + (int64_t)a.A * l : l;
       const int64_t ts = base + (int64_t)a.N1 * n2;
       float2 z = make_float2(0.f, 0.f);
       if (ts >= 0 && ts < a.nsamp) {
@@ -120,8 +146,66 @@ __global__ __launch_bounds__(SC::T * G) void cols_fwd_kernel(const LargeArgs a) 
   for (int b = 0; b < BL; ++b)
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
-      const int k2 = tl + SC::T * b + r * (L / RL);
-      S[(int64_t)k2 * a.N1 + n1] = cmul(v[b * RL + r], tw4_fwd(a, (int64_t)n1 * k2));
+      const int kk = tl + SC::T * b + r * (L / RL);
+      if (THREE)
+        S[(sa + (int64_t)a.A * kk) * a.N1 + n1] =
+            cmul(v[b * RL + r], expi_pow2((int64_t)sa * kk, a.lg2));
+      else
+        S[(int64_t)kk * a.N1 + n1] = cmul(v[b * RL + r], tw4_fwd(a, (int64_t)n1 * kk));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Three-level transforms: the second half of each column transform.  With
+// n2 = a + A b and k2 = kb + B ka, the length-N2 column DFT is
+//   C[kb + B ka] = sum_a W_A^(a ka) W_N2^(a kb) sum_b x[a + A b] W_B^(b kb);
+// cols_fwd_kernel forms the inner sums (times W_N2^(a kb)) in rows a + A kb,
+// and this kernel, for each kb, the outer sums over a, times the four-step
+// twiddle W_N^(n1 k2), back into the same rows (bin k2 in row ka + A kb).
+// The inverse (INV) takes the same steps backwards: the inverse DFT over ka
+// of rows ka + A kb, times W_N2^(-a kb), into rows a + A kb, before
+// cols_inv_kernel's inverse DFTs over kb.
+// ---------------------------------------------------------------------------
+template <class SC, int G, bool INV>
+__global__ __launch_bounds__(SC::T * G) void cols_mid_kernel(const LargeArgs a) {
+  __shared__ float lds[G * (SC::lds_floats() + 1)];
+  constexpr int L = SC::N;  // A
+  constexpr int RIN = INV ? SC::rad_i(0) : SC::rad_f(0), BIN = L / (RIN * SC::T);
+  constexpr int ROUT = INV ? SC::rad_f(0) : SC::rad_f(SC::NP - 1), BOUT = L / (ROUT * SC::T);
+  const int t = threadIdx.x, g = t % G, tl = t / G;
+  const int ngrp = a.N1 / G;
+  const int nsub = 1 << a.lgB;  // B
+  const int64_t item = a.item0 + blockIdx.x / ((unsigned)ngrp * nsub);
+  const int rem = (int)(blockIdx.x % ((unsigned)ngrp * nsub));
+  const int kb = rem / ngrp;
+  const int n1 = (rem % ngrp) * G + g;
+  // rows l + A kb (l < A) of this item, column n1
+  float2* S = a.S + (item - a.item0) * ((int64_t)a.N1 * a.N2) +
+              (int64_t)L * kb * a.N1 + n1;
+  float2 v[SC::E];
+#pragma unroll
+  for (int b = 0; b < BIN; ++b)
+#pragma unroll
+    for (int r = 0; r < RIN; ++r)
+      v[b * RIN + r] = S[(int64_t)(tl + SC::T * b + r * (L / RIN)) * a.N1];
+  float* my = lds + g * (SC::lds_floats() + 1);
+  if (INV)
+    fft_inverse<SC>(v, my, a.twm, tl);
+  else
+    fft_forward<SC>(v, my, a.twm, tl);
+#pragma unroll
+  for (int b = 0; b < BOUT; ++b)
+#pragma unroll
+    for (int r = 0; r < ROUT; ++r) {
+      const int kk = tl + SC::T * b + r * (L / ROUT);
+      float2 w;
+      if (INV) {
+        w = expi_pow2((int64_t)kk * kb, a.lg2);
+        w.y = -w.y;
+      } else {
+        w = tw4_fwd(a, (int64_t)n1 * (kb + ((int64_t)kk << a.lgB)));
+      }
+      S[(int64_t)kk * a.N1] = cmul(v[b * ROUT + r], w);
     }
 }
 
@@ -183,7 +267,7 @@ __global__ __launch_bounds__(SR::T * G) void rows_kernel(const LargeArgs a) {
   const int k2 = (blockIdx.x % ngrp) * G + g;
   const int c = (int)(item / a.nblocks);
   const int64_t N = (int64_t)a.N1 * a.N2;
-  float2* row = a.S + (item - a.item0) * N + (int64_t)k2 * a.N1;
+  float2* row = a.S + (item - a.item0) * N + spec_row(a, k2) * a.N1;
   float2 v[SR::E];
 #pragma unroll
   for (int b = 0; b < B0; ++b)
@@ -212,15 +296,21 @@ __global__ __launch_bounds__(SR::T * G) void rows_kernel(const LargeArgs a) {
 // ---------------------------------------------------------------------------
 // cols_inv: inverse column DFT, overlap-save window, detection, voltages
 // ---------------------------------------------------------------------------
-template <class SC, int G>
+// Three-level form (THREE): for each a, the inverse DFTs over kb of rows
+// a + A kb give the samples n2 = a + A b.
+template <class SC, int G, bool THREE>
 __global__ __launch_bounds__(SC::T * G) void cols_inv_kernel(const LargeArgs a) {
   __shared__ float lds[G * (SC::lds_floats() + 1)];
   constexpr int L = SC::N, RI = SC::rad_i(0), BI = L / (RI * SC::T);
   constexpr int R0 = SC::rad_f(0), B0 = L / (R0 * SC::T);
   const int t = threadIdx.x, g = t % G, tl = t / G;
   const int ngrp = a.N1 / G;
-  const int64_t item = a.item0 + blockIdx.x / ngrp;
-  const int n1 = (blockIdx.x % ngrp) * G + g;
+  const int nsub = THREE ? a.A : 1;
+  const int64_t item = a.item0 + blockIdx.x / ((unsigned)ngrp * nsub);
+  const int rem = (int)(blockIdx.x % ((unsigned)ngrp * nsub));
+  const int sa = THREE ? rem / ngrp : 0;  // a of this column run
+  const int sA = THREE ? a.A : 1;         // n2 = sa + sA * (local index)
+  const int n1 = (rem % ngrp) * G + g;
   const int c = (int)(item / a.nblocks);
   const int64_t k = item - (int64_t)c * a.nblocks;
   const float2* S = a.S + (item - a.item0) * ((int64_t)a.N1 * a.N2);
@@ -229,8 +319,8 @@ __global__ __launch_bounds__(SC::T * G) void cols_inv_kernel(const LargeArgs a) 
   for (int b = 0; b < BI; ++b)
 #pragma unroll
     for (int r = 0; r < RI; ++r) {
-      const int k2 = tl + SC::T * b + r * (L / RI);
-      v[b * RI + r] = S[(int64_t)k2 * a.N1 + n1];
+      const int kk = tl + SC::T * b + r * (L / RI);
+      v[b * RI + r] = S[(sa + (int64_t)sA * kk) * a.N1 + n1];
     }
   fft_inverse<SC>(v, lds + g * (SC::lds_floats() + 1), a.twc, tl);
   if (!a.fuse) {
@@ -238,7 +328,7 @@ __global__ __launch_bounds__(SC::T * G) void cols_inv_kernel(const LargeArgs a) 
     for (int b = 0; b < B0; ++b)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
-        const int n2 = tl + SC::T * b + r * (L / R0);
+        const int64_t n2 = sa + (int64_t)sA * (tl + SC::T * b + r * (L / R0));
         const int64_t n = n1 + (int64_t)a.N1 * n2;
         const int64_t m = n - a.nfront;
         const int64_t o = k * a.M + m;
@@ -250,9 +340,9 @@ __global__ __launch_bounds__(SC::T * G) void cols_inv_kernel(const LargeArgs a) 
       }
     return;
   }
-  // Fused detection and integration.  The workgroup holds, for each n2, the
-  // run of G consecutive samples n = n1b + N1 n2 + g (g < G).  |z|^2 of the
-  // kept samples goes to LDS as [n2][g]; groups of n_int start where
+  // Fused detection and integration.  The workgroup holds, for each of its
+  // n2, the run of G consecutive samples n = n1b + N1 n2 + g (g < G).  |z|^2
+  // of the kept samples goes to LDS as [local n2][g]; groups of n_int start where
   // n = nfront (mod n_int).  Groups inside a run are summed here and stored;
   // a group split across the end of one run and the start of the next is
   // left as two partial sums for integrate_fixup_kernel.
@@ -262,14 +352,14 @@ __global__ __launch_bounds__(SC::T * G) void cols_inv_kernel(const LargeArgs a) 
   for (int b = 0; b < B0; ++b)
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
-      const int n2 = tl + SC::T * b + r * (L / R0);
-      const int64_t n = n1 + (int64_t)a.N1 * n2;
+      const int nl = tl + SC::T * b + r * (L / R0);
+      const int64_t n = n1 + (int64_t)a.N1 * (sa + (int64_t)sA * nl);
       const int64_t m = n - a.nfront;
       const int64_t o = k * a.M + m;
       const float2 z = v[b * R0 + r];
       const bool kept = m >= 0 && m < a.M && o < a.nsamp;
       if (kept && a.vout) a.vout[(int64_t)c * a.nsamp + o] = z;
-      q[n2 * G + g] = kept ? z.x * z.x + z.y * z.y : 0.f;
+      q[nl * G + g] = kept ? z.x * z.x + z.y * z.y : 0.f;
     }
   __syncthreads();
   const int ni = a.n_int;
@@ -280,9 +370,9 @@ __global__ __launch_bounds__(SC::T * G) void cols_inv_kernel(const LargeArgs a) 
   float* part = a.p + item_local * ((int64_t)a.N1 * a.N2 / G) * 2;
   float* Pc = a.P + (int64_t)c * a.t_int;
   for (int j = threadIdx.x; j < L * (per_run + 1); j += SC::T * G) {
-    const int n2 = j / (per_run + 1), slot = j - n2 * (per_run + 1);
-    const float* run = q + n2 * G;
-    const int64_t n0 = n1b + (int64_t)a.N1 * n2;  // first sample of the run
+    const int nl = j / (per_run + 1), slot = j - nl * (per_run + 1);
+    const float* run = q + nl * G;
+    const int64_t n0 = n1b + (int64_t)a.N1 * (sa + (int64_t)sA * nl);  // run's first sample
     const int64_t ridx = n0 / G;                   // run index in the block
     if (slot == per_run) {
       // partial sums: the head [0, phi) and the tail [G - ni + phi, G)
@@ -474,7 +564,7 @@ __global__ __launch_bounds__(SR::T * G) void rows_real_kernel(const LargeArgs a)
   const int side = g & 1;
   const int k2 = pair == 0 ? side * (a.N2 / 2) : (side ? a.N2 - pair : pair);
   const int64_t N = (int64_t)a.N1 * a.N2;
-  float2* row = a.S + (item - a.item0) * N + (int64_t)k2 * a.N1;
+  float2* row = a.S + (item - a.item0) * N + spec_row(a, k2) * a.N1;
   float2 v[SR::E];
 #pragma unroll
   for (int b = 0; b < B0; ++b)
@@ -599,7 +689,11 @@ __global__ __launch_bounds__(SC::T * G) void gsb_inverse_kernel(
 // ---------------------------------------------------------------------------
 constexpr int64_t kChunkBytes = (int64_t)512 << 20;  // intermediate spectra per chunk
 
-bool large_supported(int N) { return N >= (1 << 15) && N <= (1 << 22) && (N & (N - 1)) == 0; }
+bool large_supported(int N) { return N >= (1 << 15) && N <= (1 << 26) && (N & (N - 1)) == 0; }
+
+// The fused integration leaves two partial sums per run of G >= 8 samples
+// of every item of a chunk in the |y|^2 buffer: at most N bytes per item.
+size_t large_partial_bytes(int64_t N, int64_t items) { return (size_t)items * (size_t)N; }
 
 int64_t large_chunk_items(const BeamPlan& p) {
   const int64_t items = (int64_t)p.nchan * p.nblocks;
@@ -607,18 +701,86 @@ int64_t large_chunk_items(const BeamPlan& p) {
   return std::min(items, per);
 }
 
+// How an N = 2^LGN point transform is split: N1 = 2^LG1 (rows), and the
+// column dimension N2 = A B with A = 2^LGA, B = 2^LGB.  Up to 2^22 points
+// two levels (A = 1, N2 = 2^(LGN/2)); beyond, three, with every
+// sub-transform between 128 and 2048 points.
+template <int LGN>
+struct Split {
+  static constexpr int LGA = LGN <= 22 ? 0 : (LGN >= 26 ? 8 : 7);
+  static constexpr int LGB = LGN <= 22 ? LGN / 2 : 7;
+  static constexpr int LG1 = LGN - LGA - LGB;
+  static constexpr int N1 = 1 << LG1, A = 1 << LGA, B = 1 << LGB, N2 = A * B;
+  static constexpr bool THREE = LGA > 0;
+  using SC = typename SubSched<B>::type;                   // last column sub-transform
+  using SA = typename SubSched<THREE ? A : 128>::type;     // middle one (three levels)
+  using SR = typename SubSched<N1>::type;                  // rows
+  static constexpr int GC = SC::T * 16 <= 1024 ? 16 : 8;
+  static constexpr int GA = SA::T * 16 <= 1024 ? 16 : 8;
+  static_assert(LG1 >= 7 && LG1 <= 11 && N1 % GC == 0 && N1 % GA == 0,
+                "sub-transforms of 128 .. 2048 points, column groups tiling N1");
+};
+
+// Fill the split-dependent fields of a and its sub-transform twiddles.
+template <int LGN>
+static int set_split(LargeArgs& a) {
+  using SP = Split<LGN>;
+  int e = twiddles_of<typename SP::SC>(&a.twc);
+  if (!e) e = twiddles_of<typename SP::SR>(&a.twr);
+  if (!e && SP::THREE) e = twiddles_of<typename SP::SA>(&a.twm);
+  a.N1 = SP::N1;
+  a.N2 = SP::N2;
+  a.A = SP::A;
+  a.lgB = SP::LGB;
+  a.lg2 = SP::LGA + SP::LGB;
+  a.lgn = LGN;
+  return e;
+}
+
+// The passes over one chunk of q items (blocks of one or more channels):
+// columns forward, rows (chirp; REAL: the mirror-pair filter of the real
+// series), columns inverse with the kept window, detection and (fused)
+// integration.  GR rows per workgroup.
+template <int LGN, int DT, bool REAL, int GR>
+static int run_passes(const LargeArgs& a, int64_t q, hipStream_t st) {
+  using SP = Split<LGN>;
+  using SC = typename SP::SC;
+  using SA = typename SP::SA;
+  using SR = typename SP::SR;
+  constexpr int GC = SP::GC, GA = SP::GA;
+  static_assert(SP::N2 % GR == 0 && (!REAL || GR % 2 == 0), "row groups tile N2");
+  const int64_t gc = q * SP::A * (SP::N1 / GC), ga = q * SP::B * (SP::N1 / GA);
+  const int64_t gr = q * (SP::N2 / GR);
+  if (gc > 0x7fffffffLL || ga > 0x7fffffffLL || gr > 0x7fffffffLL)
+    return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL((cols_fwd_kernel<SC, GC, DT, SP::THREE>), dim3((unsigned)gc),
+                     dim3(SC::T * GC), 0, st, a);
+  if constexpr (SP::THREE)
+    hipLaunchKernelGGL((cols_mid_kernel<SA, GA, false>), dim3((unsigned)ga), dim3(SA::T * GA), 0,
+                       st, a);
+  if (REAL)
+    hipLaunchKernelGGL((rows_real_kernel<SR, GR>), dim3((unsigned)gr), dim3(SR::T * GR), 0, st,
+                       a);
+  else
+    hipLaunchKernelGGL((rows_kernel<SR, GR>), dim3((unsigned)gr), dim3(SR::T * GR), 0, st, a);
+  if constexpr (SP::THREE)
+    hipLaunchKernelGGL((cols_mid_kernel<SA, GA, true>), dim3((unsigned)ga), dim3(SA::T * GA), 0,
+                       st, a);
+  hipLaunchKernelGGL((cols_inv_kernel<SC, GC, SP::THREE>), dim3((unsigned)gc), dim3(SC::T * GC),
+                     0, st, a);
+  int e = 0;
+  if (a.fuse && (e = launch_fixup(a, GC, q, st))) return e;
+  return (int)hipGetLastError();
+}
+
 template <int LGN>
 static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* S, float* pbuf,
                           float* P, void* vout, int exact_div, void* stream) {
-  constexpr int N2 = 1 << (LGN / 2), N1 = 1 << (LGN - LGN / 2);
-  using SC = typename SubSched<N2>::type;
-  using SR = typename SubSched<N1>::type;
-  constexpr int GC = SC::T * 16 <= 1024 ? 16 : 8;
+  using SP = Split<LGN>;
+  using SR = typename SP::SR;
   constexpr int GR = SR::T * 8 <= 1024 ? 8 : 4;
-  static_assert(N1 % GC == 0 && N2 % GR == 0, "group sizes must tile the transform");
   LargeArgs a{};
-  int e = twiddles_of<SC>(&a.twc);
-  if (!e) e = twiddles_of<SR>(&a.twr);
+  int e = set_split<LGN>(a);
   if (e) return e;
   a.x = xt;
   a.S = S;
@@ -627,11 +789,8 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
   a.nsamp = p.nsamp;
   a.nblocks = p.nblocks;
   a.nchan = p.nchan;
-  a.N1 = N1;
-  a.N2 = N2;
   a.M = p.M;
   a.nfront = p.nfront;
-  a.lgn = LGN;
   a.phase_mode = p.phase_mode;
   a.taper = p.taper;
   a.exact_div = exact_div;
@@ -642,7 +801,7 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
   a.P = P;
   a.t_int = p.t_int;
   a.n_int = p.n_int;
-  a.fuse = GC % p.n_int == 0 ? 1 : 0;
+  a.fuse = SP::GC % p.n_int == 0 ? 1 : 0;
   hipStream_t st = (hipStream_t)stream;
   const int64_t items = (int64_t)p.nchan * p.nblocks;
   const int64_t chunk = large_chunk_items(p);
@@ -656,19 +815,8 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
   for (int64_t i0 = 0; i0 < items; i0 += chunk) {
     const int64_t q = std::min(chunk, items - i0);
     a.item0 = i0;
-    const int64_t gc = q * (N1 / GC), gr = q * (N2 / GR);
-    if (gc > 0x7fffffffLL || gr > 0x7fffffffLL) return (int)hipErrorInvalidValue;
-    if (p.dtype == CDD_CI8)
-      hipLaunchKernelGGL((cols_fwd_kernel<SC, GC, CDD_CI8>), dim3((unsigned)gc), dim3(SC::T * GC),
-                         0, st, a);
-    else
-      hipLaunchKernelGGL((cols_fwd_kernel<SC, GC, CDD_CF32>), dim3((unsigned)gc),
-                         dim3(SC::T * GC), 0, st, a);
-    hipLaunchKernelGGL((rows_kernel<SR, GR>), dim3((unsigned)gr), dim3(SR::T * GR), 0, st, a);
-    hipLaunchKernelGGL((cols_inv_kernel<SC, GC>), dim3((unsigned)gc), dim3(SC::T * GC), 0, st,
-                       a);
-    if (a.fuse && (e = launch_fixup(a, GC, q, st))) return e;
-    e = (int)hipGetLastError();
+    e = p.dtype == CDD_CI8 ? run_passes<LGN, CDD_CI8, false, GR>(a, q, st)
+                           : run_passes<LGN, CDD_CF32, false, GR>(a, q, st);
     if (e) return e;
   }
   return a.fuse ? 0 : launch_integrate(pbuf, P, p.nsamp, p.t_int, p.n_int, p.nchan, st);
@@ -725,16 +873,11 @@ int64_t fullband_chunk_blocks(const FullbandPlan& f) {
 template <int LGN>
 static int launch_fullband_t(const FullbandPlan& f, const float* series, float2* S, float* pbuf,
                              float2* hb, float* I, float* vout, void* stream) {
-  constexpr int N2 = 1 << (LGN / 2), N1 = 1 << (LGN - LGN / 2);
-  using SC = typename SubSched<N2>::type;
-  using SR = typename SubSched<N1>::type;
-  constexpr int GC = SC::T * 16 <= 1024 ? 16 : 8;
-  constexpr int GR = (SR::T * 8 <= 1024 && 8 * 2 * N1 * 4 <= 65536) ? 8 : 4;
-  static_assert(N1 % GC == 0 && N2 % GR == 0 && GR % 2 == 0,
-                "group sizes must tile the transform in row pairs");
+  using SP = Split<LGN>;
+  using SR = typename SP::SR;
+  constexpr int GR = (SR::T * 8 <= 1024 && 8 * 2 * SP::N1 * 4 <= 65536) ? 8 : 4;
   LargeArgs a{};
-  int e = twiddles_of<SC>(&a.twc);
-  if (!e) e = twiddles_of<SR>(&a.twr);
+  int e = set_split<LGN>(a);
   if (e) return e;
   a.x = series;
   a.S = S;
@@ -743,11 +886,8 @@ static int launch_fullband_t(const FullbandPlan& f, const float* series, float2*
   a.nsamp = f.nsamp / 2;
   a.nblocks = f.nblocks;
   a.nchan = 1;
-  a.N1 = N1;
-  a.N2 = N2;
   a.M = f.M / 2;
   a.nfront = f.nfront / 2;
-  a.lgn = LGN;
   a.phase_mode = CDD_PHASE_FP64_REDUCED;
   a.taper = f.taper;
   a.exact_div = 1;
@@ -760,7 +900,7 @@ static int launch_fullband_t(const FullbandPlan& f, const float* series, float2*
   a.P = I;
   a.t_int = f.t_int;
   a.n_int = f.n_int / 2;  // pairs of real samples
-  a.fuse = GC % (f.n_int / 2) == 0 ? 1 : 0;
+  a.fuse = SP::GC % (f.n_int / 2) == 0 ? 1 : 0;
   hipStream_t st = (hipStream_t)stream;
   constexpr int64_t NP = (int64_t)1 << LGN;
   hipLaunchKernelGGL(band_chirp_table_kernel, dim3((unsigned)((NP + 256) / 256)), dim3(256), 0,
@@ -769,17 +909,7 @@ static int launch_fullband_t(const FullbandPlan& f, const float* series, float2*
   for (int64_t i0 = 0; i0 < f.nblocks; i0 += chunk) {
     const int64_t q = std::min(chunk, f.nblocks - i0);
     a.item0 = i0;
-    const int64_t gc = q * (N1 / GC), gr = q * (N2 / GR);
-    if (gc > 0x7fffffffLL || gr > 0x7fffffffLL) return (int)hipErrorInvalidValue;
-    hipLaunchKernelGGL((cols_fwd_kernel<SC, GC, CDD_CF32>), dim3((unsigned)gc), dim3(SC::T * GC),
-                       0, st, a);
-    hipLaunchKernelGGL((rows_real_kernel<SR, GR>), dim3((unsigned)gr), dim3(SR::T * GR), 0, st,
-                       a);
-    hipLaunchKernelGGL((cols_inv_kernel<SC, GC>), dim3((unsigned)gc), dim3(SC::T * GC), 0, st,
-                       a);
-    if (a.fuse && (e = launch_fixup(a, GC, q, st))) return e;
-    e = (int)hipGetLastError();
-    if (e) return e;
+    if ((e = run_passes<LGN, CDD_CF32, true, GR>(a, q, st))) return e;
   }
   return a.fuse ? 0 : launch_integrate(pbuf, I, f.nsamp / 2, f.t_int, f.n_int / 2, 1, st);
 }
@@ -797,6 +927,10 @@ int launch_fullband(const FullbandPlan& f, const float* series, void* Sv, float*
     case 1 << 21: return launch_fullband_t<20>(f, series, S, pbuf, H, I, vout, stream);
     case 1 << 22: return launch_fullband_t<21>(f, series, S, pbuf, H, I, vout, stream);
     case 1 << 23: return launch_fullband_t<22>(f, series, S, pbuf, H, I, vout, stream);
+    case 1 << 24: return launch_fullband_t<23>(f, series, S, pbuf, H, I, vout, stream);
+    case 1 << 25: return launch_fullband_t<24>(f, series, S, pbuf, H, I, vout, stream);
+    case 1 << 26: return launch_fullband_t<25>(f, series, S, pbuf, H, I, vout, stream);
+    case 1 << 27: return launch_fullband_t<26>(f, series, S, pbuf, H, I, vout, stream);
   }
   return (int)hipErrorInvalidValue;
 }
@@ -816,6 +950,10 @@ int launch_large(const BeamPlan& p, const void* xt, double dm, void* Sv, float* 
     case 1 << 20: return launch_large_t<20>(p, xt, dm, S, pbuf, P, vout, ex, stream);
     case 1 << 21: return launch_large_t<21>(p, xt, dm, S, pbuf, P, vout, ex, stream);
     case 1 << 22: return launch_large_t<22>(p, xt, dm, S, pbuf, P, vout, ex, stream);
+    case 1 << 23: return launch_large_t<23>(p, xt, dm, S, pbuf, P, vout, ex, stream);
+    case 1 << 24: return launch_large_t<24>(p, xt, dm, S, pbuf, P, vout, ex, stream);
+    case 1 << 25: return launch_large_t<25>(p, xt, dm, S, pbuf, P, vout, ex, stream);
+    case 1 << 26: return launch_large_t<26>(p, xt, dm, S, pbuf, P, vout, ex, stream);
   }
   return (int)hipErrorInvalidValue;
 }

@@ -204,7 +204,8 @@ WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p, bool chirp_tabl
     w.s_bytes = (size_t)(large_chunk_items(p) + p.nchan) * p.N * 8;
     off = align256(off + w.s_bytes);
     w.pb_off = off;
-    w.pb_bytes = (size_t)p.nchan * p.nsamp * sizeof(float);
+    w.pb_bytes = std::max((size_t)p.nchan * p.nsamp * sizeof(float),
+                          large_partial_bytes(p.N, large_chunk_items(p)));
     off = align256(off + w.pb_bytes);
   }
   if (chirp_table && block_supported(p.N)) {

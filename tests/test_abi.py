@@ -2,6 +2,7 @@
 every function include/cdd.h declares, validates arguments, and its planner
 agrees with the oracle's rules."""
 import ctypes
+import json
 import math
 import os
 import re
@@ -13,6 +14,7 @@ import oracle as O
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "cdd.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def _lib():
@@ -50,6 +52,8 @@ CASES = [
     (0, 10_000, 64, 325.0, 32.0 / 8, -40.0, 0, 3),
     (1, 5000, 3, 150.0, 1.0, 0.0, 0, 1),
     (0, 100_000, 256, 235.0, 16.0, 67.99, 0, 5),
+    (1, 1000, 1, 300.0, 4.0, 1.0, 1 << 15, 4),
+    (1, 3 << 24, 1, 300.0, 4.0, 3072.0, 1 << 26, 8),
 ]
 
 
@@ -80,7 +84,7 @@ def test_planner_matches_oracle_rules(case):
     (dict(dm=float("nan")), "DM"),
     (dict(fft_len=1000), "power of two"),
     (dict(fft_len=128), "power of two"),
-    (dict(fft_len=1 << 23), "power of two"),
+    (dict(fft_len=1 << 27), "power of two"),
     (dict(dm=3000.0, fft_len=256), "DM too large"),
     (dict(f_centre=float("inf")), "finite"),
 ])
@@ -228,7 +232,7 @@ def test_fullband_planner_matches_oracle_rules(args):
     ((300, 512, 610.0, 16.0, 0.3, 3), {}, "n_int"),
     ((0, 512, 610.0, 16.0, 0.3, 2), {}, "nspec"),
     ((300, 512, 610.0, 16.0, 0.3, 2), {"fft_len": 1 << 15}, "fft_len"),
-    ((300, 512, 610.0, 16.0, 3000.0, 2), {}, "DM too large"),
+    ((300, 512, 610.0, 16.0, 6600.0, 2), {}, "DM too large"),
     ((300, 512, 610.0, 16.0, 0.3, 2), {"phase_mode": 1}, "FP64"),
     ((300, 512, 10.0, 30.0, 0.3, 2), {}, "band"),
 ])
@@ -237,6 +241,37 @@ def test_fullband_invalid_arguments_are_rejected(args, kw, frag):
     with pytest.raises(cdd.CddError) as e:
         cdd.fullband_query(*args, **kw)
     assert frag in str(e.value)
+
+
+def test_fullband_plans_the_section_4_5_dm_limits_at_2_27_points():
+    """Each of Sec. 4.5's memory-bound DM limits needs 2^27-point real
+    transforms under the length rule; the library plans them (and refuses a
+    DM that would need 2^28)."""
+    g = json.load(open(os.path.join(GOLDEN, "max_dm_sec4_5.json")))
+    for case in g["cases"]:
+        f, bw, dm = case["f_mhz"], case["bw_mhz"], case["dm"]
+        q = _lib().fullband_query(1 << 15, 512, f, bw, dm, 2)
+        N, L, nf = O.fullband_plan(f - bw / 2, bw, dm, 2)
+        assert q["fft_len"] == N == 1 << 27, case
+        assert (q["overlap"], q["nfront"]) == (L, nf), case
+        with pytest.raises(_lib().CddError) as e:
+            _lib().fullband_query(1 << 15, 512, f, bw, 2.2 * dm, 2)
+        assert "DM too large" in str(e.value), case
+
+
+@pytest.mark.parametrize("nsamp,N,n_int", [(1000, 1 << 15, 4), (5000, 1 << 17, 16),
+                                           (2, 1 << 16, 2)])
+def test_workspace_holds_the_partial_integration_sums(nsamp, N, n_int):
+    """With integration fused into the long transforms, two partial sums per
+    run of 8-16 samples of every transformed block are kept in the |y|^2
+    buffer; a record much shorter than its transform still gets room for
+    them (one block: S and the chirp table take 16 N bytes, the partial sums
+    up to N bytes more)."""
+    q = _lib().query(1, nsamp, 1, 300.0, 4.0, 0.5, N, n_int)
+    assert q["nblocks"] == 1
+    assert q["ws_bytes"] >= 16 * N + N
+    f = _lib().fullband_query(1, 128, 610.0, 16.0, 0.05, 2, fft_len=1 << 16)
+    assert f["ws_bytes"] >= 256 * 4 + (1 << 15) * 8 + (1 << 15) + ((1 << 15) + 1) * 8
 
 
 def test_profile_select_validation():

@@ -2,7 +2,7 @@
 
 The recorded beam is a sequence of real-FFT spectra; the HIP path inverse
 transforms them into one real series and dedisperses it as a single band
-(real transforms of up to 2^23 points, chirp about the lower band edge).
+(real transforms of up to 2^27 points, chirp about the lower band edge).
 Tolerances as for the channel path: the dedispersed series <= 1e-5 and the
 integrated intensities <= 1e-4 relative L2.  Records are seeded int8 noise
 (the spectra of white noise are themselves independent complex Gaussians).
@@ -113,3 +113,50 @@ def test_fullband_several_chunks_of_spectra():
     assert info["nblocks"] == 17 and info["overlap"] == 1024
     assert rel_l2(y, o["y"]) <= TOL_V
     assert rel_l2(I, o["P"]) <= TOL_I
+
+
+@pytest.mark.parametrize("lg,dm,n_int", [(24, 0.5, 16), (25, 1.0, 6)])
+def test_fullband_three_level_transforms(lg, dm, n_int):
+    """Real transforms of 2^24 and 2^25 points (packed complex 2^23 and
+    2^24, columns split in two passes each): two blocks, the second ragged;
+    fused integration with split groups (n_int 16) and the separate
+    integration (n_int 6)."""
+    nchan = 512
+    M = _cdd().fullband_query(1, nchan, 610.0, 16.0, dm, n_int, fft_len=1 << lg)["step"]
+    nspec = -(-(M + M // 3 + 5000) // (2 * nchan))
+    sp = _records(20 + lg, nspec, nchan)
+    y, I, o, info = _fb_both(sp, 610.0, 16.0, dm, n_int, fft_len=1 << lg)
+    assert (info["fft_len"], info["nblocks"]) == (1 << lg, 2)
+    assert rel_l2(y, o["y"]) <= TOL_V, rel_l2(y, o["y"])
+    assert rel_l2(I, o["P"]) <= TOL_I, rel_l2(I, o["P"])
+
+
+def test_fullband_at_the_section_4_5_dm_limit():
+    """The first of Sec. 4.5's memory-bound limits, DM 3000 at 610 MHz over
+    16 MHz, planned by the length rule at 2^27 real points (L = 2^26): one
+    block over 2^25 real samples (1 s), against the oracle."""
+    sp = _records(31, 1 << 15, 512)
+    y, I, o, info = _fb_both(sp, 610.0, 16.0, 3000.0, 16)
+    assert (info["fft_len"], info["overlap"], info["nblocks"]) == (1 << 27, 1 << 26, 1)
+    assert rel_l2(y, o["y"]) <= TOL_V, rel_l2(y, o["y"])
+    assert rel_l2(I, o["P"]) <= TOL_I, rel_l2(I, o["P"])
+
+
+def test_fullband_short_record_stays_inside_its_workspace():
+    """One record of 128 bins (256 real samples) on a 2^16-point transform:
+    the fused integration's partial sums stay inside the workspace (a canary
+    after it is untouched) and the result matches the oracle."""
+    import torch
+    cdd = _cdd()
+    sp = _records(32, 1, 128)
+    q = cdd.fullband_query(1, 128, 610.0, 16.0, 0.05, 2, fft_len=1 << 16)
+    ws = torch.full((q["ws_bytes"] + (1 << 20),), 0x5A, dtype=torch.uint8, device="cuda")
+    flush("case: fullband short record ws=%d" % q["ws_bytes"])
+    g = cdd.fullband(to_dev(sp), 610.0, 16.0, 0.05, 2, fft_len=1 << 16, want_voltages=True,
+                     out={"ws": ws})
+    torch.cuda.synchronize()
+    assert bool((ws[q["ws_bytes"]:] == 0x5A).all())
+    o = O.fullband_dedisperse(sp, 610.0, 16.0, 0.05, 2, fft_len=1 << 16, overlap=q["overlap"],
+                              nfront=q["nfront"], want_voltages=True)
+    assert rel_l2(g["y"].cpu().numpy(), o["y"]) <= TOL_V
+    assert rel_l2(g["I"].cpu().numpy(), o["P"]) <= TOL_I

@@ -313,7 +313,7 @@ def test_multi_beam_plan_uneven_beams():
 # ---------------------------------------------------------------------------
 # Long transforms (four-step kernels, N >= 2^15)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("lgN", [15, 16, 17, 19, 20, 22])
+@pytest.mark.parametrize("lgN", [15, 16, 17, 19, 20, 22, 23, 24])
 def test_long_transform_lengths_cf32(lgN):
     N = 1 << lgN
     fcen, bw = 300.0, 4.0
@@ -324,6 +324,49 @@ def test_long_transform_lengths_cf32(lgN):
     got, o, info = _run_both(x, fcen, bw, dm, 8, N)
     assert info["fft_len"] == N
     _check(got, o)
+
+
+@pytest.mark.parametrize("n_int", [16, 3])
+def test_three_level_transform_2_26_cf32(n_int):
+    """2^26-point transforms (rows of 2^11, columns split 2^8 x 2^7): two
+    blocks, the second ragged; integration fused into the last column pass
+    with groups split between its runs (n_int 16, odd nfront), or the
+    separate integration (n_int 3)."""
+    N = 1 << 26
+    fcen, bw, dm = 300.0, 4.0, 3072.0
+    q = _cdd().query(1, 1000, 1, fcen, bw, dm, N, n_int)
+    nsamp = q["step"] + 12_345
+    rng = np.random.default_rng(77 + n_int)
+    x = (rng.standard_normal(nsamp) + 1j * rng.standard_normal(nsamp)).astype(np.complex64)
+    got, o, info = _run_both(x, fcen, bw, dm, n_int, N)
+    assert (info["fft_len"], info["nblocks"]) == (N, 2)
+    assert n_int != 16 or info["nfront"] % 16 != 0
+    _check(got, o)
+
+
+def test_short_record_on_a_long_transform_stays_inside_its_workspace():
+    """A record far shorter than its transform (1000 samples, N = 2^15) with
+    integration groups split across the fused pass's runs: every partial sum
+    lands inside the workspace (a canary after it is untouched) and the
+    results match the oracle."""
+    import torch
+    cdd = _cdd()
+    N, n_int = 1 << 15, 4
+    rng = np.random.default_rng(79)
+    x = (rng.standard_normal(1000) + 1j * rng.standard_normal(1000)).astype(np.complex64)
+    q = cdd.query(1, 1000, 1, 300.0, 4.0, 0.5, N, n_int, want_voltages=True)
+    L, nfront = q["overlap"], q["nfront"] | 1
+    q = cdd.query(1, 1000, 1, 300.0, 4.0, 0.5, N, n_int, want_voltages=True,
+                  overlap=L, nfront=nfront)
+    ws = torch.full((q["ws_bytes"] + (1 << 20),), 0x5A, dtype=torch.uint8, device="cuda")
+    flush("case: short record N=2^15 nfront=%d ws=%d" % (nfront, q["ws_bytes"]))
+    g = cdd.dedisperse(to_dev(x), 300.0, 4.0, 0.5, N, n_int, want_chan=True,
+                       want_voltages=True, overlap=L, nfront=nfront, out={"ws": ws})
+    torch.cuda.synchronize()
+    assert bool((ws[q["ws_bytes"]:] == 0x5A).all())
+    o = O.dedisperse(x, 300.0, 4.0, 0.5, n_int, fft_len=N, overlap=L, nfront=nfront,
+                     want_voltages=True)
+    _check({k: g[k].cpu().numpy() for k in ("I", "cov", "P", "y")}, o)
 
 
 def test_long_transform_multichannel_int8():
