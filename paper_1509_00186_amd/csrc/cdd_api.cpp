@@ -21,12 +21,16 @@ namespace {
 
 bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 
-// Layout change with stage timing.
-int launch_transposed(const BeamPlan& p, const void* in, void* out, void* stream) {
+// Layout change with stage timing; with H, the one-DM chirp table (of dm)
+// is built by the same kernel.
+int launch_transposed(const BeamPlan& p, const void* in, void* out, void* stream,
+                      void* H = nullptr, double dm = 0.0) {
   void* tok = nullptr;
   int e = stage_begin(kStageTranspose, stream, &tok);
   if (e) return e;
-  if ((e = launch_transpose(in, out, p.dtype, p.nsamp, p.nchan, p.nsamp, stream))) return e;
+  if ((e = H ? launch_transpose_chirp(p, in, out, dm, H, stream)
+             : launch_transpose(in, out, p.dtype, p.nsamp, p.nchan, xt_stride(p), stream)))
+    return e;
   return stage_end(kStageTranspose, stream, tok);
 }
 
@@ -46,11 +50,21 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
   int e = 0;
   auto begin = [&](int stage) { return timed ? stage_begin(stage, stream, &tok) : 0; };
   auto end = [&](int stage) { return timed ? stage_end(stage, stream, tok) : 0; };
+  // one DM on the block kernel: a chirp table, built by the layout change
+  // itself when it can
+  const bool table = block_supported(p.N) && tile.ndm == 1;
+  if (table && lay.h_bytes < chirp_table_bytes(p))
+    return fail(CDD_EINTERNAL, "no chirp table space");
+  void* H = table ? ws + lay.h_off : nullptr;
+  bool table_built = false;
   if (xt == nullptr) {
     if (p.nchan > 1) {
+      table_built = table && transpose_chirp_fits(p);
       if ((e = begin(kStageTranspose)) ||
-          (e = launch_transpose(voltages, ws + lay.xt_off, p.dtype, p.nsamp, p.nchan, p.nsamp,
-                                stream)) ||
+          (e = table_built
+                   ? launch_transpose_chirp(p, voltages, ws + lay.xt_off, tile.dm[0], H, stream)
+                   : launch_transpose(voltages, ws + lay.xt_off, p.dtype, p.nsamp, p.nchan,
+                                      xt_stride(p), stream)) ||
           (e = end(kStageTranspose)))
         return device_fail("transpose launch", e);
       xt = ws + lay.xt_off;
@@ -62,13 +76,8 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
   int32_t* d = (int32_t*)(ws + lay.d_off);
   if ((e = begin(kStageDelays))) return device_fail("event record", e);
   if ((e = launch_delays(p, tile, d, stream))) return device_fail("delay launch", e);
-  void* H = nullptr;
-  if (block_supported(p.N) && tile.ndm == 1) {
-    if (lay.h_bytes < chirp_table_bytes(p)) return fail(CDD_EINTERNAL, "no chirp table space");
-    H = ws + lay.h_off;
-    if ((e = launch_chirp_table(p, tile.dm[0], H, stream)))
-      return device_fail("chirp table launch", e);
-  }
+  if (table && !table_built && (e = launch_chirp_table(p, tile.dm[0], H, stream)))
+    return device_fail("chirp table launch", e);
   if ((e = end(kStageDelays))) return device_fail("event record", e);
   if ((e = begin(kStageBlock))) return device_fail("event record", e);
   if (block_supported(p.N)) {
@@ -599,26 +608,29 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
       if ((err = stage_end(kStageBlock, stream, tok))) return device_fail("event record", err);
       return CDD_OK;
     };
-    // Round 0.  The chirp tables of the one-DM beams are built on the
-    // auxiliary stream while the caller's stream changes the layout of the
-    // first beam.  In the pipelined form each beam then takes its layout
-    // change, its launch and its delays and aligned sums in turn on the
-    // caller's stream (running the layout changes of later beams beside the
-    // transforms of earlier ones slows both down on this GPU as much as it
-    // hides); the single-launch form changes every layout first.
+    // Round 0.  The chirp table of a one-DM beam is built by its layout
+    // change where that kernel can (int8, a workgroup per channel at least),
+    // else on the auxiliary stream while the caller's stream changes the
+    // layout of the first beam.  In the pipelined form each beam then takes
+    // its layout change, its launch and its delays and aligned sums in turn
+    // on the caller's stream (running the layout changes of later beams
+    // beside the transforms of earlier ones slows both down on this GPU as
+    // much as it hides); the single-launch form changes every layout first.
     AuxSession aux;
     if ((e = aux_open(stream, &aux))) return device_fail("auxiliary stream", e);
     size_t li = 0;
     cdd_status st = CDD_OK;
     bool tables_waited = false;
+    auto fused_table = [&](size_t b) { return H[b] && transpose_chirp_fits(plan->beams[b]); };
     for (size_t j = 0; j < nb && st == CDD_OK; ++j) {
       const size_t b = order[j];
       const BeamPlan& p = plan->beams[b];
       int err = 0;
       void* tok = nullptr;
-      if (H[b] && ((err = stage_begin(kStageDelays, aux.aux, &tok)) ||
-                   (err = launch_chirp_table(p, p.dms[0], H[b], aux.aux)) ||
-                   (err = stage_end(kStageDelays, aux.aux, tok))))
+      if (H[b] && !fused_table(b) &&
+          ((err = stage_begin(kStageDelays, aux.aux, &tok)) ||
+           (err = launch_chirp_table(p, p.dms[0], H[b], aux.aux)) ||
+           (err = stage_end(kStageDelays, aux.aux, tok))))
         st = device_fail("chirp table launch", err);
     }
     for (size_t j = 0; j < nb && st == CDD_OK; ++j) {
@@ -626,7 +638,8 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
       const BeamPlan& p = plan->beams[b];
       int err = 0;
       if (p.nchan > 1 &&
-          (err = launch_transposed(p, plan->desc[b].voltages, (void*)xt[b], stream))) {
+          (err = launch_transposed(p, plan->desc[b].voltages, (void*)xt[b], stream,
+                                   fused_table(b) ? H[b] : nullptr, p.dms[0]))) {
         st = device_fail("transpose launch", err);
         break;
       }

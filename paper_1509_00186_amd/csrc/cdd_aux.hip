@@ -3,6 +3,7 @@
 
 #include <cmath>
 
+#include "cdd_fft.h"
 #include "cdd_internal.h"
 
 namespace cdd {
@@ -14,11 +15,15 @@ namespace cdd {
 // the load (along channels) and the store (along time) side.
 // Float pairs: a 64 x 64 tile, one element per lane access.
 // ---------------------------------------------------------------------------
+// With ct.H set, workgroup w < ct.nwg also writes table workgroup w's share
+// of the one-DM chirp table once its tile stores are issued: the table's
+// FP64 arithmetic runs while the memory-bound layout change's traffic is in
+// flight, instead of in a kernel of its own beside it.
 __global__ __launch_bounds__(256) void transpose_i8_kernel(const unsigned short* __restrict__ in,
                                                            unsigned short* __restrict__ out,
                                                            int64_t nsamp, int32_t nchan,
                                                            int32_t tiles_c, int32_t in_aligned,
-                                                           int64_t ostr) {
+                                                           int64_t ostr, const ChirpTableArgs ct) {
   __shared__ unsigned short tile[64][128 + 4];
   const int64_t bid = blockIdx.x;
   const int c0 = (int)(bid % tiles_c) * 128;
@@ -74,6 +79,7 @@ __global__ __launch_bounds__(256) void transpose_i8_kernel(const unsigned short*
         if (ts + q < nsamp) out[(int64_t)cs * ostr + ts + q] = tile[tl + q][c];
     }
   }
+  if (ct.H != nullptr && blockIdx.x < ct.nwg) chirp_table_part(ct, blockIdx.x, l);
 }
 
 __global__ __launch_bounds__(256) void transpose_c8_kernel(const float2* __restrict__ in,
@@ -109,7 +115,8 @@ int launch_transpose(const void* in, void* out, int32_t dtype, int64_t nsamp, in
     if (n <= 0 || n > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(transpose_i8_kernel, dim3((unsigned)n), dim3(256), 0, st,
                        (const unsigned short*)in, (unsigned short*)out, nsamp, nchan,
-                       (int32_t)tiles_c, (int32_t)(((uintptr_t)in & 7u) == 0), out_stride);
+                       (int32_t)tiles_c, (int32_t)(((uintptr_t)in & 7u) == 0), out_stride,
+                       ChirpTableArgs{});
   } else {
     const int64_t tiles_c = (nchan + 63) / 64, tiles_t = (nsamp + 63) / 64;
     const int64_t n = tiles_c * tiles_t;
@@ -118,6 +125,28 @@ int launch_transpose(const void* in, void* out, int32_t dtype, int64_t nsamp, in
                        (const float2*)in, (float2*)out, nsamp, nchan, (int32_t)tiles_c,
                        out_stride);
   }
+  return (int)hipGetLastError();
+}
+
+bool transpose_chirp_fits(const BeamPlan& p) {
+  if (p.dtype != CDD_CI8 || p.nchan < 2 || !block_supported(p.N)) return false;
+  const int64_t n = (int64_t)((p.nchan + 127) / 128) * ((p.nsamp + 63) / 64);
+  return (int64_t)p.nchan <= n;  // at least one channel's table per workgroup at kpt = N/256
+}
+
+int launch_transpose_chirp(const BeamPlan& p, const void* in, void* out, double dm, void* H,
+                           void* stream) {
+  if (!transpose_chirp_fits(p) || H == nullptr) return (int)hipErrorInvalidValue;
+  const int64_t tiles_c = (p.nchan + 127) / 128, tiles_t = (p.nsamp + 63) / 64;
+  const int64_t n = tiles_c * tiles_t;
+  if (n > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+  // the fewest table entries per thread that the layout change's workgroups cover
+  int kpt = 1;
+  while ((int64_t)p.nchan * (p.N / (256 * kpt)) > n && 256 * kpt * 2 <= p.N) kpt *= 2;
+  const ChirpTableArgs ct = chirp_table_args(p, dm, H, kpt);
+  hipLaunchKernelGGL(transpose_i8_kernel, dim3((unsigned)n), dim3(256), 0, (hipStream_t)stream,
+                     (const unsigned short*)in, (unsigned short*)out, p.nsamp, p.nchan,
+                     (int32_t)tiles_c, (int32_t)(((uintptr_t)in & 7u) == 0), xt_stride(p), ct);
   return (int)hipGetLastError();
 }
 

@@ -507,62 +507,9 @@ __global__ __launch_bounds__(kMixT, MULTI ? 2 : 3) void mixed_kernel(
 
 __global__ void zero_counter_kernel(unsigned int* c) { *c = 0u; }
 
-// Chirp table of one DM: H[c*N + i] = exp(-2 pi i q)/N for bin i of channel c
-// (signed bin s = i or i - N, offset f = s*df/N from the channel centre fc),
-// q = D*DM*f^2/(fc^2 (fc + f)) turns (Eq. 3), evaluated in FP64 exactly as
-// apply_chirp does -- q = B s^2 / (1 + beta s) with B = D*DM*(df/N)^2/fc^3 and
-// beta = (df/N)/fc, the division replaced by the series s^2 (B - B beta s +
-// B beta^2 s^2) where its truncation is negligible (exact_div = 0) -- so the
-// table and the in-kernel chirp give the same numbers.  The channel
-// constants are formed once per thread for kpt entries of one channel.  The
-// reduction r = q - rint(q) to [-1/2, 1/2] turns is FP64; sin/cos of 2 pi r
-// are FP32.  The FP32 phase mode forms q itself in FP32 (precision study).
-// The taper (Sec. 2.2) scales the entry with the 1/N of the inverse transform.
-__global__ __launch_bounds__(256) void chirp_table_kernel(float2* __restrict__ H, int32_t lgN,
-                                                          int32_t kpt, double f_lo, double df,
-                                                          double dconst, double dm,
-                                                          int32_t phase_mode, int32_t taper,
-                                                          int32_t exact_div) {
-  const int N = 1 << lgN;
-  const int per_wg = 256 * kpt;
-  const int bpc = N / per_wg;                       // workgroups per channel
-  const int c = (int)(blockIdx.x / bpc);
-  const int i0 = (int)(blockIdx.x - (unsigned)c * bpc) * per_wg + threadIdx.x;
-  const double fc = f_lo + ((double)c + 0.5) * df;
-  const float inv_n = ldexpf(1.0f, -lgN);
-  float2* row = H + ((int64_t)c << lgN);
-  if (phase_mode == CDD_PHASE_FP64_REDUCED) {
-    const double dfn = df / (double)N;
-    const double B = dconst * dm * dfn * dfn / (fc * fc * fc);  // turns
-    const double beta = dfn / fc;
-    const double Bb = B * beta, Bbb = Bb * beta;
-    for (int k = 0; k < kpt; ++k) {
-      const int i = i0 + 256 * k;
-      const int s = i < N / 2 ? i : i - N;
-      const double sd = (double)s;
-      const double q = exact_div ? (B * (sd * sd)) / fma(beta, sd, 1.0)
-                                 : (sd * sd) * fma(sd, fma(sd, Bbb, -Bb), B);
-      // r in [-1/2, 1/2] turns: the hardware sine and cosine take turns
-      // (absolute error about 1.2e-7)
-      const float r = (float)(q - rint(q));
-      const float gn = taper_gain<false>(taper, (float)s * inv_n) * inv_n;
-      row[i] = make_float2(__builtin_amdgcn_cosf(r) * gn, -__builtin_amdgcn_sinf(r) * gn);
-    }
-  } else {
-    const float fcf = (float)fc;
-    const float Af = (float)(dconst * dm) / (fcf * fcf);
-    const float dff = (float)df * inv_n;
-    for (int k = 0; k < kpt; ++k) {
-      const int i = i0 + 256 * k;
-      const int s = i < N / 2 ? i : i - N;
-      const float f = (float)s * dff;
-      const float q = Af * (f * f) / (fcf + f);
-      float sn, cs;
-      sincospif(2.0f * q, &sn, &cs);
-      const float gn = taper_gain<false>(taper, (float)s * inv_n) * inv_n;
-      row[i] = make_float2(cs * gn, -sn * gn);
-    }
-  }
+// The one-DM chirp table as a kernel of its own (see chirp_table_part).
+__global__ __launch_bounds__(256) void chirp_table_kernel(const ChirpTableArgs a) {
+  chirp_table_part(a, blockIdx.x, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -633,7 +580,7 @@ static int needs_exact_division(const BeamPlan& p, const DmTile& dms) {
 
 Coords offline_coords(const BeamPlan& p) {
   Coords co;
-  co.x_stride = p.nsamp;
+  co.x_stride = xt_stride(p);
   co.x_len = p.nsamp;
   co.load_off = p.nfront;
   co.p_stride = p.t_int;
@@ -797,14 +744,29 @@ size_t chirp_table_bytes(const BeamPlan& p) {
   return block_supported(p.N) ? (size_t)p.nchan * p.N * sizeof(float2) : 0;
 }
 
+ChirpTableArgs chirp_table_args(const BeamPlan& p, double dm, void* H, int kpt) {
+  ChirpTableArgs a{};
+  a.H = (float2*)H;
+  a.f_lo = p.f_lo;
+  a.df = p.df;
+  a.dconst = p.dconst;
+  a.dm = dm;
+  a.lgN = log2i(p.N);
+  a.kpt = kpt;
+  a.phase_mode = p.phase_mode;
+  a.taper = p.taper;
+  a.exact_div = exact_division_needed(p, std::fabs(dm));
+  a.nwg = (uint32_t)((int64_t)p.nchan * (p.N / (256 * kpt)));
+  return a;
+}
+
 int launch_chirp_table(const BeamPlan& p, double dm, void* H, void* stream) {
   if (!block_supported(p.N) || H == nullptr) return (int)hipErrorInvalidValue;
   const int kpt = std::max(1, std::min(8, p.N / 256));
   const int64_t grid = (int64_t)p.nchan * (p.N / (256 * kpt));
   if (grid > 0x7fffffffLL) return (int)hipErrorInvalidValue;
   hipLaunchKernelGGL(chirp_table_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
-                     (float2*)H, log2i(p.N), kpt, p.f_lo, p.df, p.dconst, dm, p.phase_mode,
-                     p.taper, exact_division_needed(p, std::fabs(dm)));
+                     chirp_table_args(p, dm, H, kpt));
   return (int)hipGetLastError();
 }
 

@@ -431,6 +431,76 @@ __device__ __forceinline__ float taper_gain(int kind, float x) {
   return 1.0f;
 }
 
+// Chirp table of one DM: H[c*N + i] = exp(-2 pi i q)/N for bin i of channel c
+// (signed bin s = i or i - N, offset f = s*df/N from the channel centre fc),
+// q = D*DM*f^2/(fc^2 (fc + f)) turns (Eq. 3), evaluated in FP64 exactly as
+// apply_chirp does -- q = B s^2 / (1 + beta s) with B = D*DM*(df/N)^2/fc^3 and
+// beta = (df/N)/fc, the division replaced by the series s^2 (B - B beta s +
+// B beta^2 s^2) where its truncation is negligible (exact_div = 0) -- so the
+// table and the in-kernel chirp give the same numbers.  The channel
+// constants are formed once per thread for kpt entries of one channel.  The
+// reduction r = q - rint(q) to [-1/2, 1/2] turns is FP64; sin/cos of 2 pi r
+// are FP32.  The FP32 phase mode forms q itself in FP32 (precision study).
+// The taper (Sec. 2.2) scales the entry with the 1/N of the inverse transform.
+struct ChirpTableArgs {
+  float2* H;
+  double f_lo, df, dconst, dm;
+  int32_t lgN, kpt, phase_mode, taper, exact_div;
+  uint32_t nwg;  // workgroups of 256 threads covering the table (nchan N / (256 kpt))
+};
+
+// Entries of table workgroup wg (< a.nwg), thread tid: kpt entries of one
+// channel, 256 apart.
+__device__ __forceinline__ void chirp_table_part(const ChirpTableArgs& a, unsigned wg, int tid) {
+  const int lgN = a.lgN, kpt = a.kpt, phase_mode = a.phase_mode, taper = a.taper;
+  const double f_lo = a.f_lo, df = a.df, dconst = a.dconst, dm = a.dm;
+  float2* H = a.H;
+  const int N = 1 << lgN;
+  const int per_wg = 256 * kpt;
+  const int bpc = N / per_wg;                       // workgroups per channel
+  const int c = (int)(wg / bpc);
+  const int i0 = (int)(wg - (unsigned)c * bpc) * per_wg + tid;
+  const double fc = f_lo + ((double)c + 0.5) * df;
+  const float inv_n = ldexpf(1.0f, -lgN);
+  float2* row = H + ((int64_t)c << lgN);
+  if (phase_mode == CDD_PHASE_FP64_REDUCED) {
+    const double dfn = df / (double)N;
+    const double B = dconst * dm * dfn * dfn / (fc * fc * fc);  // turns
+    const double beta = dfn / fc;
+    const double Bb = B * beta, Bbb = Bb * beta;
+    for (int k = 0; k < kpt; ++k) {
+      const int i = i0 + 256 * k;
+      const int s = i < N / 2 ? i : i - N;
+      const double sd = (double)s;
+      const double q = a.exact_div ? (B * (sd * sd)) / fma(beta, sd, 1.0)
+                                 : (sd * sd) * fma(sd, fma(sd, Bbb, -Bb), B);
+      // r in [-1/2, 1/2] turns: the hardware sine and cosine take turns
+      // (absolute error about 1.2e-7)
+      const float r = (float)(q - rint(q));
+      const float gn = taper_gain<false>(taper, (float)s * inv_n) * inv_n;
+      row[i] = make_float2(__builtin_amdgcn_cosf(r) * gn, -__builtin_amdgcn_sinf(r) * gn);
+    }
+  } else {
+    const float fcf = (float)fc;
+    const float Af = (float)(dconst * dm) / (fcf * fcf);
+    const float dff = (float)df * inv_n;
+    for (int k = 0; k < kpt; ++k) {
+      const int i = i0 + 256 * k;
+      const int s = i < N / 2 ? i : i - N;
+      const float f = (float)s * dff;
+      const float q = Af * (f * f) / (fcf + f);
+      float sn, cs;
+      sincospif(2.0f * q, &sn, &cs);
+      const float gn = taper_gain<false>(taper, (float)s * inv_n) * inv_n;
+      row[i] = make_float2(cs * gn, -sn * gn);
+    }
+  }
+}
+
+// Host: the table arguments of beam p at one DM (cdd_block.hip).
+struct BeamPlan;
+ChirpTableArgs chirp_table_args(const BeamPlan& p, double dm, void* H, int kpt);
+
 // cos and sin of 2 pi k / 64 for the 64 octant-of-an-octant rotations.
 struct RotTable {
   float cs[64][2];  // cos, sin of 2 pi k / 64

@@ -62,6 +62,10 @@ struct WsLayout {
   size_t total = 0;
 };
 WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p, bool chirp_table = false);
+// Samples between channel rows of the channel-major copy of a record: for
+// the block kernels nsamp rounded up to 64 (every row starts on a 128-byte
+// boundary, so the layout change writes whole cache lines), else nsamp.
+int64_t xt_stride(const BeamPlan& p);
 
 // ---------------------------------------------------------------------
 // Launchers (defined in the .hip files).  Return hipError_t as int.
@@ -97,6 +101,12 @@ int launch_block_co(const BeamPlan& p, const Coords& co, const void* xt, const D
                     float* P, void* vout, const void* H, void* stream);
 size_t chirp_table_bytes(const BeamPlan& p);
 int launch_chirp_table(const BeamPlan& p, double dm, void* H, void* stream);
+// The int8 layout change of a whole record (into [c][nsamp]) with the
+// one-DM chirp table built by the same kernel; possible when the layout
+// change has at least one workgroup per channel of the table.
+bool transpose_chirp_fits(const BeamPlan& p);
+int launch_transpose_chirp(const BeamPlan& p, const void* in, void* out, double dm, void* H,
+                           void* stream);
 // One DM, block kernel, record split into time chunks with the layout change
 // and the aligned sums on an auxiliary stream (cdd_pipeline.hip).
 int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, float* P,

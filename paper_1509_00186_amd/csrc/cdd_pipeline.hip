@@ -68,8 +68,10 @@ static int aux_of(Aux** out) {
 
 // One chunk: the layout change, the block kernel and the aligned sum run in
 // order on the caller's stream (no cross-stream wait in front of the block
-// kernel); the chirp table and the delays run meanwhile on the auxiliary
-// stream, which the caller's stream waits for before the block kernel.
+// kernel); the delays run meanwhile on the auxiliary stream, which the
+// caller's stream waits for before the block kernel.  The chirp table is
+// built by the layout-change kernel itself (int8 records with at least one
+// layout workgroup per channel), else beside it on the auxiliary stream.
 static int run_single(Aux& ax, const BeamPlan& p, const void* voltages, double dm, char* xt,
                       float* P, int32_t* d, void* H, void* volt_out, float* I, int32_t* cov,
                       int npol, hipStream_t S) {
@@ -80,12 +82,13 @@ static int run_single(Aux& ax, const BeamPlan& p, const void* voltages, double d
   DmTile tile;
   tile.ndm = 1;
   tile.dm[0] = dm;
+  const bool fused_table = H != nullptr && transpose_chirp_fits(p);
   // fork after the caller's earlier work (a previous call may still read H)
   hipEvent_t e0 = take(ax);
   if ((e = hipEventRecord(e0, S)) != hipSuccess) return (int)e;
   if ((e = hipStreamWaitEvent(A, e0, 0)) != hipSuccess) return (int)e;
   if ((err = stage_begin(kStageDelays, A, &tok))) return err;
-  if ((err = launch_chirp_table(p, dm, H, A))) return err;
+  if (!fused_table && (err = launch_chirp_table(p, dm, H, A))) return err;
   if ((err = launch_delays(p, tile, d, A))) return err;
   if ((err = stage_end(kStageDelays, A, tok))) return err;
   hipEvent_t eA = take(ax);
@@ -95,9 +98,12 @@ static int run_single(Aux& ax, const BeamPlan& p, const void* voltages, double d
   Coords co = offline_coords(p);
   for (int pol = 0; pol < npol; ++pol) {
     if ((err = stage_begin(kStageTranspose, S, &tok))) return err;
-    if ((err = launch_transpose((const char*)voltages + pol * rec, xt, p.dtype, p.nsamp,
-                                p.nchan, p.nsamp, S)))
-      return err;
+    if (pol == 0 && fused_table)
+      err = launch_transpose_chirp(p, voltages, xt, dm, H, S);
+    else
+      err = launch_transpose((const char*)voltages + pol * rec, xt, p.dtype, p.nsamp, p.nchan,
+                             xt_stride(p), S);
+    if (err) return err;
     if ((err = stage_end(kStageTranspose, S, tok))) return err;
     if (pol == 0 && (e = hipStreamWaitEvent(S, eA, 0)) != hipSuccess) return (int)e;
     co.accum = pol > 0;
@@ -219,7 +225,8 @@ int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, 
     if (rows > 0) {
       if ((err = stage_begin(kStageTranspose, A, &tok))) return err;
       if ((err = launch_transpose((const char*)voltages + tr[i] * p.nchan * elem,
-                                  xt + tr[i] * elem, p.dtype, rows, p.nchan, p.nsamp, A)))
+                                  xt + tr[i] * elem, p.dtype, rows, p.nchan, xt_stride(p),
+                                  A)))
         return err;
       if ((err = stage_end(kStageTranspose, A, tok))) return err;
     }

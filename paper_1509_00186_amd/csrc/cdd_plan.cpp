@@ -181,13 +181,17 @@ cdd_status make_plan(int32_t dtype, int64_t nsamp, int32_t nchan,
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+int64_t xt_stride(const BeamPlan& p) {
+  return block_supported(p.N) && p.nchan > 1 ? (p.nsamp + 63) / 64 * 64 : p.nsamp;
+}
+
 WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p, bool chirp_table) {
   WsLayout w;
   size_t off = 0;
   size_t elem = p.dtype == CDD_CI8 ? 2 : 8;
   if (p.nchan > 1) {
     w.xt_off = off;
-    w.xt_bytes = (size_t)p.nchan * p.nsamp * elem;
+    w.xt_bytes = (size_t)p.nchan * xt_stride(p) * elem;
     off = align256(off + w.xt_bytes);
   }
   if (need_p) {

@@ -123,7 +123,9 @@ extern "C" cdd_status cdd_autotune(int32_t dtype, int32_t nchan, double f_centre
   }
   // synthetic record: eight blocks of the longest candidate, at most 256 MiB
   const int64_t cap_samples = std::max<int64_t>(1, ((int64_t)256 << 20) / (2LL * nchan));
-  const int64_t T = std::min<int64_t>((int64_t)8 * n_max, cap_samples);
+  // (a multiple of 64, so the record is its own channel-major layout)
+  const int64_t T =
+      std::max<int64_t>(64, std::min<int64_t>((int64_t)8 * n_max, cap_samples) / 64 * 64);
   const int max_tile = std::min<int>(ndm, kMaxDmTile);
   std::vector<int> tiles;
   if (ndm == 1) {
