@@ -714,6 +714,8 @@ def other_legs(cdd, torch, vd, b, args, only=""):
         legs += [("dm_trials_autotuned",
                   lambda: dm_trials(cdd, torch, vd, b, None, taper=args.taper, autotune=True)),
                  ("dm_trials", lambda: dm_trials(cdd, torch, vd, b, None, taper=args.taper))]
+    if only == "fullband_dm_limit":  # for profiling the three-level passes alone
+        legs = [("fullband_dm_limit", lambda: fullband_dm_limit(cdd, torch, max(2, args.steps)))]
     if only:
         legs = [lg for lg in legs if lg[0] == only]
         if not legs:
@@ -751,7 +753,8 @@ def main():
                     help="config 1 only: a noise record of this many samples instead")
     ap.add_argument("--leg", default="",
                     help="only this sub-object of the default line (e.g. dm_trials, "
-                         "dm_trials_autotuned, config4_multibeam), for profiling")
+                         "dm_trials_autotuned, config4_multibeam), or fullband_dm_limit "
+                         "(the 2^27-point full-band record alone), for profiling")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
     args = ap.parse_args()

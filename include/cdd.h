@@ -159,7 +159,8 @@ typedef struct {
  * 2.3): front/back = ceil of the largest forward/backward reach of the
  * chirp's impulse response over the channels, from its group delay at the
  * channel edges; L = next power of two >= front + back (>= 1), raised until
- * n_int divides N - L; nfront = front + (L - front - back) / 2; N (if 0) =
+ * n_int divides N - L; nfront = front + (L - front - back) / 2, moved down
+ * to a multiple of 16 if that stays >= front; N (if 0) =
  * max(smallest power of two > 2 x the widest channel's dispersion samples,
  * 2L, 256).  EINVAL if N is not a power of two in [256, 2^26], if
  * L >= N ("DM too large for fft_len"), or on any invalid argument below.
@@ -290,7 +291,8 @@ cdd_status cdd_gsb_inverse(const void* spectra, int64_t nspec, int32_t nchan, fl
  * in real samples (Sec. 2.2, 2.3): front = ceil of the dispersion samples
  * across the band, D*|DM|*(f_lo^-2 - f_hi^-2) * 2 bw, for DM >= 0 (back = 0;
  * swapped for DM < 0); L = the power of two >= front + back (>= 2), raised
- * until n_int divides N - L; nfront = front + (L - front - back)/2, moved to
+ * until n_int divides N - L; nfront = front + (L - front - back)/2, moved
+ * down to a multiple of 32 if that stays >= front, else to
  * the even neighbour inside [front, L - back]; N (if 0) = max(smallest power
  * of two > 2 x the dispersion samples, 2L, 2^16).  opts: dm_const, taper and
  * explicit_plan (fft_len, overlap, nfront even) apply.

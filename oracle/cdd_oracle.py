@@ -164,7 +164,8 @@ def overlap_plan(f_centre: float, bw: float, nchan: int, dms, n_int: int,
     front/back = ceil of the largest forward/backward reach of the impulse
     response over all channels and DMs; L = the power of two at or above
     front + back (at least 1), raised until n_int divides N - L; nfront =
-    front + floor((L - front - back) / 2) (the spare margin centred).
+    front + floor((L - front - back) / 2) (the spare margin centred), then
+    moved down to a multiple of 16 if that stays >= front.
     N defaults to the Sec. 2.3 rule on the widest channel dispersion, raised
     to 2L and to 256 if either is larger.
     """
@@ -188,6 +189,8 @@ def overlap_plan(f_centre: float, bw: float, nchan: int, dms, n_int: int,
     if L >= N:
         raise ValueError("fft_len too short for this DM: need N > %d" % L)
     nfront = front + (L - front - back) // 2
+    if nfront - nfront % 16 >= front:
+        nfront -= nfront % 16
     return N, L, nfront
 
 
@@ -396,8 +399,8 @@ def fullband_plan(f_lo: float, bw: float, dm: float, n_int: int,
     only, by the dispersion time across the band (Sec. 2.2): front = ceil of
     it, back = 0 (the other way round for DM < 0).  L = the power of two at or
     above front + back (at least 2), raised until n_int divides N - L; nfront
-    = front + floor((L - front - back)/2), moved to an even value inside
-    [front, L - back].  N defaults to the Sec. 2.3 rule, raised to 2L and to
+    = front + floor((L - front - back)/2), moved down to a multiple of 32 if
+    that stays >= front, else to an even value inside [front, L - back].  N defaults to the Sec. 2.3 rule, raised to 2L and to
     2^16 (the mode is for long transforms; shorter ones are the channel
     form's).  n_int must be even (integration over pairs of real samples)."""
     if n_int < 2 or n_int % 2:
@@ -413,7 +416,9 @@ def fullband_plan(f_lo: float, bw: float, dm: float, n_int: int,
     if L >= N:
         raise ValueError("fft_len too short for this DM: need N > %d" % L)
     nf = front + (L - front - back) // 2
-    if nf % 2:
+    if nf - nf % 32 >= front:
+        nf -= nf % 32
+    elif nf % 2:
         nf = nf + 1 if nf + 1 <= L - back else nf - 1
     return N, L, nf
 

@@ -158,6 +158,48 @@ __device__ __forceinline__ void apply_chirp(float2* v, double dm, double fc, con
   }
 }
 
+// The chirp phase is linear in DM (Eq. 3: q = DM x a function of the bin),
+// so a tile of DM trials forms the per-unit-DM phase of every bin of its
+// channel once per work item, in FP64 with the same expression as
+// apply_chirp at DM = 1, and each trial then costs one FP64 multiply per bin
+// before the same reduction and rotation.  Entry (b R + r) T + t belongs to
+// thread t alone (written and read by it, no barrier needed).
+template <class S>
+__device__ __forceinline__ void chirp_phase_per_dm(double* qd, double fc, const BlockArgs& a,
+                                                   int t) {
+  constexpr int N = S::N, R = S::rad_f(S::NP - 1), BPT = N / (R * S::T);
+  const double dfn = a.df / (double)N;
+  const double B = a.dconst * dfn * dfn / (fc * fc * fc);  // turns per unit DM
+  const double beta = dfn / fc;
+  const double Bb = B * beta, Bbb = Bb * beta;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const double s0 = (double)(t + S::T * b);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double sd = s0 + (double)(r * (N / R) - (2 * r >= R ? N : 0));
+      qd[(b * R + r) * S::T + t] = a.exact_div ? (B * (sd * sd)) / fma(beta, sd, 1.0)
+                                               : (sd * sd) * fma(sd, fma(sd, Bbb, -Bb), B);
+    }
+  }
+}
+
+template <class S>
+__device__ __forceinline__ void apply_chirp_dm(float2* v, double dm, const double* qd, int t) {
+  constexpr int N = S::N, R = S::rad_f(S::NP - 1), BPT = N / (R * S::T);
+#pragma unroll
+  for (int b = 0; b < BPT; ++b)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double q = dm * qd[(b * R + r) * S::T + t];
+      const float x = (float)(q - rint(q));
+      const float c = __builtin_amdgcn_cosf(x), sn = __builtin_amdgcn_sinf(x);
+      const float2 z = v[b * R + r];
+      v[b * R + r] = make_float2(z.x * c + z.y * sn, z.y * c - z.x * sn);  // z (c - i s)
+    }
+  (void)N;
+}
+
 // Taper (Sec. 2.2) on the bins this thread holds after the forward transform
 // (same bin layout as apply_chirp).
 template <class S>
@@ -304,9 +346,11 @@ __device__ __forceinline__ void epilogue(const float2* v, float* lds, const Bloc
   }
 }
 
+// qd: N doubles of LDS for the per-unit-DM chirp phase (DM tiles with the
+// FP64 phase), or null to form the phase per trial.
 template <class S, int DT, bool MULTI>
 __device__ __forceinline__ void process_item(const BlockArgs& a, int c, int64_t k, float* lds,
-                                             int t, bool live = true) {
+                                             int t, bool live = true, double* qd = nullptr) {
   const double fc = a.f_lo + ((double)c + 0.5) * a.df;
   float2 v[S::E];
   load_block<S, DT>(v, a, c, k, t);
@@ -327,6 +371,8 @@ __device__ __forceinline__ void process_item(const BlockArgs& a, int c, int64_t 
     float2 X[S::E];
 #pragma unroll
     for (int e = 0; e < S::E; ++e) X[e] = make_float2(v[e].x * inv_n, v[e].y * inv_n);
+    const bool per_dm = qd != nullptr && a.phase_mode == CDD_PHASE_FP64_REDUCED;
+    if (per_dm) chirp_phase_per_dm<S>(qd, fc, a, t);
     for (int i = 0; i < a.dms.ndm; ++i) {
       // Per-bin indices do not depend on the DM; an opaque copy of the
       // thread index keeps the compiler from hoisting them (and holding them
@@ -335,11 +381,22 @@ __device__ __forceinline__ void process_item(const BlockArgs& a, int c, int64_t 
       asm volatile("" : "+v"(tt));
 #pragma unroll
       for (int e = 0; e < S::E; ++e) v[e] = X[e];
-      apply_chirp<S>(v, a.dms.dm[i], fc, a, tt);
+      if (per_dm)
+        apply_chirp_dm<S>(v, a.dms.dm[i], qd, tt);
+      else
+        apply_chirp<S>(v, a.dms.dm[i], fc, a, tt);
       fft_inverse<S>(v, lds, a.tw, tt);
       epilogue<S, false>(v, lds, a, c, k, i, tt, live);
     }
   }
+}
+
+// DM tiles keep the per-unit-DM chirp phase in LDS up to 4096 points (8 N
+// bytes beside the exchange buffer, within what the register budget's
+// occupancy leaves); longer transforms form the phase per trial.
+template <class S>
+constexpr bool qd_in_lds() {
+  return S::N <= 4096;
 }
 
 // Workgroups are dispatched round-robin over the XCDs (8 on this chip, each
@@ -359,10 +416,12 @@ template <class S, int DT, bool MULTI>
 __global__ __launch_bounds__(S::T, MULTI ? (S::MINB + 1) / 2 : S::MINB) void block_kernel(
     const BlockArgs a) {
   __shared__ __align__(16) float lds[S::lds_floats()];
+  constexpr bool QD = MULTI && qd_in_lds<S>();
+  __shared__ double qd[QD ? S::N : 1];
   const int64_t item = xcd_item(blockIdx.x, (int64_t)gridDim.x);
   const int c = (int)(item / a.nblocks);
   const int64_t k = item - (int64_t)c * a.nblocks;
-  process_item<S, DT, MULTI>(a, c, k, lds, threadIdx.x);
+  process_item<S, DT, MULTI>(a, c, k, lds, threadIdx.x, true, QD ? qd : nullptr);
 }
 
 // Persistent form for several beams sharing one transform length and sample
@@ -376,6 +435,8 @@ __global__ __launch_bounds__(S::T, (S::MINB + 1) / 2) void batch_kernel(
     const BlockArgs* __restrict__ beams, int32_t nbeams, int64_t total,
     unsigned int* __restrict__ counter) {
   __shared__ __align__(16) float lds[S::lds_floats()];
+  constexpr bool QD = qd_in_lds<S>();
+  __shared__ double qd[QD ? S::N : 1];
   __shared__ unsigned int s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
@@ -396,7 +457,7 @@ __global__ __launch_bounds__(S::T, (S::MINB + 1) / 2) void batch_kernel(
     // registers across it)
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
-    process_item<S, DT, true>(a, c, k, lds, t);
+    process_item<S, DT, true>(a, c, k, lds, t, true, QD ? qd : nullptr);
   }
 }
 

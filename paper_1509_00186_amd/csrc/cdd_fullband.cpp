@@ -13,7 +13,8 @@
 // impulse response reaches forward by the dispersion time across the band
 // (backward for DM < 0); L = the power of two >= that reach (>= 2), raised
 // until n_int divides N - L; nfront = front + (L - front - back) / 2, moved
-// to an even value; N (if not given) = max(smallest power of two > twice the
+// down to a multiple of 32 if that stays >= front, else to an even value;
+// N (if not given) = max(smallest power of two > twice the
 // dispersion samples, 2L, 2^16).  Everything stays even so that blocks start
 // on sample pairs.
 #include <algorithm>
@@ -119,8 +120,14 @@ static cdd_status make_fullband_plan(int64_t nspec, int32_t nchan, double f_cent
                   (long long)L);
     f.N = (int32_t)N;
     f.L = (int32_t)L;
+    // centred, then moved down to a multiple of 32 real samples (16 sample
+    // pairs: whole 128-byte runs of the packed series) where the margin
+    // allows, else to an even value
     int32_t nf = f.front + (f.L - f.front - f.back) / 2;
-    if (nf % 2) nf = nf + 1 <= f.L - f.back ? nf + 1 : nf - 1;
+    if (nf - nf % 32 >= f.front)
+      nf -= nf % 32;
+    else if (nf % 2)
+      nf = nf + 1 <= f.L - f.back ? nf + 1 : nf - 1;
     f.nfront = nf;
     if (f.nfront < f.front || f.nfront > f.L - f.back || f.nfront % 2)
       return fail(CDD_EINTERNAL, "plan rule broke its invariant (nfront %d)", f.nfront);

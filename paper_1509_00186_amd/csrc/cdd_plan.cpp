@@ -162,7 +162,11 @@ cdd_status make_plan(int32_t dtype, int64_t nsamp, int32_t nchan,
                   (long long)N, (long long)L);
     p.N = (int32_t)N;
     p.L = (int32_t)L;
+    // the spare margin centred, then the start moved down to a multiple of
+    // 16 samples where the margin allows (the long transforms then write the
+    // kept window in whole 128-byte runs)
     p.nfront = p.front + (p.L - p.front - p.back) / 2;
+    if (p.nfront - p.nfront % 16 >= p.front) p.nfront -= p.nfront % 16;
   }
   if (p.variant < 0 || (block_supported(p.N) && p.variant >= block_variants(p.N)))
     return fail(CDD_EINVAL, "kernel_variant %d not available for fft_len %d", p.variant, p.N);

@@ -115,18 +115,22 @@ def test_fullband_several_chunks_of_spectra():
     assert rel_l2(I, o["P"]) <= TOL_I
 
 
-@pytest.mark.parametrize("lg,dm,n_int", [(24, 0.5, 16), (25, 1.0, 6)])
-def test_fullband_three_level_transforms(lg, dm, n_int):
+@pytest.mark.parametrize("lg,dm,n_int,odd_pairs", [(24, 0.5, 16, True), (24, 0.5, 16, False),
+                                                   (25, 1.0, 6, False)])
+def test_fullband_three_level_transforms(lg, dm, n_int, odd_pairs):
     """Real transforms of 2^24 and 2^25 points (packed complex 2^23 and
     2^24, columns split in two passes each): two blocks, the second ragged;
-    fused integration with split groups (n_int 16) and the separate
-    integration (n_int 6)."""
+    fused integration with an odd pair start (split groups) or the rule's
+    (a multiple of 32 samples), and the separate integration (n_int 6)."""
     nchan = 512
-    M = _cdd().fullband_query(1, nchan, 610.0, 16.0, dm, n_int, fft_len=1 << lg)["step"]
+    q = _cdd().fullband_query(1, nchan, 610.0, 16.0, dm, n_int, fft_len=1 << lg)
+    M = q["step"]
     nspec = -(-(M + M // 3 + 5000) // (2 * nchan))
-    sp = _records(20 + lg, nspec, nchan)
-    y, I, o, info = _fb_both(sp, 610.0, 16.0, dm, n_int, fft_len=1 << lg)
+    sp = _records(20 + lg + odd_pairs, nspec, nchan)
+    plan = dict(overlap=q["overlap"], nfront=q["nfront"] + 2) if odd_pairs else {}
+    y, I, o, info = _fb_both(sp, 610.0, 16.0, dm, n_int, fft_len=1 << lg, **plan)
     assert (info["fft_len"], info["nblocks"]) == (1 << lg, 2)
+    assert ((info["nfront"] // 2) % 2 == 1) == odd_pairs
     assert rel_l2(y, o["y"]) <= TOL_V, rel_l2(y, o["y"])
     assert rel_l2(I, o["P"]) <= TOL_I, rel_l2(I, o["P"])
 

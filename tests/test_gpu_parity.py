@@ -326,21 +326,22 @@ def test_long_transform_lengths_cf32(lgN):
     _check(got, o)
 
 
-@pytest.mark.parametrize("n_int", [16, 3])
-def test_three_level_transform_2_26_cf32(n_int):
+@pytest.mark.parametrize("n_int,odd_start", [(16, True), (16, False), (3, False)])
+def test_three_level_transform_2_26_cf32(n_int, odd_start):
     """2^26-point transforms (rows of 2^11, columns split 2^8 x 2^7): two
-    blocks, the second ragged; integration fused into the last column pass
-    with groups split between its runs (n_int 16, odd nfront), or the
-    separate integration (n_int 3)."""
+    blocks, the second ragged; integration fused into the last column pass,
+    with an odd window start (groups split between its runs) or the rule's
+    (a multiple of 16: none split), or the separate integration (n_int 3)."""
     N = 1 << 26
     fcen, bw, dm = 300.0, 4.0, 3072.0
     q = _cdd().query(1, 1000, 1, fcen, bw, dm, N, n_int)
     nsamp = q["step"] + 12_345
-    rng = np.random.default_rng(77 + n_int)
+    rng = np.random.default_rng(77 + n_int + odd_start)
     x = (rng.standard_normal(nsamp) + 1j * rng.standard_normal(nsamp)).astype(np.complex64)
-    got, o, info = _run_both(x, fcen, bw, dm, n_int, N)
+    plan = dict(overlap=q["overlap"], nfront=q["nfront"] | 1) if odd_start else {}
+    got, o, info = _run_both(x, fcen, bw, dm, n_int, N, **plan)
     assert (info["fft_len"], info["nblocks"]) == (N, 2)
-    assert n_int != 16 or info["nfront"] % 16 != 0
+    assert (info["nfront"] % 16 != 0) == odd_start
     _check(got, o)
 
 
@@ -392,10 +393,10 @@ def test_config1_full_size_and_pulse():
                        want_chan=True)
     torch.cuda.synchronize()
     info = g["info"]
-    assert (info["fft_len"], info["overlap"], info["nfront"]) == (1 << 18, 1 << 17, 64615)
+    assert (info["fft_len"], info["overlap"], info["nfront"]) == (1 << 18, 1 << 17, 64608)
     y = g["y"].cpu().numpy()[0]
     o = O.dedisperse(x, b.f_centre, b.bw, b.dm, b.n_int, fft_len=1 << 18, overlap=1 << 17,
-                     nfront=64615, want_voltages=True)
+                     nfront=64608, want_voltages=True)
     ev, ei = rel_l2(y, o["y"][0]), rel_l2(g["I"].cpu().numpy(), o["I"])
     flush("config 1 voltage rel L2 %.3g intensity rel L2 %.3g" % (ev, ei))
     assert ev <= TOL_V and ei <= TOL_I
