@@ -262,13 +262,33 @@ def _time(fn, torch, reps):
     return (time.perf_counter() - t0) / reps
 
 
+def _time_interleaved(fns, torch, reps, rounds=3, warmup=2):
+    """Seconds per call of each function, timed in alternating rounds of
+    ``reps`` calls after ``warmup`` untimed calls of each (the best round of
+    each counts), so that the GPU's clock ramp favours none of them."""
+    for fn in fns:
+        for _ in range(warmup):
+            fn()
+    torch.cuda.synchronize()
+    best = [float("inf")] * len(fns)
+    for _ in range(rounds):
+        for i, fn in enumerate(fns):
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            best[i] = min(best[i], (time.perf_counter() - t0) / reps)
+    return best
+
+
 def multibeam(cdd, torch, reps: int = 5, vd2=None, b2=None):
     """Four beams of uneven bandwidth and length (16/32/32/200 MHz, 512/512/
     1024/4096 channels, 1-4 s, DM 10/67.9/67.9/120), seeded int8 noise: one
-    plan (autotuned transform length per beam; each beam's launch pipelined
-    behind the layout changes, and as a variant every beam in one persistent
-    launch) against a loop of one-shot calls at the same plans, with the
-    one-DM chirps from per-execute tables and formed in the kernel.  With the
+    plan (autotuned transform length per beam; each beam in turn, and as
+    variants every beam in one launch, or every chirp formed in the kernel)
+    against a loop of one-shot calls at the same plans, with the
+    one-DM chirps from per-execute tables and formed in the kernel (all timed
+    in alternating rounds, best round each).  With the
     resident 512-channel beam ``vd2`` it also runs the workload as specified:
     64 DM trials on that beam plus the four beams in one plan, against the
     loop of 68 one-shot calls."""
@@ -282,13 +302,9 @@ def multibeam(cdd, torch, reps: int = 5, vd2=None, b2=None):
     plan = cdd.Plan(spec, autotune=True)
     t_tune = time.perf_counter() - t0
     infos = [plan.info(i) for i in range(len(beams))]
-    t_plan = _time(plan.execute, torch, reps)
     spec_n = [dict(s, fft_len=q["fft_len"]) for s, q in zip(spec, infos)]
     plan_k = cdd.Plan(spec_n, chirp_in_kernel=True)
-    t_plan_k = _time(plan_k.execute, torch, reps)
     plan_1 = cdd.Plan(spec_n, single_launch=True)
-    t_plan_1 = _time(plan_1.execute, torch, reps)
-    plan_1.close()
     outs = [cdd.dedisperse(v, b.f_centre, b.bw, b.dm, q["fft_len"], b.n_int,
                            overlap=q["overlap"], nfront=q["nfront"])
             for v, b, q in zip(vs, beams, infos)]
@@ -297,7 +313,9 @@ def multibeam(cdd, torch, reps: int = 5, vd2=None, b2=None):
         for v, b, q, o in zip(vs, beams, infos, outs):
             cdd.dedisperse(v, b.f_centre, b.bw, b.dm, q["fft_len"], b.n_int,
                            overlap=q["overlap"], nfront=q["nfront"], out=o)
-    t_loop = _time(loop, torch, reps)
+    t_plan, t_plan_k, t_plan_1, t_loop = _time_interleaved(
+        [plan.execute, plan_k.execute, plan_1.execute, loop], torch, reps)
+    plan_1.close()
     diff = max(float(torch.linalg.norm(plan.I[i][0] - outs[i]["I"]) /
                      torch.linalg.norm(outs[i]["I"])) for i in range(len(beams)))
     diff_k = max(float(torch.linalg.norm(plan_k.I[i][0] - outs[i]["I"]) /
@@ -324,7 +342,6 @@ def multibeam(cdd, torch, reps: int = 5, vd2=None, b2=None):
                         n_int=b2.n_int, fft_len=b2.fft_len)] + spec_n
         planc = cdd.Plan(allspec)
         ic = planc.info(0)
-        t_c = _time(planc.execute, torch, 2)
         o2 = [cdd.dedisperse(vd2, b2.f_centre, b2.bw, dm, b2.fft_len, b2.n_int,
                              overlap=ic["overlap"], nfront=ic["nfront"]) for dm in dms]
 
@@ -333,7 +350,7 @@ def multibeam(cdd, torch, reps: int = 5, vd2=None, b2=None):
                 cdd.dedisperse(vd2, b2.f_centre, b2.bw, dm, b2.fft_len, b2.n_int,
                                overlap=ic["overlap"], nfront=ic["nfront"], out=o)
             loop()
-        t_cl = _time(loop_all, torch, 2)
+        t_c, t_cl = _time_interleaved([planc.execute, loop_all], torch, 2, warmup=1)
         dc = float(torch.linalg.norm(planc.I[0] - torch.stack([o["I"] for o in o2])) /
                    torch.linalg.norm(torch.stack([o["I"] for o in o2])))
         planc.close()
@@ -384,7 +401,8 @@ def dm_trials(cdd, torch, vd, b, info, reps: int = 5, taper: str = "none",
               autotune: bool = False):
     """64 DM trials (60.0 + 0.254 i) on the same resident beam: the batched
     plan (forward transform shared, one persistent launch per 64 trials)
-    against a plain loop of single-DM calls at the same (N, L, nfront).  With
+    against a plain loop of single-DM calls at the same (N, L, nfront), timed
+    in alternating rounds (best round each).  With
     ``autotune`` the plan's transform length and schedule come from the
     autotuner (2^11 .. 2^14) instead of the beam's N."""
     import synth
@@ -393,27 +411,15 @@ def dm_trials(cdd, torch, vd, b, info, reps: int = 5, taper: str = "none",
                           fft_len=0 if autotune else b.fft_len)], taper=taper,
                     autotune=autotune)
     pi = plan.info(0)
-    plan.execute()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        plan.execute()
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / reps
     outs = [cdd.dedisperse(vd, b.f_centre, b.bw, dm, pi["fft_len"], b.n_int,
                            overlap=pi["overlap"], nfront=pi["nfront"], taper=taper)
             for dm in dms]
-    for dm, o in zip(dms, outs):  # one untimed pass at steady clocks
-        cdd.dedisperse(vd, b.f_centre, b.bw, dm, pi["fft_len"], b.n_int,
-                       overlap=pi["overlap"], nfront=pi["nfront"], taper=taper, out=o)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
+
+    def loop():
         for dm, o in zip(dms, outs):
             cdd.dedisperse(vd, b.f_centre, b.bw, dm, pi["fft_len"], b.n_int,
                            overlap=pi["overlap"], nfront=pi["nfront"], taper=taper, out=o)
-    torch.cuda.synchronize()
-    t_loop = (time.perf_counter() - t0) / reps
+    t_batch, t_loop = _time_interleaved([plan.execute, loop], torch, reps, rounds=2, warmup=1)
     tuned = (cdd.autotune(b.nchan, b.f_centre, b.bw, dms, b.n_int) if autotune else None)
     I_loop = torch.stack([o["I"] for o in outs])
     diff = float(torch.linalg.norm(plan.I[0] - I_loop) / torch.linalg.norm(I_loop))

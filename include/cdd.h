@@ -134,9 +134,9 @@ typedef struct {
                               per execute                                  */
   int32_t single_launch;   /* cdd_plan_*: per round of DM tiles, every beam
                               of length <= 8192 (per sample type) in one
-                              persistent launch after all layout changes,
-                              instead of one launch per beam pipelined
-                              behind the layout changes                    */
+                              launch after all layout changes, instead of
+                              one launch per beam, each after its own
+                              layout change                                */
 } cdd_opts;
 
 /* Plan figures for one beam (filled by cdd_query / cdd_plan_info). */
@@ -336,9 +336,11 @@ cdd_status cdd_fullband_dedisperse(const void* spectra, int64_t nspec, int32_t n
  * its delays and aligned sums; the chirp tables of one-DM beams are built
  * on an auxiliary stream beside the first layout change.  With
  * opts->single_launch, every beam of length 256 .. 8192 (and one sample
- * type) shares one persistent launch per round of DM tiles instead, longest
- * work per workgroup first (that kernel holds the largest length's register
- * budget, which lowers the occupancy of the short lengths).  A beam with a
+ * type) shares one launch per round of DM tiles instead: that length's own
+ * kernel when all share one length and chirp form, else one persistent
+ * launch, longest work per workgroup first, of a kernel that holds the
+ * largest length's register budget (which lowers the occupancy of the
+ * short lengths).  A beam with a
  * single DM reads its chirp from a table built once per execute unless
  * opts->chirp_in_kernel asks for the in-kernel chirp.
  * ------------------------------------------------------------------- */

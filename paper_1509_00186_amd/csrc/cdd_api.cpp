@@ -435,8 +435,11 @@ cdd_status cdd_plan_info_get(const cdd_plan* plan, int32_t beam, cdd_plan_info* 
 
 // Delays and aligned sums of beam b's tile of round r (and, for lengths above
 // the block kernel's, its four-step transforms first), on `stream`.
+// The tail of beam b's round r on the stream: the long transforms (lengths
+// beyond the block kernels), the delays (unless already computed) and the
+// aligned sums.
 static cdd_status finish_beam(cdd_plan* plan, char* ws, size_t b, int r, const void* xt,
-                              void* stream) {
+                              void* stream, bool delays_ready = false) {
   const BeamPlan& p = plan->beams[b];
   const cdd_beam& d = plan->desc[b];
   const int i0 = r * plan->tile[b];
@@ -458,9 +461,11 @@ static cdd_status finish_beam(cdd_plan* plan, char* ws, size_t b, int r, const v
     if ((e = stage_end(kStageBlock, stream, tok))) return device_fail("event record", e);
   }
   int32_t* dl = (int32_t*)(wb + lay.d_off);
-  if ((e = stage_begin(kStageDelays, stream, &tok))) return device_fail("event record", e);
-  if ((e = launch_delays(p, tile, dl, stream))) return device_fail("delay launch", e);
-  if ((e = stage_end(kStageDelays, stream, tok))) return device_fail("event record", e);
+  if (!delays_ready) {
+    if ((e = stage_begin(kStageDelays, stream, &tok))) return device_fail("event record", e);
+    if ((e = launch_delays(p, tile, dl, stream))) return device_fail("delay launch", e);
+    if ((e = stage_end(kStageDelays, stream, tok))) return device_fail("event record", e);
+  }
   if ((e = stage_begin(kStageDsum, stream, &tok))) return device_fail("event record", e);
   if ((e = launch_dsum(p, tile.ndm, P, dl, d.intensity + (int64_t)i0 * p.t_int,
                        d.coverage ? d.coverage + (int64_t)i0 * p.t_int : nullptr, p.t_int,
@@ -564,12 +569,27 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
       }
       std::vector<BatchBeam> group[kGroupKinds];
       std::vector<const void*> gh[kGroupKinds];
+      // when every beam of a sample type shares one length and one chirp
+      // form, that length's own kernel takes them all; otherwise the mixed
+      // kernel does (one launch either way)
+      int len[2] = {0, 0}, form[2] = {0, 0};
       for (size_t b = 0; b < nb; ++b) {
         const BeamPlan& p = plan->beams[b];
         BatchBeam bb;
         if (!block_supported(p.N) || tile_of(b, r, &bb) == 0) continue;
-        const int kind =
-            mixed_supported(p.N) ? kLaunchMixed : (H[b] ? kLaunchTables : kLaunchBatch);
+        const int t = p.dtype == CDD_CI8 ? 0 : 1, f = H[b] ? 1 : 2;
+        len[t] = len[t] == 0 ? p.N : (len[t] == p.N ? len[t] : -1);
+        form[t] = form[t] == 0 ? f : (form[t] == f ? f : -1);
+      }
+      for (size_t b = 0; b < nb; ++b) {
+        const BeamPlan& p = plan->beams[b];
+        BatchBeam bb;
+        if (!block_supported(p.N) || tile_of(b, r, &bb) == 0) continue;
+        const int t = p.dtype == CDD_CI8 ? 0 : 1;
+        const bool uniform = len[t] == p.N && form[t] > 0;
+        const int kind = (mixed_supported(p.N) && !uniform)
+                             ? kLaunchMixed
+                             : (H[b] ? kLaunchTables : kLaunchBatch);
         const int k = kind * 2 + (p.dtype == CDD_CI8 ? 0 : 1);
         group[k].push_back(bb);
         gh[k].push_back(H[b]);
@@ -633,6 +653,21 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
            (err = stage_end(kStageDelays, aux.aux, tok))))
         st = device_fail("chirp table launch", err);
     }
+    // the delays of every beam's first tile, beside the first layout change
+    for (size_t j = 0; j < nb && st == CDD_OK; ++j) {
+      const size_t b = order[j];
+      const BeamPlan& p = plan->beams[b];
+      DmTile t0;
+      t0.ndm = std::min(plan->tile[b], (int)p.dms.size());
+      for (int i = 0; i < t0.ndm; ++i) t0.dm[i] = p.dms[i];
+      int err = 0;
+      void* tok = nullptr;
+      if ((err = stage_begin(kStageDelays, aux.aux, &tok)) ||
+          (err = launch_delays(p, t0, (int32_t*)(ws + plan->ws_base[b] + plan->lay[b].d_off),
+                               aux.aux)) ||
+          (err = stage_end(kStageDelays, aux.aux, tok)))
+        st = device_fail("delay launch", err);
+    }
     for (size_t j = 0; j < nb && st == CDD_OK; ++j) {
       const size_t b = order[j];
       const BeamPlan& p = plan->beams[b];
@@ -654,7 +689,7 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
       while (st == CDD_OK && li < launches.size() && launches[li].round == 0 &&
              launches[li].beam == b)
         st = enqueue(launches[li++]);
-      if (st == CDD_OK) st = finish_beam(plan, ws, b, 0, xt[b], stream);
+      if (st == CDD_OK) st = finish_beam(plan, ws, b, 0, xt[b], stream, true);
     }
     const int ce = aux_close(stream, &aux);
     if (st != CDD_OK) return st;
@@ -662,8 +697,9 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
     for (int r = plan->single_launch ? 0 : 1; r < plan->rounds; ++r) {
       while (li < launches.size() && launches[li].round == r)
         if ((st = enqueue(launches[li++])) != CDD_OK) return st;
-      for (size_t j = 0; j < nb; ++j)
-        if ((st = finish_beam(plan, ws, order[j], r, xt[order[j]], stream)) != CDD_OK) return st;
+      for (size_t j = 0; j < nb; ++j)  // round 0's delays came from the auxiliary stream
+        if ((st = finish_beam(plan, ws, order[j], r, xt[order[j]], stream, r == 0)) != CDD_OK)
+          return st;
     }
     hipError_t he = hipEventRecord(plan->tab_done, (hipStream_t)stream);
     if (he != hipSuccess) return device_fail("event record", (int)he);

@@ -185,13 +185,13 @@ int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream
 // ---------------------------------------------------------------------------
 template <int DT>
 __global__ __launch_bounds__(256) void detect_kernel(const void* __restrict__ xt,
-                                                     float* __restrict__ P, int64_t nsamp,
+                                                     float* __restrict__ P, int64_t xstride,
                                                      int64_t t_int, int32_t n_int) {
   const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int c = blockIdx.y;
   if (u >= t_int) return;
   float s = 0.f;
-  const int64_t base = (int64_t)c * nsamp + u * n_int;
+  const int64_t base = (int64_t)c * xstride + u * n_int;
   for (int r = 0; r < n_int; ++r) {
     float re, im;
     if constexpr (DT == CDD_CI8) {
@@ -215,10 +215,10 @@ int launch_detect(const BeamPlan& p, const void* xt, float* P, void* stream) {
   dim3 grid((unsigned)nb, (unsigned)p.nchan);
   if (p.dtype == CDD_CI8)
     hipLaunchKernelGGL(detect_kernel<CDD_CI8>, grid, dim3(256), 0, (hipStream_t)stream, xt, P,
-                       p.nsamp, p.t_int, p.n_int);
+                       xt_stride(p), p.t_int, p.n_int);
   else
     hipLaunchKernelGGL(detect_kernel<CDD_CF32>, grid, dim3(256), 0, (hipStream_t)stream, xt, P,
-                       p.nsamp, p.t_int, p.n_int);
+                       xt_stride(p), p.t_int, p.n_int);
   return (int)hipGetLastError();
 }
 

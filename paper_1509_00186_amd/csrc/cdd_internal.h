@@ -63,8 +63,9 @@ struct WsLayout {
 };
 WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p, bool chirp_table = false);
 // Samples between channel rows of the channel-major copy of a record: for
-// the block kernels nsamp rounded up to 64 (every row starts on a 128-byte
-// boundary, so the layout change writes whole cache lines), else nsamp.
+// the block kernels and the incoherent detection nsamp rounded up to 64
+// (every row starts on a 128-byte boundary, so the layout change writes
+// whole cache lines); for the long transforms nsamp.
 int64_t xt_stride(const BeamPlan& p);
 
 // ---------------------------------------------------------------------

@@ -186,7 +186,7 @@ cdd_status make_plan(int32_t dtype, int64_t nsamp, int32_t nchan,
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 int64_t xt_stride(const BeamPlan& p) {
-  return block_supported(p.N) && p.nchan > 1 ? (p.nsamp + 63) / 64 * 64 : p.nsamp;
+  return !large_supported(p.N) && p.nchan > 1 ? (p.nsamp + 63) / 64 * 64 : p.nsamp;
 }
 
 WsLayout ws_layout(const BeamPlan& p, int ndm_tile, bool need_p, bool chirp_table) {

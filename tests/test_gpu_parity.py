@@ -547,6 +547,37 @@ def test_mixed_lengths_one_persistent_launch():
         plan.close()
 
 
+def test_one_length_beams_in_one_launch_of_that_length():
+    """One-DM beams that all share one transform length (1024): with
+    single_launch they go through one launch of that length's own kernel
+    (not the mixed one), every beam against the oracle."""
+    import torch
+    cdd = _cdd()
+    spec = [(610.0, 16, 0.03125, 9_000, 10.0), (325.0, 24, 0.0625, 11_000, 67.9),
+            (400.0, 8, 0.048828125, 7_001, 30.0)]
+    raw = [(_beam_int8(190 + k, nsamp, nchan, fcen, nchan * df, dm), fcen, nchan * df, dm)
+           for k, (fcen, nchan, df, nsamp, dm) in enumerate(spec)]
+    flush("case: three one-DM beams at N 1024, single_launch")
+    plan = cdd.Plan([dict(voltages=to_dev(v), f_centre=f, bw=bw, dms=[dm], n_int=4,
+                          fft_len=1024) for v, f, bw, dm in raw], single_launch=True)
+    plan.execute()
+    torch.cuda.synchronize()
+    cdd.profile_read()
+    cdd.profile_enable(True, stages=["block"])
+    plan.execute()
+    torch.cuda.synchronize()
+    cdd.profile_enable(False)
+    st = cdd.profile_read()
+    assert st["block"][1] == 1, st
+    for bi, (v, fcen, bw, dm) in enumerate(raw):
+        info = plan.info(bi)
+        o = O.dedisperse(v, fcen, bw, dm, 4, fft_len=1024, overlap=info["overlap"],
+                         nfront=info["nfront"])
+        assert rel_l2(plan.I[bi][0].cpu().numpy(), o["I"]) <= TOL_I, bi
+        assert np.array_equal(plan.cov[bi][0].cpu().numpy(), o["cov"])
+    plan.close()
+
+
 def test_dm_tiles_beyond_one_launch():
     """More DM trials than one launch holds (70 > 64): two rounds."""
     import torch
