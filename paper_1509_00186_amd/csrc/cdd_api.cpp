@@ -21,14 +21,14 @@ namespace {
 
 bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 
-// Layout change with stage timing; with H, the one-DM chirp table (of dm)
-// is built by the same kernel.
+// Layout change with stage timing; with H, the one-DM chirp table (of dm),
+// and with delays the channel delays, are built by the same kernel.
 int launch_transposed(const BeamPlan& p, const void* in, void* out, void* stream,
-                      void* H = nullptr, double dm = 0.0) {
+                      void* H = nullptr, double dm = 0.0, int32_t* delays = nullptr) {
   void* tok = nullptr;
   int e = stage_begin(kStageTranspose, stream, &tok);
   if (e) return e;
-  if ((e = H ? launch_transpose_chirp(p, in, out, dm, H, stream)
+  if ((e = H ? launch_transpose_chirp(p, in, out, dm, H, stream, delays)
              : launch_transpose(in, out, p.dtype, p.nsamp, p.nchan, xt_stride(p), stream)))
     return e;
   return stage_end(kStageTranspose, stream, tok);
@@ -56,15 +56,16 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
   if (table && lay.h_bytes < chirp_table_bytes(p))
     return fail(CDD_EINTERNAL, "no chirp table space");
   void* H = table ? ws + lay.h_off : nullptr;
-  bool table_built = false;
+  int32_t* d = (int32_t*)(ws + lay.d_off);
+  bool table_built = false;  // the layout change built the table and the delays
   if (xt == nullptr) {
     if (p.nchan > 1) {
       table_built = table && transpose_chirp_fits(p);
       if ((e = begin(kStageTranspose)) ||
-          (e = table_built
-                   ? launch_transpose_chirp(p, voltages, ws + lay.xt_off, tile.dm[0], H, stream)
-                   : launch_transpose(voltages, ws + lay.xt_off, p.dtype, p.nsamp, p.nchan,
-                                      xt_stride(p), stream)) ||
+          (e = table_built ? launch_transpose_chirp(p, voltages, ws + lay.xt_off, tile.dm[0], H,
+                                                    stream, d)
+                           : launch_transpose(voltages, ws + lay.xt_off, p.dtype, p.nsamp,
+                                              p.nchan, xt_stride(p), stream)) ||
           (e = end(kStageTranspose)))
         return device_fail("transpose launch", e);
       xt = ws + lay.xt_off;
@@ -73,12 +74,13 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
     }
   }
   float* P = chan_P ? chan_P : (float*)(ws + lay.p_off);
-  int32_t* d = (int32_t*)(ws + lay.d_off);
-  if ((e = begin(kStageDelays))) return device_fail("event record", e);
-  if ((e = launch_delays(p, tile, d, stream))) return device_fail("delay launch", e);
-  if (table && !table_built && (e = launch_chirp_table(p, tile.dm[0], H, stream)))
-    return device_fail("chirp table launch", e);
-  if ((e = end(kStageDelays))) return device_fail("event record", e);
+  if (!table_built) {
+    if ((e = begin(kStageDelays))) return device_fail("event record", e);
+    if ((e = launch_delays(p, tile, d, stream))) return device_fail("delay launch", e);
+    if (table && (e = launch_chirp_table(p, tile.dm[0], H, stream)))
+      return device_fail("chirp table launch", e);
+    if ((e = end(kStageDelays))) return device_fail("event record", e);
+  }
   if ((e = begin(kStageBlock))) return device_fail("event record", e);
   if (block_supported(p.N)) {
     if ((e = launch_block(p, xt, tile, P, volt_out, H, stream)))
@@ -628,45 +630,39 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
       if ((err = stage_end(kStageBlock, stream, tok))) return device_fail("event record", err);
       return CDD_OK;
     };
-    // Round 0.  The chirp table of a one-DM beam is built by its layout
-    // change where that kernel can (int8, a workgroup per channel at least),
-    // else on the auxiliary stream while the caller's stream changes the
-    // layout of the first beam.  In the pipelined form each beam then takes
-    // its layout change, its launch and its delays and aligned sums in turn
-    // on the caller's stream (running the layout changes of later beams
-    // beside the transforms of earlier ones slows both down on this GPU as
-    // much as it hides); the single-launch form changes every layout first.
+    // Round 0.  A one-DM beam whose layout change can carry them has its
+    // chirp table and delays built by that kernel; the tables and first-tile
+    // delays of the other beams are built on the auxiliary stream while the
+    // caller's stream changes the layout of the first beam (the auxiliary
+    // stream is not used at all when there are none).  In the pipelined form
+    // each beam then takes its layout change, its launches and its aligned
+    // sums in turn on the caller's stream (running the layout changes of
+    // later beams beside the transforms of earlier ones slows both down on
+    // this GPU as much as it hides); the single-launch form changes every
+    // layout first.
+    auto fused = [&](size_t b) { return H[b] && transpose_chirp_fits(plan->beams[b]); };
+    auto d_of = [&](size_t b) { return (int32_t*)(ws + plan->ws_base[b] + plan->lay[b].d_off); };
+    bool use_aux = false;
+    for (size_t b = 0; b < nb; ++b) use_aux = use_aux || !fused(b);
     AuxSession aux;
-    if ((e = aux_open(stream, &aux))) return device_fail("auxiliary stream", e);
+    if (use_aux && (e = aux_open(stream, &aux))) return device_fail("auxiliary stream", e);
     size_t li = 0;
     cdd_status st = CDD_OK;
-    bool tables_waited = false;
-    auto fused_table = [&](size_t b) { return H[b] && transpose_chirp_fits(plan->beams[b]); };
+    bool aux_waited = !use_aux;
     for (size_t j = 0; j < nb && st == CDD_OK; ++j) {
       const size_t b = order[j];
       const BeamPlan& p = plan->beams[b];
-      int err = 0;
-      void* tok = nullptr;
-      if (H[b] && !fused_table(b) &&
-          ((err = stage_begin(kStageDelays, aux.aux, &tok)) ||
-           (err = launch_chirp_table(p, p.dms[0], H[b], aux.aux)) ||
-           (err = stage_end(kStageDelays, aux.aux, tok))))
-        st = device_fail("chirp table launch", err);
-    }
-    // the delays of every beam's first tile, beside the first layout change
-    for (size_t j = 0; j < nb && st == CDD_OK; ++j) {
-      const size_t b = order[j];
-      const BeamPlan& p = plan->beams[b];
+      if (fused(b)) continue;
       DmTile t0;
       t0.ndm = std::min(plan->tile[b], (int)p.dms.size());
       for (int i = 0; i < t0.ndm; ++i) t0.dm[i] = p.dms[i];
       int err = 0;
       void* tok = nullptr;
       if ((err = stage_begin(kStageDelays, aux.aux, &tok)) ||
-          (err = launch_delays(p, t0, (int32_t*)(ws + plan->ws_base[b] + plan->lay[b].d_off),
-                               aux.aux)) ||
+          (H[b] && (err = launch_chirp_table(p, p.dms[0], H[b], aux.aux))) ||
+          (err = launch_delays(p, t0, d_of(b), aux.aux)) ||
           (err = stage_end(kStageDelays, aux.aux, tok)))
-        st = device_fail("delay launch", err);
+        st = device_fail("chirp table or delay launch", err);
     }
     for (size_t j = 0; j < nb && st == CDD_OK; ++j) {
       const size_t b = order[j];
@@ -674,30 +670,31 @@ cdd_status cdd_plan_execute(cdd_plan* plan, void* workspace, size_t ws_bytes, vo
       int err = 0;
       if (p.nchan > 1 &&
           (err = launch_transposed(p, plan->desc[b].voltages, (void*)xt[b], stream,
-                                   fused_table(b) ? H[b] : nullptr, p.dms[0]))) {
+                                   fused(b) ? H[b] : nullptr, p.dms[0],
+                                   fused(b) ? d_of(b) : nullptr))) {
         st = device_fail("transpose launch", err);
         break;
       }
       if (plan->single_launch) continue;
-      if (!tables_waited) {
+      if (!aux_waited) {
         if ((err = aux_mark(&aux, stream))) {
           st = device_fail("stream wait", err);
           break;
         }
-        tables_waited = true;
+        aux_waited = true;
       }
       while (st == CDD_OK && li < launches.size() && launches[li].round == 0 &&
              launches[li].beam == b)
         st = enqueue(launches[li++]);
       if (st == CDD_OK) st = finish_beam(plan, ws, b, 0, xt[b], stream, true);
     }
-    const int ce = aux_close(stream, &aux);
+    const int ce = use_aux ? aux_close(stream, &aux) : 0;
     if (st != CDD_OK) return st;
     if (ce) return device_fail("auxiliary stream", ce);
     for (int r = plan->single_launch ? 0 : 1; r < plan->rounds; ++r) {
       while (li < launches.size() && launches[li].round == r)
         if ((st = enqueue(launches[li++])) != CDD_OK) return st;
-      for (size_t j = 0; j < nb; ++j)  // round 0's delays came from the auxiliary stream
+      for (size_t j = 0; j < nb; ++j)  // round 0: delays already computed (see above)
         if ((st = finish_beam(plan, ws, order[j], r, xt[order[j]], stream, r == 0)) != CDD_OK)
           return st;
     }

@@ -8,6 +8,27 @@
 
 namespace cdd {
 
+// Delay of channel c at one DM in integrated samples (the expression of
+// delays_kernel below and of the host planner, in the same order, without
+// fused multiply-adds, so all three round to the same integers).
+__device__ __forceinline__ int32_t channel_delay(int c, double dm, int32_t nchan, double f_centre,
+                                                 double bw, double df, double dconst,
+                                                 int32_t n_int) {
+#pragma clang fp contract(off)
+  const double fc = (f_centre - bw / 2.0) + ((double)c + 0.5) * df;
+  const int cref = dm >= 0 ? nchan - 1 : 0;
+  const double fref = (f_centre - bw / 2.0) + ((double)cref + 0.5) * df;
+  const double x = dconst * dm * (1.0 / (fc * fc) - 1.0 / (fref * fref)) * df / (double)n_int;
+  return (int32_t)floor(x + 0.5);
+}
+
+// One DM's channel delays, computed by one workgroup of the layout change.
+struct DelayArgs {
+  int32_t* d;  // null: none
+  double dm, f_centre, bw, df, dconst;
+  int32_t nchan, n_int;
+};
+
 // ---------------------------------------------------------------------------
 // Time-major [nsamp][nchan] -> channel-major [nchan][nsamp].
 // int8 pairs (2 bytes per complex sample): 64 samples x 128 channels per
@@ -18,12 +39,14 @@ namespace cdd {
 // With ct.H set, workgroup w < ct.nwg also writes table workgroup w's share
 // of the one-DM chirp table once its tile stores are issued: the table's
 // FP64 arithmetic runs while the memory-bound layout change's traffic is in
-// flight, instead of in a kernel of its own beside it.
+// flight, instead of in a kernel of its own beside it.  With dl.d set, the
+// last workgroup also writes the channel delays.
 __global__ __launch_bounds__(256) void transpose_i8_kernel(const unsigned short* __restrict__ in,
                                                            unsigned short* __restrict__ out,
                                                            int64_t nsamp, int32_t nchan,
                                                            int32_t tiles_c, int32_t in_aligned,
-                                                           int64_t ostr, const ChirpTableArgs ct) {
+                                                           int64_t ostr, const ChirpTableArgs ct,
+                                                           const DelayArgs dl) {
   __shared__ unsigned short tile[64][128 + 4];
   const int64_t bid = blockIdx.x;
   const int c0 = (int)(bid % tiles_c) * 128;
@@ -80,6 +103,9 @@ __global__ __launch_bounds__(256) void transpose_i8_kernel(const unsigned short*
     }
   }
   if (ct.H != nullptr && blockIdx.x < ct.nwg) chirp_table_part(ct, blockIdx.x, l);
+  if (dl.d != nullptr && blockIdx.x == gridDim.x - 1)
+    for (int c = l; c < dl.nchan; c += 256)
+      dl.d[c] = channel_delay(c, dl.dm, dl.nchan, dl.f_centre, dl.bw, dl.df, dl.dconst, dl.n_int);
 }
 
 __global__ __launch_bounds__(256) void transpose_c8_kernel(const float2* __restrict__ in,
@@ -116,7 +142,7 @@ int launch_transpose(const void* in, void* out, int32_t dtype, int64_t nsamp, in
     hipLaunchKernelGGL(transpose_i8_kernel, dim3((unsigned)n), dim3(256), 0, st,
                        (const unsigned short*)in, (unsigned short*)out, nsamp, nchan,
                        (int32_t)tiles_c, (int32_t)(((uintptr_t)in & 7u) == 0), out_stride,
-                       ChirpTableArgs{});
+                       ChirpTableArgs{}, DelayArgs{});
   } else {
     const int64_t tiles_c = (nchan + 63) / 64, tiles_t = (nsamp + 63) / 64;
     const int64_t n = tiles_c * tiles_t;
@@ -135,7 +161,7 @@ bool transpose_chirp_fits(const BeamPlan& p) {
 }
 
 int launch_transpose_chirp(const BeamPlan& p, const void* in, void* out, double dm, void* H,
-                           void* stream) {
+                           void* stream, int32_t* delays) {
   if (!transpose_chirp_fits(p) || H == nullptr) return (int)hipErrorInvalidValue;
   const int64_t tiles_c = (p.nchan + 127) / 128, tiles_t = (p.nsamp + 63) / 64;
   const int64_t n = tiles_c * tiles_t;
@@ -144,9 +170,21 @@ int launch_transpose_chirp(const BeamPlan& p, const void* in, void* out, double 
   int kpt = 1;
   while ((int64_t)p.nchan * (p.N / (256 * kpt)) > n && 256 * kpt * 2 <= p.N) kpt *= 2;
   const ChirpTableArgs ct = chirp_table_args(p, dm, H, kpt);
+  DelayArgs dl{};
+  if (delays) {
+    dl.d = delays;
+    dl.dm = dm;
+    dl.f_centre = p.f_centre;
+    dl.bw = p.bw;
+    dl.df = p.df;
+    dl.dconst = p.dconst;
+    dl.nchan = p.nchan;
+    dl.n_int = p.n_int;
+  }
   hipLaunchKernelGGL(transpose_i8_kernel, dim3((unsigned)n), dim3(256), 0, (hipStream_t)stream,
                      (const unsigned short*)in, (unsigned short*)out, p.nsamp, p.nchan,
-                     (int32_t)tiles_c, (int32_t)(((uintptr_t)in & 7u) == 0), xt_stride(p), ct);
+                     (int32_t)tiles_c, (int32_t)(((uintptr_t)in & 7u) == 0), xt_stride(p), ct,
+                     dl);
   return (int)hipGetLastError();
 }
 
@@ -162,12 +200,8 @@ __global__ __launch_bounds__(256) void delays_kernel(int32_t* __restrict__ d, Dm
   const int c = blockIdx.x * 256 + threadIdx.x;
   const int i = blockIdx.y;
   if (c >= nchan || i >= dms.ndm) return;
-  const double dm = dms.dm[i];
-  const double fc = (f_centre - bw / 2.0) + ((double)c + 0.5) * df;
-  const int cref = dm >= 0 ? nchan - 1 : 0;
-  const double fref = (f_centre - bw / 2.0) + ((double)cref + 0.5) * df;
-  const double x = dconst * dm * (1.0 / (fc * fc) - 1.0 / (fref * fref)) * df / (double)n_int;
-  d[(int64_t)i * nchan + c] = (int32_t)floor(x + 0.5);
+  d[(int64_t)i * nchan + c] =
+      channel_delay(c, dms.dm[i], nchan, f_centre, bw, df, dconst, n_int);
 }
 #pragma clang fp contract(on)
 

@@ -102,12 +102,13 @@ int launch_block_co(const BeamPlan& p, const Coords& co, const void* xt, const D
                     float* P, void* vout, const void* H, void* stream);
 size_t chirp_table_bytes(const BeamPlan& p);
 int launch_chirp_table(const BeamPlan& p, double dm, void* H, void* stream);
-// The int8 layout change of a whole record (into [c][nsamp]) with the
-// one-DM chirp table built by the same kernel; possible when the layout
-// change has at least one workgroup per channel of the table.
+// The int8 layout change of a whole record (into [c][xt_stride]) with the
+// one-DM chirp table (and, if delays is set, the channel delays at that DM)
+// built by the same kernel; possible when the layout change has at least one
+// workgroup per channel of the table.
 bool transpose_chirp_fits(const BeamPlan& p);
 int launch_transpose_chirp(const BeamPlan& p, const void* in, void* out, double dm, void* H,
-                           void* stream);
+                           void* stream, int32_t* delays = nullptr);
 // One DM, block kernel, record split into time chunks with the layout change
 // and the aligned sums on an auxiliary stream (cdd_pipeline.hip).
 int run_pipelined(const BeamPlan& p, const void* voltages, double dm, char* xt, float* P,

@@ -67,11 +67,12 @@ static int aux_of(Aux** out) {
 }
 
 // One chunk: the layout change, the block kernel and the aligned sum run in
-// order on the caller's stream (no cross-stream wait in front of the block
-// kernel); the delays run meanwhile on the auxiliary stream, which the
-// caller's stream waits for before the block kernel.  The chirp table is
-// built by the layout-change kernel itself (int8 records with at least one
-// layout workgroup per channel), else beside it on the auxiliary stream.
+// order on the caller's stream.  For int8 records with at least one layout
+// workgroup per channel the layout-change kernel also builds the chirp table
+// and the channel delays, so the call is those three kernels on one stream
+// and nothing else; otherwise the table and the delays run beside the
+// layout change on the auxiliary stream, which the caller's stream waits
+// for before the block kernel.
 static int run_single(Aux& ax, const BeamPlan& p, const void* voltages, double dm, char* xt,
                       float* P, int32_t* d, void* H, void* volt_out, float* I, int32_t* cov,
                       int npol, hipStream_t S) {
@@ -82,30 +83,33 @@ static int run_single(Aux& ax, const BeamPlan& p, const void* voltages, double d
   DmTile tile;
   tile.ndm = 1;
   tile.dm[0] = dm;
-  const bool fused_table = H != nullptr && transpose_chirp_fits(p);
-  // fork after the caller's earlier work (a previous call may still read H)
-  hipEvent_t e0 = take(ax);
-  if ((e = hipEventRecord(e0, S)) != hipSuccess) return (int)e;
-  if ((e = hipStreamWaitEvent(A, e0, 0)) != hipSuccess) return (int)e;
-  if ((err = stage_begin(kStageDelays, A, &tok))) return err;
-  if (!fused_table && (err = launch_chirp_table(p, dm, H, A))) return err;
-  if ((err = launch_delays(p, tile, d, A))) return err;
-  if ((err = stage_end(kStageDelays, A, tok))) return err;
-  hipEvent_t eA = take(ax);
-  if ((e = hipEventRecord(eA, A)) != hipSuccess) return (int)e;
+  const bool fused = H != nullptr && transpose_chirp_fits(p);
+  hipEvent_t eA = nullptr;
+  if (!fused) {
+    // fork after the caller's earlier work (a previous call may still read H)
+    hipEvent_t e0 = take(ax);
+    if ((e = hipEventRecord(e0, S)) != hipSuccess) return (int)e;
+    if ((e = hipStreamWaitEvent(A, e0, 0)) != hipSuccess) return (int)e;
+    if ((err = stage_begin(kStageDelays, A, &tok))) return err;
+    if (H && (err = launch_chirp_table(p, dm, H, A))) return err;
+    if ((err = launch_delays(p, tile, d, A))) return err;
+    if ((err = stage_end(kStageDelays, A, tok))) return err;
+    eA = take(ax);
+    if ((e = hipEventRecord(eA, A)) != hipSuccess) return (int)e;
+  }
   // polarisation records back to back; the second adds its intensities
   const size_t rec = (size_t)p.nsamp * p.nchan * (p.dtype == CDD_CI8 ? 2 : 8);
   Coords co = offline_coords(p);
   for (int pol = 0; pol < npol; ++pol) {
     if ((err = stage_begin(kStageTranspose, S, &tok))) return err;
-    if (pol == 0 && fused_table)
-      err = launch_transpose_chirp(p, voltages, xt, dm, H, S);
+    if (pol == 0 && fused)
+      err = launch_transpose_chirp(p, voltages, xt, dm, H, S, d);
     else
       err = launch_transpose((const char*)voltages + pol * rec, xt, p.dtype, p.nsamp, p.nchan,
                              xt_stride(p), S);
     if (err) return err;
     if ((err = stage_end(kStageTranspose, S, tok))) return err;
-    if (pol == 0 && (e = hipStreamWaitEvent(S, eA, 0)) != hipSuccess) return (int)e;
+    if (pol == 0 && eA && (e = hipStreamWaitEvent(S, eA, 0)) != hipSuccess) return (int)e;
     co.accum = pol > 0;
     if ((err = stage_begin(kStageBlock, S, &tok))) return err;
     if ((err = launch_block_co(p, co, xt, tile, P, volt_out, H, S))) return err;
