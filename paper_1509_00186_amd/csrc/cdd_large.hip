@@ -778,7 +778,9 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
                           float* P, void* vout, int exact_div, void* stream) {
   using SP = Split<LGN>;
   using SR = typename SP::SR;
-  constexpr int GR = SR::T * 8 <= 1024 ? 8 : 4;
+  // 2048-point rows four to a workgroup: eight (1024 threads) would cap the
+  // registers at 128 and spill
+  constexpr int GR = SR::T * 8 <= 512 ? 8 : 4;
   LargeArgs a{};
   int e = set_split<LGN>(a);
   if (e) return e;

@@ -253,9 +253,14 @@ def test_plan_window_lies_inside_uncorrupted_span(fcen, bw, nchan, dms, n_int, f
     N, L, nfront = O.overlap_plan(fcen, bw, nchan, dms, n_int, fft)
     fc, df = O.channel_centres(fcen, bw, nchan)
     assert (N - L) % n_int == 0 and N & (N - 1) == 0
+    fronts = []
     for dm in dms:
         fr, bk = O.wrap_extent(fc, df, dm)
         assert nfront >= math.ceil(fr) and nfront + (N - L) <= N - math.ceil(bk)
+        fronts.append(math.ceil(fr))
+    # the window start is a multiple of 16 unless rounding it down would cut
+    # into the impulse response's reach
+    assert nfront % 16 == 0 or (nfront - nfront % 16) < max(fronts)
 
 
 # --------------------------------------------------------------------------
