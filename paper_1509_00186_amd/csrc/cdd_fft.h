@@ -289,7 +289,10 @@ __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 // Twiddles of one pass (radix R, span NS) for this thread's butterflies,
 // loaded ahead of the exchange that precedes the pass.  The table holds
 // W^(r k) at r * NS + k, so the lanes of a wave, whose k are consecutive,
-// read consecutive entries.
+// read consecutive entries.  The loads go through a buffer resource on the
+// pass's table (scalar base, constant offset r NS per load), so each needs
+// only the thread's offset k, formed once per butterfly group, and no
+// 64-bit address arithmetic.
 template <class S, int R, int NS, int TWOFF>
 struct PassTw {
   static constexpr int BPT = S::N / (R * S::T);
@@ -297,12 +300,15 @@ struct PassTw {
   float2 w[CNT];
   __device__ __forceinline__ void load(const float2* __restrict__ tw, int t) {
     if constexpr (NS > 1) {
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(tw + TWOFF), (short)0, R * NS * 8, 0x00020000);
 #pragma unroll
       for (int b = 0; b < BPT; ++b) {
         const int k = (t + S::T * b) & (NS - 1);
-        const float2* col = tw + TWOFF + k;
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[b * (R - 1) + r - 1] = gload2(col, r * NS);
+        for (int r = 1; r < R; ++r)
+          w[b * (R - 1) + r - 1] = __builtin_bit_cast(
+              float2, __builtin_amdgcn_raw_buffer_load_b64(rs, k * 8, r * NS * 8, 0));
       }
     }
   }
