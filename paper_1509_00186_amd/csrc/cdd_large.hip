@@ -703,17 +703,18 @@ int64_t large_chunk_items(const BeamPlan& p) {
 
 // How an N = 2^LGN point transform is split: N1 = 2^LG1 (rows), and the
 // column dimension N2 = A B with A = 2^LGA, B = 2^LGB.  Up to 2^22 points
-// two levels (A = 1, N2 = 2^(LGN/2)); beyond, three, with every
-// sub-transform between 128 and 2048 points.  The channel transforms of
-// 2^16 .. 2^20 points take columns half as long (and rows twice as long):
-// the two column passes then hold half the data per workgroup and run five
-// workgroups per CU instead of two (config 1: -4 to -5% per call); the
-// full-band row pass, which holds two rows per pair, is faster the other way.
-template <int LGN, bool REAL = false>
+// two levels; beyond, three, with every sub-transform between 128 and 2048
+// points.  Up to 2^22 the columns are 2^(LGN/2) long, except from 2^16 to
+// 2^20 points, where columns half as long (rows twice as long) measured
+// faster: the column passes then hold half the data per workgroup and more
+// workgroups fit on a CU (2^18-point channel transforms 0.175 -> 0.168 ms per
+// call on the 2^23-sample single-channel workload; the full band at 2^19,
+// 2^20 and 2^21 real points 0.195 -> 0.184, 0.162 -> 0.144 and 0.181 ->
+// 0.153 ms, with the row groups below).
+template <int LGN>
 struct Split {
   static constexpr int LGA = LGN <= 22 ? 0 : (LGN >= 26 ? 8 : 7);
-  static constexpr int LGB =
-      LGN <= 22 ? ((!REAL && LGN >= 16 && LGN <= 20) ? LGN / 2 - 1 : LGN / 2) : 7;
+  static constexpr int LGB = LGN > 22 ? 7 : (LGN >= 16 && LGN <= 20) ? LGN / 2 - 1 : LGN / 2;
   static constexpr int LG1 = LGN - LGA - LGB;
   static constexpr int N1 = 1 << LG1, A = 1 << LGA, B = 1 << LGB, N2 = A * B;
   static constexpr bool THREE = LGA > 0;
@@ -726,10 +727,20 @@ struct Split {
                 "sub-transforms of 128 .. 2048 points, column groups tiling N1");
 };
 
+// Rows per workgroup of the row pass (T threads per row): at most eight and
+// at most 256 threads.  Small workgroups let several be resident per CU at
+// different phases (loads of one beside the transforms of another); 1024-point
+// rows four to a workgroup instead of eight: 0.168 -> 0.158 ms per call on
+// the 2^23-sample single-channel workload; 2048-point rows two instead of
+// four: 2^22-point channel transforms 1.40 -> 1.37 ms, full band at 2^20
+// real points 0.156 -> 0.144 ms.  (With the real series each workgroup holds
+// mirror-row pairs, so the count stays even.)
+constexpr int rows_per_group(int T) { return T * 8 <= 256 ? 8 : 256 / T; }
+
 // Fill the split-dependent fields of a and its sub-transform twiddles.
-template <int LGN, bool REAL>
+template <int LGN>
 static int set_split(LargeArgs& a) {
-  using SP = Split<LGN, REAL>;
+  using SP = Split<LGN>;
   int e = twiddles_of<typename SP::SC>(&a.twc);
   if (!e) e = twiddles_of<typename SP::SR>(&a.twr);
   if (!e && SP::THREE) e = twiddles_of<typename SP::SA>(&a.twm);
@@ -748,7 +759,7 @@ static int set_split(LargeArgs& a) {
 // integration.  GR rows per workgroup.
 template <int LGN, int DT, bool REAL, int GR>
 static int run_passes(const LargeArgs& a, int64_t q, hipStream_t st) {
-  using SP = Split<LGN, REAL>;
+  using SP = Split<LGN>;
   using SC = typename SP::SC;
   using SA = typename SP::SA;
   using SR = typename SP::SR;
@@ -781,13 +792,11 @@ static int run_passes(const LargeArgs& a, int64_t q, hipStream_t st) {
 template <int LGN>
 static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* S, float* pbuf,
                           float* P, void* vout, int exact_div, void* stream) {
-  using SP = Split<LGN, false>;
+  using SP = Split<LGN>;
   using SR = typename SP::SR;
-  // 2048-point rows four to a workgroup: eight (1024 threads) would cap the
-  // registers at 128 and spill
-  constexpr int GR = SR::T * 8 <= 512 ? 8 : 4;
+  constexpr int GR = rows_per_group(SR::T);
   LargeArgs a{};
-  int e = set_split<LGN, false>(a);
+  int e = set_split<LGN>(a);
   if (e) return e;
   a.x = xt;
   a.S = S;
@@ -880,11 +889,11 @@ int64_t fullband_chunk_blocks(const FullbandPlan& f) {
 template <int LGN>
 static int launch_fullband_t(const FullbandPlan& f, const float* series, float2* S, float* pbuf,
                              float2* hb, float* I, float* vout, void* stream) {
-  using SP = Split<LGN, true>;
+  using SP = Split<LGN>;
   using SR = typename SP::SR;
-  constexpr int GR = (SR::T * 8 <= 1024 && 8 * 2 * SP::N1 * 4 <= 65536) ? 8 : 4;
+  constexpr int GR = rows_per_group(SR::T);
   LargeArgs a{};
-  int e = set_split<LGN, true>(a);
+  int e = set_split<LGN>(a);
   if (e) return e;
   a.x = series;
   a.S = S;
