@@ -578,6 +578,39 @@ def test_one_length_beams_in_one_launch_of_that_length():
     plan.close()
 
 
+def test_evenly_spaced_dm_tile_recurrence():
+    """64 evenly spaced DM trials (one tile), ascending and descending, on a
+    band whose chirp phases reach about 115 turns at the channel edges (1.7
+    turns between neighbouring trials): the tile advances the
+    chirped spectrum by a fixed per-bin rotation per trial; every trial
+    against the one-DM call (chirp table from the FP64 phase) and the first,
+    middle and last against the oracle."""
+    import torch
+    cdd = _cdd()
+    fcen, nchan, df, nsamp, n_int, N = 150.0, 8, 0.25, 12_000, 4, 2048
+    v = _beam_int8(90, nsamp, nchan, fcen, nchan * df, 3.0)
+    vd = to_dev(v)
+    step = 5.5 / 63
+    for dms in ([0.5 + step * i for i in range(64)], [6.0 - step * i for i in range(64)]):
+        flush("case: evenly spaced tile from DM %.2f step %.4f" % (dms[0], dms[1] - dms[0]))
+        plan = cdd.Plan([dict(voltages=vd, f_centre=fcen, bw=nchan * df, dms=dms,
+                              n_int=n_int, fft_len=N)])
+        plan.execute()
+        torch.cuda.synchronize()
+        info = plan.info(0)
+        for i, dm in enumerate(dms):
+            one = cdd.dedisperse(vd, fcen, nchan * df, dm, N, n_int, overlap=info["overlap"],
+                                 nfront=info["nfront"])
+            torch.cuda.synchronize()
+            assert rel_l2(plan.I[0][i].cpu().numpy(), one["I"].cpu().numpy()) <= 1e-5, (i, dm)
+        for i in (0, 31, 63):
+            o = O.dedisperse(v, fcen, nchan * df, dms[i], n_int, fft_len=N,
+                             overlap=info["overlap"], nfront=info["nfront"])
+            assert rel_l2(plan.I[0][i].cpu().numpy(), o["I"]) <= TOL_I, i
+            assert np.array_equal(plan.cov[0][i].cpu().numpy(), o["cov"])
+        plan.close()
+
+
 def test_dm_tiles_beyond_one_launch():
     """More DM trials than one launch holds (70 > 64): two rounds."""
     import torch
