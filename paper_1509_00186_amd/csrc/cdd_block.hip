@@ -201,20 +201,6 @@ __device__ __forceinline__ void apply_chirp_dm(float2* v, double dm, const doubl
   (void)N;
 }
 
-// Evenly spaced DM trials, DM_i = DM_0 + i step: the chirp of trial i + 1 is
-// that of trial i times exp(-2 pi i step Q) with Q the per-unit-DM phase of
-// the bin (Eq. 3 is linear in DM), so a tile keeps the chirped spectrum of
-// the current trial and advances it by one complex multiply per bin and
-// trial instead of forming the FP64 phase and its sine and cosine again.
-// The first trial's chirp and then the step rotation of every bin are formed
-// once per work item in FP64 (phase reduced to [-1/2, 1/2] turns, then an
-// FP64 sine and cosine) and rounded to FP32 once, so each step carries the
-// same relative error of at most 2^-24 sqrt 2 (8.4e-8) in the rotation, plus
-// the rounding of the product: after k steps the chirp is off by at most
-// about k 1e-7 (6e-6 relative at the 64th trial of a tile; measured on the
-// 512-channel beam, the intensities of 64 trials differ from 64 one-DM calls
-// by 1.1e-7 relative L2).  Entry (b R + r) T + t belongs to thread t alone,
-// as in chirp_phase_per_dm (whose LDS the table takes).
 // exp(-2 pi i x) for |x| <= 1/2 turn, rounded to FP32: the quadrant
 // n = rint(4x) is taken out exactly, and the sine and cosine of the remaining
 // angle (at most pi/4) come from their Taylor series in FP64 through the
@@ -241,6 +227,21 @@ __device__ __forceinline__ float2 expi_neg_turns_fp64(double x) {
   return make_float2((float)c, (float)-sn);
 }
 
+// Evenly spaced DM trials, DM_i = DM_0 + i step: the chirp of trial i + 1 is
+// that of trial i times exp(-2 pi i step Q) with Q the per-unit-DM phase of
+// the bin (Eq. 3 is linear in DM), so a tile keeps the chirped spectrum of
+// the current trial and advances it by one complex multiply per bin and
+// trial instead of forming the FP64 phase and its sine and cosine again.
+// The first trial's chirp and then the step rotation of every bin are formed
+// once per work item in FP64 (phase reduced to [-1/2, 1/2] turns, then an
+// FP64 sine and cosine) and rounded to FP32 once, so each step carries the
+// same relative error of at most 2^-24 sqrt 2 (8.4e-8) in the rotation, plus
+// the rounding of the product: after k steps the chirp is off by at most
+// about k 1e-7 (6e-6 relative at the 64th trial of a tile; measured on the
+// 512-channel beam, the intensities of 64 trials differ from 64 one-DM calls
+// by 1.1e-7 relative L2).  Entry (b R + r) T + t belongs to thread t alone,
+// as in chirp_phase_per_dm (whose LDS the table takes).
+// rs[] receives exp(-2 pi i DM Q) of this thread's bins for the given DM.
 template <class S>
 __device__ __forceinline__ void rotation_table(float2* rs, double dm, double fc,
                                                const BlockArgs& a, int t) {
