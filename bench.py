@@ -362,6 +362,37 @@ def multibeam(cdd, torch, reps: int = 5, vd2=None, b2=None):
             "plan_msamples_dm_per_s": round(sdm / t_c / 1e6, 1),
             "loop_msamples_dm_per_s": round(sdm / t_cl / 1e6, 1),
             "rel_l2_plan_vs_loop_dm_trials": dc}
+        # the same with the autotuner choosing every beam's transform length
+        # (the loop of one-shot calls runs at the lengths it chose)
+        t0 = time.perf_counter()
+        plana = cdd.Plan([dict(allspec[0], fft_len=0)] + spec, autotune=True)
+        t_tune_a = time.perf_counter() - t0
+        ia = [plana.info(i) for i in range(1 + len(beams))]
+        oa = [cdd.dedisperse(vd2, b2.f_centre, b2.bw, dm, ia[0]["fft_len"], b2.n_int,
+                             overlap=ia[0]["overlap"], nfront=ia[0]["nfront"]) for dm in dms]
+        oa4 = [cdd.dedisperse(v, b.f_centre, b.bw, b.dm, q["fft_len"], b.n_int,
+                              overlap=q["overlap"], nfront=q["nfront"])
+               for v, b, q in zip(vs, beams, ia[1:])]
+
+        def loop_all_a():
+            for dm, o in zip(dms, oa):
+                cdd.dedisperse(vd2, b2.f_centre, b2.bw, dm, ia[0]["fft_len"], b2.n_int,
+                               overlap=ia[0]["overlap"], nfront=ia[0]["nfront"], out=o)
+            for v, b, q, o in zip(vs, beams, ia[1:], oa4):
+                cdd.dedisperse(v, b.f_centre, b.bw, b.dm, q["fft_len"], b.n_int,
+                               overlap=q["overlap"], nfront=q["nfront"], out=o)
+        t_a, t_al = _time_interleaved([plana.execute, loop_all_a], torch, 2, warmup=1)
+        da = float(torch.linalg.norm(plana.I[0] - torch.stack([o["I"] for o in oa])) /
+                   torch.linalg.norm(torch.stack([o["I"] for o in oa])))
+        plana.close()
+        res["as_specified_autotuned"] = {
+            "what": "the same plan with every beam's transform length from the autotuner",
+            "fft_len": [q["fft_len"] for q in ia], "autotune_s": round(t_tune_a, 2),
+            "plan_ms": round(t_a * 1e3, 3), "loop_ms": round(t_al * 1e3, 3),
+            "speedup": round(t_al / t_a, 3),
+            "plan_msamples_dm_per_s": round(sdm / t_a / 1e6, 1),
+            "loop_msamples_dm_per_s": round(sdm / t_al / 1e6, 1),
+            "rel_l2_plan_vs_loop_dm_trials": da}
     return res
 
 
