@@ -147,13 +147,16 @@ def test_taper_one_dm_against_oracle(window):
     assert rel_l2(got["I"], plain["I"]) > 1e-3
 
 
+@pytest.mark.parametrize("dms", [[10.0, 11.5, 8.0], [8.0, 9.5, 11.0, 12.5]],
+                         ids=["uneven", "evenly_spaced"])
 @pytest.mark.parametrize("window", ["hann", "welch"])
-def test_taper_batched_dm_trials_against_oracle(window):
-    """The taper in the chirp generated inside the persistent batched kernel."""
+def test_taper_batched_dm_trials_against_oracle(window, dms):
+    """The taper in the chirp generated inside the persistent batched kernel,
+    with the per-trial phase (uneven DMs) and the rotation step (evenly
+    spaced DMs)."""
     import torch
     cdd = _cdd()
     v = _beam_int8(131, 12_000, 16, 610.0, 16 * 0.03125, 10.0)
-    dms = [10.0, 11.5, 8.0]
     plan = cdd.Plan([dict(voltages=to_dev(v), f_centre=610.0, bw=0.5, dms=dms, n_int=2,
                           fft_len=1024)], taper=window)
     plan.execute()
