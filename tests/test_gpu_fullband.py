@@ -72,6 +72,22 @@ def test_fullband_against_oracle(nchan, nspec, fcen, bw, dm, n_int, taper):
         assert rel_l2(y, o["x"]) <= TOL_V
 
 
+@pytest.mark.parametrize("lg", [20, 21, 22])
+def test_fullband_two_level_lengths(lg):
+    """Real transforms of 2^20 .. 2^22 points (2048-point row pairs, columns
+    of 256 .. 1024): 16 MHz at 610 MHz with the DM scaled so the impulse
+    response spans about an eighth of the transform, two blocks, the second
+    ragged."""
+    N = 1 << lg
+    dm = 10.0 * N / (1 << 21)
+    nspec = (8 * N // 5) // 1024 + 3
+    sp = _records(40 + lg, nspec, 512)
+    y, I, o, info = _fb_both(sp, 610.0, 16.0, dm, 16, fft_len=N)
+    assert info["fft_len"] == N and info["nblocks"] == 2
+    assert rel_l2(y, o["y"]) <= TOL_V, rel_l2(y, o["y"])
+    assert rel_l2(I, o["P"]) <= TOL_I, rel_l2(I, o["P"])
+
+
 def test_fullband_explicit_plan():
     sp = _records(11, 400, 512)
     y, I, o, info = _fb_both(sp, 610.0, 16.0, 0.5, 4, fft_len=1 << 17, overlap=1 << 15,

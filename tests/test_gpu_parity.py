@@ -316,7 +316,7 @@ def test_multi_beam_plan_uneven_beams():
 # ---------------------------------------------------------------------------
 # Long transforms (four-step kernels, N >= 2^15)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("lgN", [15, 16, 17, 19, 20, 22, 23, 24])
+@pytest.mark.parametrize("lgN", [15, 16, 17, 19, 20, 21, 22, 23, 24])
 def test_long_transform_lengths_cf32(lgN):
     N = 1 << lgN
     fcen, bw = 300.0, 4.0
