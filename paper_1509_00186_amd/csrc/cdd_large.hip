@@ -636,51 +636,73 @@ __global__ __launch_bounds__(SR::T * G) void rows_real_kernel(const LargeArgs a)
 // (with w = exp(-i pi / L) and X_L = 0), the record becomes L complex values
 // Z_c = (E_c + i O_c), whose inverse DFT (times 1/L) is the record's 2L real
 // samples in pairs.  A group of SC::T lanes handles one record; G records
-// per workgroup.
+// per workgroup.  The workgroups loop over groups of G records (grid-stride),
+// each lane holding the next group's words in registers while the current
+// group is transformed and stored, so loads, transforms and stores of
+// different groups overlap instead of every workgroup loading, then
+// transforming, then storing at the same time.
 template <class SC, int G>
 __global__ __launch_bounds__(SC::T * G) void gsb_inverse_kernel(
     const uint32_t* __restrict__ spec, float2* __restrict__ out,
     const float2* __restrict__ pre, const float2* __restrict__ tw, int64_t nspec) {
   constexpr int L = SC::N, STRIDE = pair_stride<SC::N, SC::lds_floats()>();
+  constexpr int W = L / 2 / SC::T;  // words (two bins each) per lane per record
   static_assert(STRIDE % 4 == 0, "records are staged as float4");
+  static_assert(W * SC::T == L / 2, "lanes tile a record's words");
   __shared__ __align__(16) float lds[G * STRIDE];
   constexpr int RI = SC::rad_i(0), BI = L / (RI * SC::T);
   constexpr int R0 = SC::rad_f(0), B0 = L / (R0 * SC::T);
   const int t = threadIdx.x, g = t / SC::T, tl = t % SC::T;
-  const int64_t s = (int64_t)blockIdx.x * G + g;
-  const bool live = s < nspec;
+  const int64_t ngroups = (nspec + G - 1) / G;
   float* my = lds + g * STRIDE;
   float4* X4 = (float4*)my;
-  for (int c2 = tl; c2 < L / 2; c2 += SC::T) {
-    const uint32_t w = live ? spec[s * (L / 2) + c2] : 0u;
-    X4[c2] = make_float4((float)(int8_t)(w & 0xffu), (float)(int8_t)((w >> 8) & 0xffu),
-                         (float)(int8_t)((w >> 16) & 0xffu), (float)(int8_t)(w >> 24));
-  }
-  __syncthreads();
-  const float2* X = (const float2*)my;
   const float sc = 0.5f / (float)L;
-  float2 v[SC::E];
+  uint32_t wd[W];
+  auto fetch = [&](int64_t grp) {
+    const int64_t s = grp * G + g;
+    const bool ok = grp < ngroups && s < nspec;
 #pragma unroll
-  for (int b = 0; b < BI; ++b)
+    for (int j = 0; j < W; ++j) wd[j] = ok ? spec[s * (L / 2) + tl + SC::T * j] : 0u;
+  };
+  fetch(blockIdx.x);
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t s = grp * G + g;
+    const bool live = s < nspec;
+    __syncthreads();  // the previous group's transform is done with the LDS
 #pragma unroll
-    for (int r = 0; r < RI; ++r) {
-      const int c = tl + SC::T * b + r * (L / RI);
-      float2 x = X[c];
-      float2 m = make_float2(0.f, 0.f);
-      if (c == 0)
-        x.y = 0.f;
-      else
-        m = X[L - c];
-      const float2 e = make_float2(x.x + m.x, x.y - m.y);                    // 2 E_c
-      const float2 o = cmul(make_float2(x.x - m.x, x.y + m.y), pre[c]);      // 2 O_c
-      v[b * RI + r] = make_float2(sc * (e.x - o.y), sc * (e.y + o.x));
+    for (int j = 0; j < W; ++j) {
+      const uint32_t w = wd[j];
+      X4[tl + SC::T * j] = make_float4((float)(int8_t)(w & 0xffu),
+                                       (float)(int8_t)((w >> 8) & 0xffu),
+                                       (float)(int8_t)((w >> 16) & 0xffu),
+                                       (float)(int8_t)(w >> 24));
     }
-  fft_inverse<SC>(v, my, tw, tl);  // its first exchange waits for the reads above
-  if (live) {
+    fetch(grp + gridDim.x);  // in flight during this group's transform
+    __syncthreads();
+    const float2* X = (const float2*)my;
+    float2 v[SC::E];
 #pragma unroll
-    for (int b = 0; b < B0; ++b)
+    for (int b = 0; b < BI; ++b)
 #pragma unroll
-      for (int r = 0; r < R0; ++r) out[s * L + tl + SC::T * b + r * (L / R0)] = v[b * R0 + r];
+      for (int r = 0; r < RI; ++r) {
+        const int c = tl + SC::T * b + r * (L / RI);
+        float2 x = X[c];
+        float2 m = make_float2(0.f, 0.f);
+        if (c == 0)
+          x.y = 0.f;
+        else
+          m = X[L - c];
+        const float2 e = make_float2(x.x + m.x, x.y - m.y);                    // 2 E_c
+        const float2 o = cmul(make_float2(x.x - m.x, x.y + m.y), pre[c]);      // 2 O_c
+        v[b * RI + r] = make_float2(sc * (e.x - o.y), sc * (e.y + o.x));
+      }
+    fft_inverse<SC>(v, my, tw, tl);  // its first exchange waits for the reads above
+    if (live) {
+#pragma unroll
+      for (int b = 0; b < B0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) out[s * L + tl + SC::T * b + r * (L / R0)] = v[b * R0 + r];
+    }
   }
 }
 
@@ -872,8 +894,20 @@ static int launch_gsb_t(const void* spec, int64_t nspec, float* series, void* st
   if (!e) e = cached_table((std::string("gsbpre") + std::to_string(LG)).c_str(),
                            &make_gsb_pre<LG>, &pre);
   if (e) return e;
-  const int64_t nb = (nspec + G - 1) / G;
-  if (nb < 1 || nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+  const int64_t ngroups = (nspec + G - 1) / G;
+  if (ngroups < 1) return (int)hipErrorInvalidValue;
+  // as many workgroups as are resident at once (each loops over groups of
+  // records): 0.0265 -> 0.0217 ms for the 16,384 records of 512 bins of the
+  // 16 MHz full-band workload, against one workgroup per group
+  int dev = 0, ncu = 0, per_cu = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he == hipSuccess) he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (he == hipSuccess)
+    he = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&gsb_inverse_kernel<SC, G>), SC::T * G, 0);
+  if (he != hipSuccess) return (int)he;
+  const int64_t nb =
+      std::min<int64_t>(ngroups, (int64_t)std::max(ncu, 1) * std::max(per_cu, 1));
   hipLaunchKernelGGL((gsb_inverse_kernel<SC, G>), dim3((unsigned)nb), dim3(SC::T * G), 0,
                      (hipStream_t)stream, (const uint32_t*)spec, (float2*)series, pre, tw, nspec);
   return (int)hipGetLastError();
