@@ -73,10 +73,16 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
       xt = voltages;
     }
   }
-  float* P = chan_P ? chan_P : (float*)(ws + lay.p_off);
+  // One channel is its own delay reference (Eq. 2 relative to the top
+  // channel for DM >= 0, the bottom one otherwise), so its delay is 0 and the
+  // aligned sum is the identity: the transform kernels write the intensities
+  // straight into the output (the same [trial][t_int] layout) and every
+  // output sample has coverage 1.
+  const bool direct = p.nchan == 1 && !chan_P && out_stride == p.t_int;
+  float* P = direct ? intensity : chan_P ? chan_P : (float*)(ws + lay.p_off);
   if (!table_built) {
     if ((e = begin(kStageDelays))) return device_fail("event record", e);
-    if ((e = launch_delays(p, tile, d, stream))) return device_fail("delay launch", e);
+    if (!direct && (e = launch_delays(p, tile, d, stream))) return device_fail("delay launch", e);
     if (table && (e = launch_chirp_table(p, tile.dm[0], H, stream)))
       return device_fail("chirp table launch", e);
     if ((e = end(kStageDelays))) return device_fail("event record", e);
@@ -96,8 +102,12 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
   }
   if ((e = end(kStageBlock))) return device_fail("event record", e);
   if ((e = begin(kStageDsum))) return device_fail("event record", e);
-  if ((e = launch_dsum(p, tile.ndm, P, d, intensity, coverage, out_stride, stream)))
+  if (direct) {
+    if (coverage && (e = launch_fill_i32(coverage, (int64_t)tile.ndm * p.t_int, 1, stream)))
+      return device_fail("coverage launch", e);
+  } else if ((e = launch_dsum(p, tile.ndm, P, d, intensity, coverage, out_stride, stream))) {
     return device_fail("delay-sum launch", e);
+  }
   if ((e = end(kStageDsum))) return device_fail("event record", e);
   return CDD_OK;
 }

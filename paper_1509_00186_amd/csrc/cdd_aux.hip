@@ -212,6 +212,24 @@ int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream
   return (int)hipGetLastError();
 }
 
+// v[i] = x for i < n (four per thread).
+__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* __restrict__ v, int64_t n,
+                                                       int32_t x) {
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (i + j < n) v[i + j] = x;
+}
+
+int launch_fill_i32(int32_t* v, int64_t n, int32_t x, void* stream) {
+  if (n <= 0) return 0;
+  const int64_t nb = (n + 1023) / 1024;
+  if (nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)nb), dim3(256), 0, (hipStream_t)stream, v,
+                     n, x);
+  return (int)hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Detection and integration without the coherent step (incoherent
 // dedispersion): P[c][u] = sum over r < n_int of |x_c[u n_int + r]|^2, in

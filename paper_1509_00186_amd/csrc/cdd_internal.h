@@ -172,6 +172,8 @@ int enqueue_launch(const LaunchDesc& d, const void* host_tab, void* dev_tab,
 int launch_batch(const BatchBeam* beams, int nbeams, void* host_tab, void* dev_tab,
                  unsigned int* counter, void* stream);
 int launch_delays(const BeamPlan& p, const DmTile& dms, int32_t* d, void* stream);
+// v[i] = x for i < n (a kernel, not a memset, so the launch is capture-safe).
+int launch_fill_i32(int32_t* v, int64_t n, int32_t x, void* stream);
 // The whole path for one beam and one tile of DM trials, every launch on the
 // one stream (workspace regions per ws_layout; xt_ready = an existing
 // channel-major copy or NULL).  timed: record stage events when profiling.
