@@ -96,14 +96,17 @@ cdd_status run_tile(const BeamPlan& p, const void* voltages, const DmTile& tile,
     for (int i = 0; i < tile.ndm; ++i) {
       if ((e = launch_large(p, xt, tile.dm[i], ws + lay.s_off, (float*)(ws + lay.pb_off),
                             P + (int64_t)i * p.nchan * p.t_int, tile.ndm == 1 ? volt_out : nullptr,
-                            stream)))
+                            stream, direct && i == 0 ? coverage : nullptr,
+                            (int64_t)tile.ndm * p.t_int)))
         return device_fail("long-transform launch", e);
     }
   }
   if ((e = end(kStageBlock))) return device_fail("event record", e);
   if ((e = begin(kStageDsum))) return device_fail("event record", e);
   if (direct) {
-    if (coverage && (e = launch_fill_i32(coverage, (int64_t)tile.ndm * p.t_int, 1, stream)))
+    // (the long transforms' chirp-table kernel has set the coverage)
+    if (coverage && block_supported(p.N) &&
+        (e = launch_fill_i32(coverage, (int64_t)tile.ndm * p.t_int, 1, stream)))
       return device_fail("coverage launch", e);
   } else if ((e = launch_dsum(p, tile.ndm, P, d, intensity, coverage, out_stride, stream))) {
     return device_fail("delay-sum launch", e);

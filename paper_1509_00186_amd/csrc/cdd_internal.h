@@ -202,7 +202,8 @@ int64_t large_chunk_items(const BeamPlan& p);  // (channel, block) items per chu
 // |y|^2 buffer holds them when integration is fused; it must be this large)
 size_t large_partial_bytes(int64_t N, int64_t items);
 int launch_large(const BeamPlan& p, const void* xt, double dm, void* S, float* pbuf,
-                 float* P, void* vout, void* stream);
+                 float* P, void* vout, void* stream, int32_t* cov_fill = nullptr,
+                 int64_t cov_n = 0);  // cov_fill: cov_n entries set to 1 as well
 int block_variants(int N);  // number of schedules compiled for N
 
 // Stage timing (cdd_profile.hip): no-ops unless profiling is enabled.

@@ -72,6 +72,9 @@ struct LargeArgs {
   // twiddles of the length-A sub-transform, and log2 of N2 and B
   int32_t A, lg2, lgB;
   const float2* twm;
+  // one-channel calls: coverage set to 1 by the chirp-table kernel (or null)
+  int32_t* cov_fill;
+  int64_t cov_n;
 };
 
 // Row of the intermediate array that holds spectrum bin k2 (< N2): k2 itself
@@ -242,9 +245,11 @@ __device__ __forceinline__ float2 chan_chirp(const LargeArgs& a, double fc, int6
 
 // The chirp functions of one call, per channel in the order the row pass
 // reads them: entry c N + k2 N1 + k1 holds bin i = k2 + N2 k1 of channel c.
+// With a.cov_fill the same launch also sets a.cov_n coverage entries to 1.
 __global__ __launch_bounds__(256) void chan_chirp_table_kernel(LargeArgs a, int64_t N,
                                                                float2* __restrict__ hb) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx < a.cov_n) a.cov_fill[idx] = 1;
   if (idx >= N * a.nchan) return;
   const int c = (int)(idx / N);
   const int64_t e = idx - (int64_t)c * N;
@@ -823,7 +828,8 @@ static int run_passes(const LargeArgs& a, int64_t q, hipStream_t st) {
 
 template <int LGN>
 static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* S, float* pbuf,
-                          float* P, void* vout, int exact_div, void* stream) {
+                          float* P, void* vout, int exact_div, int32_t* cov_fill, int64_t cov_n,
+                          void* stream) {
   using SP = Split<LGN>;
   using SR = typename SP::SR;
   constexpr int GR = rows_per_group(SR::T);
@@ -850,13 +856,15 @@ static int launch_large_t(const BeamPlan& p, const void* xt, double dm, float2* 
   a.t_int = p.t_int;
   a.n_int = p.n_int;
   a.fuse = SP::GC % p.n_int == 0 ? 1 : 0;
+  a.cov_fill = cov_fill;
+  a.cov_n = cov_fill ? cov_n : 0;
   hipStream_t st = (hipStream_t)stream;
   const int64_t items = (int64_t)p.nchan * p.nblocks;
   const int64_t chunk = large_chunk_items(p);
   // the call's chirp table follows the chunk of spectra in the workspace
   constexpr int64_t NP = (int64_t)1 << LGN;
   a.hb = S + chunk * NP;
-  const int64_t nt = (NP * p.nchan + 255) / 256;
+  const int64_t nt = (std::max<int64_t>(NP * p.nchan, a.cov_n) + 255) / 256;
   if (nt > 0x7fffffffLL) return (int)hipErrorInvalidValue;
   hipLaunchKernelGGL(chan_chirp_table_kernel, dim3((unsigned)nt), dim3(256), 0, st, a, NP,
                      (float2*)a.hb);
@@ -998,22 +1006,22 @@ int launch_fullband(const FullbandPlan& f, const float* series, void* Sv, float*
 int exact_division_needed(const BeamPlan& p, double dm_abs_max);
 
 int launch_large(const BeamPlan& p, const void* xt, double dm, void* Sv, float* pbuf, float* P,
-                 void* vout, void* stream) {
+                 void* vout, void* stream, int32_t* cov_fill, int64_t cov_n) {
   float2* S = (float2*)Sv;
   const int ex = exact_division_needed(p, std::fabs(dm));
   switch (p.N) {
-    case 1 << 15: return launch_large_t<15>(p, xt, dm, S, pbuf, P, vout, ex, stream);
-    case 1 << 16: return launch_large_t<16>(p, xt, dm, S, pbuf, P, vout, ex, stream);
-    case 1 << 17: return launch_large_t<17>(p, xt, dm, S, pbuf, P, vout, ex, stream);
-    case 1 << 18: return launch_large_t<18>(p, xt, dm, S, pbuf, P, vout, ex, stream);
-    case 1 << 19: return launch_large_t<19>(p, xt, dm, S, pbuf, P, vout, ex, stream);
-    case 1 << 20: return launch_large_t<20>(p, xt, dm, S, pbuf, P, vout, ex, stream);
-    case 1 << 21: return launch_large_t<21>(p, xt, dm, S, pbuf, P, vout, ex, stream);
-    case 1 << 22: return launch_large_t<22>(p, xt, dm, S, pbuf, P, vout, ex, stream);
-    case 1 << 23: return launch_large_t<23>(p, xt, dm, S, pbuf, P, vout, ex, stream);
-    case 1 << 24: return launch_large_t<24>(p, xt, dm, S, pbuf, P, vout, ex, stream);
-    case 1 << 25: return launch_large_t<25>(p, xt, dm, S, pbuf, P, vout, ex, stream);
-    case 1 << 26: return launch_large_t<26>(p, xt, dm, S, pbuf, P, vout, ex, stream);
+    case 1 << 15: return launch_large_t<15>(p, xt, dm, S, pbuf, P, vout, ex, cov_fill, cov_n, stream);
+    case 1 << 16: return launch_large_t<16>(p, xt, dm, S, pbuf, P, vout, ex, cov_fill, cov_n, stream);
+    case 1 << 17: return launch_large_t<17>(p, xt, dm, S, pbuf, P, vout, ex, cov_fill, cov_n, stream);
+    case 1 << 18: return launch_large_t<18>(p, xt, dm, S, pbuf, P, vout, ex, cov_fill, cov_n, stream);
+    case 1 << 19: return launch_large_t<19>(p, xt, dm, S, pbuf, P, vout, ex, cov_fill, cov_n, stream);
+    case 1 << 20: return launch_large_t<20>(p, xt, dm, S, pbuf, P, vout, ex, cov_fill, cov_n, stream);
+    case 1 << 21: return launch_large_t<21>(p, xt, dm, S, pbuf, P, vout, ex, cov_fill, cov_n, stream);
+    case 1 << 22: return launch_large_t<22>(p, xt, dm, S, pbuf, P, vout, ex, cov_fill, cov_n, stream);
+    case 1 << 23: return launch_large_t<23>(p, xt, dm, S, pbuf, P, vout, ex, cov_fill, cov_n, stream);
+    case 1 << 24: return launch_large_t<24>(p, xt, dm, S, pbuf, P, vout, ex, cov_fill, cov_n, stream);
+    case 1 << 25: return launch_large_t<25>(p, xt, dm, S, pbuf, P, vout, ex, cov_fill, cov_n, stream);
+    case 1 << 26: return launch_large_t<26>(p, xt, dm, S, pbuf, P, vout, ex, cov_fill, cov_n, stream);
   }
   return (int)hipErrorInvalidValue;
 }
